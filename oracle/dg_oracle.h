@@ -1,0 +1,87 @@
+/*
+ * Plain FP64 CPU oracle for the 2D modal discontinuous Galerkin scheme of
+ * Velasco Romero, Han Veiga, Teyssier & Masset (2018), "Planet-disc
+ * interactions with Discontinuous Galerkin Methods using GPUs".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link or call
+ * this library; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or helper with the HIP
+ * library: quadrature, basis, fluxes, time stepping and reductions are all
+ * written out again here, as plainly as possible, for checking by eye against
+ * the paper.
+ *
+ * Conventions (own to the oracle, mirrored by its Python wrapper):
+ *   n        points per direction = polynomial degree N_p + 1
+ *   mode     (a, b), a = degree in x, b = degree in y, flat index a*n + b
+ *   node     (q, r), Gauss-Legendre point q in x, r in y, flat index q*n + r
+ *   element  e = j*nx + i
+ *   state    u[(v*n*n + mode)*E + e]         (one nx*ny plane per mode)
+ *   nodes    x[e*n*n + node], y[e*n*n + node]
+ *   prim     prim[(v*E + e)*n*n + node]       (rho, vx, vy[, p])
+ */
+#ifndef DG_ORACLE_H
+#define DG_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int n;            /* points per direction (order m of the scheme) */
+    int nvar;         /* 3 (isothermal closures) or 4 (adiabatic) */
+    int nx, ny;       /* elements per direction */
+    double x0, x1, y0, y1;
+    int closure;      /* 0 isothermal c_s, 1 locally isothermal, 2 adiabatic */
+    double cs;        /* isothermal sound speed */
+    double h;         /* aspect ratio: c_s^2 = h^2 GM / max(r, r_core) */
+    double gamma;     /* adiabatic index */
+    int bc;           /* 0 periodic, 1 exterior trace = initial trace */
+    int star;         /* 1: stellar potential (harmonic core inside r_core) */
+    double gm, r_core;
+    double q, eps;    /* planet mass ratio (0: no planet) and softening */
+    double rp, phi0;  /* planet orbit radius and phase at t = 0 */
+    int damping;      /* 1: wave-killing zones */
+    double rd_in, rd_out;
+    double cfl;
+} or_cfg;
+
+/* Sec. 2.2, eq. (3): Gauss-Legendre nodes (ascending) and weights on [-1,1]. */
+int or_gauss_legendre(int n, double *x, double *w);
+/* Sec. 2.2: orthonormal Legendre basis phi_a = sqrt(2a+1) P_a and derivative. */
+double or_phi(int a, double x);
+double or_dphi(int a, double x);
+
+/* volume node coordinates of every element */
+void or_nodes(const or_cfg *c, double *x, double *y);
+/* Sec. 3.1 steps (i)(a)-(c): primitive nodes -> conservative nodes -> modes */
+void or_project(const or_cfg *c, const double *prim, double *u);
+/* evaluate the modal state at the volume nodes, out[(v*E+e)*n*n + node] */
+void or_eval_nodes(const or_cfg *c, const double *u, double *out);
+/* eq. (3): du/dt = L(u) at time t.  u0 (initial modes) supplies the exterior
+ * traces when bc == 1 and may be NULL for periodic boxes. */
+void or_rhs(const or_cfg *c, double t, const double *u, const double *u0, double *rhs);
+/* Sec. 2.3: global CFL time step from the element means */
+double or_dt(const or_cfg *c, const double *u);
+
+/* Algorithm 1 / Appendix A in Butcher form for a generic right-hand side */
+typedef void (*or_rhs_fn)(void *ctx, double t, const double *u, double *k);
+void or_rk_butcher(int s, const double *A, const double *b, const double *cc,
+                   or_rhs_fn f, void *ctx, long N, double *u, double t, double dt);
+/* SSP(3,3) tableau with c = (0, 1, 1/2) */
+void or_ssprk3_tableau(double *A9, double *b3, double *c3);
+/* one DG step: dt (CFL if dt_fixed <= 0), SSP-RK3 stages, damping; returns dt */
+double or_step(const or_cfg *c, double *u, double t, double dt_fixed, const double *u0);
+
+/* Sec. 5.1: wave-killing damping of rho, v (and T) towards the initial state */
+void or_damp(const or_cfg *c, double *u, const double *u0, double dt);
+/* Sec. 5.2 eq. (5): z-torque of the disc on the planet (G = 1, per unit planet
+ * mass); *sum_abs receives the sum of |terms| */
+double or_torque(const or_cfg *c, double t, const double *u, double *sum_abs);
+
+/* planet position at time t */
+void or_planet_pos(const or_cfg *c, double t, double *xp, double *yp);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

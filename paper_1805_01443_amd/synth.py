@@ -1,0 +1,126 @@
+"""Seeded synthetic initial conditions.
+
+This module only evaluates the problem set-ups (initial primitive fields at
+caller-supplied coordinates) and draws seeded random numbers.  It holds none of
+the discontinuous Galerkin arithmetic: no quadrature, no basis, no fluxes.  Both
+the HIP path (through ``dg_init``) and the CPU oracle receive the arrays it
+returns, so the two sides see identical input bits.
+
+Set-ups:
+
+* ``periodic_wave``   density wave rho = 1 + 0.2 sin(2 pi (x + y)) carried by a
+  uniform velocity (1, 1) on the periodic unit square (isothermal, c_s = 1).
+* ``entropy_wave``    the same wave for the adiabatic equations with p = 1; it is
+  an exact solution, translated with velocity (1, 1).
+* ``disc``            the planet-disc set-up: surface density
+  Sigma0 * max(r, r_c)^(-1/2), locally isothermal sound speed
+  c_s^2 = h^2 GM / max(r, r_c) and the azimuthal velocity of rotational
+  equilibrium v_phi^2 = r dPhi*/dr + (r / Sigma) d(c_s^2 Sigma)/dr (Sec. 5.1 of
+  the paper, with the stellar potential read as a harmonic core inside r_c and
+  Keplerian outside, the reading of its Omega^2(r) definition).
+* ``disc_ring``       the adiabatic disc (gamma = 1.4, p = c_s^2 Sigma) with an
+  axisymmetric Gaussian over-pressure ring p *= 1 + 4 exp(-(r-r_ring)^2/(2 s^2)).
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood 2014): the 64-bit
+state is ``seed * 0x9E3779B97F4A7C15 + (index + 1) * 0x9E3779B97F4A7C15`` and one
+output is the standard mix of that state; the top 53 bits give a double in
+[0, 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, index) -> np.ndarray:
+    """One SplitMix64 output per (seed, index) pair, as uint64."""
+    idx = np.asarray(index, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) * _GOLDEN + (idx + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform01(seed: int, index) -> np.ndarray:
+    """Doubles in [0, 1) from the top 53 bits of SplitMix64."""
+    z = splitmix64(seed, index)
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+# ---------------------------------------------------------------------------
+# set-ups; every function takes coordinate arrays of any (equal) shape and
+# returns a tuple of primitive arrays of that shape.
+# ---------------------------------------------------------------------------
+
+def periodic_wave(x, y):
+    """(rho, vx, vy): rho = 1 + 0.2 sin(2 pi (x + y)), v = (1, 1)."""
+    rho = 1.0 + 0.2 * np.sin(2.0 * np.pi * (x + y))
+    return rho, np.ones_like(rho), np.ones_like(rho)
+
+
+def entropy_wave(x, y, t=0.0):
+    """(rho, vx, vy, p) of the adiabatic entropy wave at time t."""
+    rho = 1.0 + 0.2 * np.sin(2.0 * np.pi * (x + y - 2.0 * t))
+    one = np.ones_like(rho)
+    return rho, one, one.copy(), one.copy()
+
+
+def _disc_fields(x, y, gm, h, r_core, sigma0):
+    r = np.sqrt(x * x + y * y)
+    rr = np.maximum(r, r_core)
+    sigma = sigma0 / np.sqrt(rr)
+    cs2 = h * h * gm / rr
+    # angular velocity of rotational equilibrium
+    inner = r < r_core
+    om2 = np.where(inner, gm / r_core ** 3, gm * (1.0 - 1.5 * h * h) / np.maximum(r, 1e-300) ** 3)
+    om = np.sqrt(om2)
+    vx = -om * y
+    vy = om * x
+    return sigma, vx, vy, cs2, r
+
+
+def disc_sigma0(seed):
+    """Sigma0 ~ U[0.5, 2] drawn from the seed (index 2**62 is reserved for it)."""
+    return 0.5 + 1.5 * float(uniform01(seed, np.uint64(1) << np.uint64(62)))
+
+
+def disc(x, y, gm=1.0, h=0.05, r_core=0.4, sigma0=1.0, noise_seed=None,
+         noise_amp=1e-4, node_ids=None):
+    """(rho, vx, vy) of the locally isothermal disc in rotational equilibrium.
+
+    With ``noise_seed`` the density gets rho *= 1 + amp * xi, xi ~ U[-1, 1)
+    drawn per node from SplitMix64(noise_seed, node id); ``node_ids`` are the
+    global node indices (defaults to the flat index of ``x``).
+    """
+    sigma, vx, vy, _, _ = _disc_fields(x, y, gm, h, r_core, sigma0)
+    if noise_seed is not None:
+        ids = np.arange(np.size(x), dtype=np.uint64).reshape(np.shape(x)) if node_ids is None else node_ids
+        xi = 2.0 * uniform01(noise_seed, ids) - 1.0
+        sigma = sigma * (1.0 + noise_amp * xi)
+    return sigma, vx, vy
+
+
+def disc_ring(x, y, gm=1.0, h=0.05, r_core=0.4, sigma0=1.0, r_ring=1.6,
+              width=0.05, peak=5.0):
+    """(rho, vx, vy, p) of the adiabatic disc plus an over-pressure ring."""
+    sigma, vx, vy, cs2, r = _disc_fields(x, y, gm, h, r_core, sigma0)
+    p = cs2 * sigma * (1.0 + (peak - 1.0) * np.exp(-((r - r_ring) ** 2) / (2.0 * width * width)))
+    return sigma, vx, vy, p
+
+
+def ring_radius(seed):
+    """r_ring ~ U[1.4, 1.9] from the seed (index 2**62 + 1 is reserved for it)."""
+    return 1.4 + 0.5 * float(uniform01(seed, (np.uint64(1) << np.uint64(62)) + np.uint64(1)))
+
+
+def pack_prim(fields, n_elem, n_nodes):
+    """Stack primitive fields given per node as [E, n^2] into [var][E][n^2]."""
+    out = np.empty((len(fields), n_elem, n_nodes), dtype=np.float64)
+    for k, f in enumerate(fields):
+        out[k] = np.asarray(f, dtype=np.float64).reshape(n_elem, n_nodes)
+    return out
