@@ -1,0 +1,132 @@
+/*
+ * dg.h -- C ABI of the MI355X (gfx950) modal discontinuous Galerkin library.
+ *
+ * The library advances the 2D compressible Euler equations with stellar and
+ * planetary gravity (Velasco Romero et al. 2018, Sec. 2.1 eq. (1)) by the
+ * modal DG semi-discretisation of Sec. 2.2 eq. (3) and the SSP Runge-Kutta
+ * march of Algorithm 1 (Appendix A, SSP(3,3)).  All compute runs in HIP
+ * kernels on the caller's stream; nothing here takes or returns framework
+ * (PyTorch) types.
+ *
+ * Data layout (caller-owned device arrays, FP64):
+ *   state  u[(v*n*n + a*n + b)*E + e]   v: variable (rho, rho vx, rho vy[, E]),
+ *          (a, b): Legendre degrees in x and y, e = j*nx + i the element.
+ *          One nx*ny plane per (variable, mode), i fastest: the paper's
+ *          "one matrix per mode" layout (Sec. 3.1), coalesced by element.
+ *   basis  phi_ab(xi, eta) = sqrt((2a+1)(2b+1)) P_a(xi) P_b(eta), orthonormal
+ *          under (1/|K|) int_K, so mode 00 is the element mean (Sec. 2.2 and
+ *          the zeroth-mode statement of Sec. 3.1).
+ *   nodes  Gauss-Legendre points, n per direction: node (q, r), flat q*n + r.
+ *
+ * Errors: every call returns 0 or a negative DG_E* code and never aborts or
+ * throws; dg_last_error() gives the message of the last failure of a handle
+ * (or of dg_init / dg_get_nodes when the handle is NULL).  Device-side
+ * problems (non-finite or non-positive density means) raise a flag that the
+ * next dg_sync() reports as DG_ENONFINITE.  A handle belongs to one stream and
+ * is not thread-safe; the library keeps no global mutable state apart from
+ * per-device scratch set up explicitly by the calls that use it.
+ */
+#ifndef DG_MI355X_H
+#define DG_MI355X_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DG_OK 0
+#define DG_EINVAL -1        /* bad argument or configuration */
+#define DG_ENOMEM -2        /* device allocation failed */
+#define DG_EHIP -3          /* a HIP runtime call failed */
+#define DG_EUNSUPPORTED -4  /* valid but not built (e.g. order outside 2..5) */
+#define DG_ENONFINITE -5    /* device flagged a non-finite / non-positive mean */
+
+enum { DG_CLOSURE_ISOTHERMAL = 0, DG_CLOSURE_LOCALLY_ISOTHERMAL = 1, DG_CLOSURE_ADIABATIC = 2 };
+enum { DG_BC_PERIODIC = 0, DG_BC_FIXED_INITIAL = 1 };
+enum { DG_PRECISION_FP64 = 0, DG_PRECISION_MIXED = 1 };
+enum { DG_LIMITER_NONE = 0, DG_LIMITER_MODAL_DECAY = 1, DG_LIMITER_LEARNED = 2 };
+
+/* Problem statement.  Units: G = M_* = r_p = 1 as in Sec. 5.1. */
+typedef struct dg_config {
+    int order;            /* n = N_p + 1 points/modes per direction, 2..5 */
+    int nvar;             /* 3 (isothermal closures) or 4 (adiabatic) */
+    int nx, ny;           /* elements per direction */
+    double x0, x1, y0, y1;/* box */
+    int closure;          /* DG_CLOSURE_* */
+    double cs;            /* isothermal sound speed */
+    double h;             /* aspect ratio: c_s^2 = h^2 GM / max(r, r_core) */
+    double gamma;         /* adiabatic index */
+    int bc;               /* DG_BC_*: periodic, or exterior trace = initial trace */
+    int star;             /* 1: stellar potential, harmonic core inside r_core */
+    double gm, r_core;
+    double q, eps;        /* planet mass ratio (0: no planet) and softening */
+    double rp, phi0;      /* planet orbit radius, phase at t = 0 */
+    int damping;          /* 1: wave-killing zones r < rd_in and r > rd_out */
+    double rd_in, rd_out;
+    double cfl;           /* C of the CFL condition (Sec. 2.3) */
+    int precision;        /* DG_PRECISION_* */
+    int limiter;          /* DG_LIMITER_* */
+    double limiter_s0;    /* modal-decay threshold on log10 of the top-mode energy share */
+    double mlp_theta;     /* learned indicator: flag when sigmoid output > theta */
+} dg_config;
+
+typedef struct dg_handle dg_handle;
+
+/* Volume Gauss node coordinates, host arrays x_host[e*n*n + node] and y_host
+ * likewise (E*n*n doubles each, caller-owned).  Needs no device. */
+int dg_get_nodes(const dg_config *cfg, double *x_host, double *y_host);
+
+/* Initial conditions (Sec. 3.1 steps (i)(a)-(c)).  prim_nodes_host holds the
+ * primitive variables (rho, vx, vy[, p]) at the volume nodes, layout
+ * [var][e][node], host memory read during the call only.  The projected modes
+ * are written to the caller's device array u0_dev (layout above) on
+ * hip_stream (a hipStream_t; NULL = default stream), and the library keeps its
+ * own copy as the fixed exterior state and the damping target.  With
+ * precision DG_PRECISION_MIXED, eq_prim_nodes_host gives the equilibrium
+ * primitive state that the deviation form expands about (NULL: the initial
+ * state); u0_dev then receives the full state u as in FP64 mode.  The handle
+ * owns all workspace it allocates; dg_free releases it. */
+int dg_init(const dg_config *cfg, const double *prim_nodes_host, const double *eq_prim_nodes_host,
+            double *u0_dev, void *hip_stream, dg_handle **out);
+
+/* Right-hand side of eq. (3), rhs = L(u) at time t (planet at its position
+ * at t), without limiter or damping.  u_dev, rhs_dev: device arrays in the
+ * state layout, distinct.  Asynchronous on the handle's stream. */
+int dg_rhs(dg_handle *h, double t, const double *u_dev, double *rhs_dev);
+
+/* One SSP-RK3 step (Algorithm 1 with the SSP(3,3) tableau, c = (0, 1, 1/2))
+ * of the state u_dev, in place.  t_dev is a device double holding t^n; it is
+ * advanced to t^n + dt on the device.  dt = dt_fixed if dt_fixed > 0, else the
+ * CFL step of Sec. 2.3 from the element means of u^n, reduced on the device.
+ * dt_used_dev (device double, may be NULL) receives dt.  After the three
+ * stages the limiter (if configured) has been applied per stage and the
+ * damping once.  No host synchronisation. */
+int dg_rk_step(dg_handle *h, double *u_dev, double *t_dev, double dt_fixed, double *dt_used_dev);
+
+/* z-torque of the disc on the planet, eq. (5) (G = 1, per unit planet mass),
+ * with the cells read as the volume Gauss nodes (mass rho_h w_q w_r |K| / 4).
+ * Time: *t_dev if t_dev is not NULL, else t.  The result is written to the
+ * device double torque_dev; the summation order is fixed, so repeated calls
+ * give identical bits. */
+int dg_torque(dg_handle *h, double t, const double *t_dev, const double *u_dev, double *torque_dev);
+
+/* Wait for the handle's stream; returns DG_ENONFINITE if a kernel flagged a
+ * non-finite or non-positive density mean since the last dg_sync. */
+int dg_sync(dg_handle *h);
+
+/* Kernel timing for measurement: between dg_profile_begin and dg_profile_end
+ * every launch of the fused RK-stage kernel issued by dg_rk_step is bracketed
+ * by HIP events on the handle's stream.  dg_profile_end waits for them and
+ * returns the summed duration (ms) and the number of launches. */
+int dg_profile_begin(dg_handle *h);
+int dg_profile_end(dg_handle *h, double *stage_ms, int *stage_launches);
+
+/* Release the handle and its workspace (NULL is accepted). */
+int dg_free(dg_handle *h);
+
+/* Message of the last error of h (NULL: of the last failed handle-less call). */
+const char *dg_last_error(const dg_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

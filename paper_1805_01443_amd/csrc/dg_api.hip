@@ -1,0 +1,365 @@
+// C ABI of the gfx950 DG library (declarations and contracts in include/dg.h).
+#include "../../include/dg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+
+using dgk::Geo;
+using dgk::StageCoeffs;
+using dgk::StepBlock;
+using dgk::Tables;
+
+struct dg_handle {
+    dg_config cfg{};
+    int n = 0, nvar = 0;
+    long long E = 0;
+    Geo g{};
+    Tables T{};
+    hipStream_t s = nullptr;
+    int device = 0;
+    double* u0 = nullptr;   // initial modes: fixed exterior state and damping target
+    double* ws1 = nullptr;  // SSP stage states u^(1), u^(2)
+    double* ws2 = nullptr;
+    StageCoeffs* sc_rhs = nullptr;
+    StepBlock* sb = nullptr;
+    int* damp_list = nullptr;
+    int ndamp = 0;
+    double* tq_part = nullptr;
+    int tq_blocks = 0;
+    bool prof = false;               // bracket stage launches with events
+    std::vector<hipEvent_t> ev;      // start/stop pairs
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;  // last error of a handle-less call
+
+int fail(dg_handle* h, int code, const std::string& msg) {
+    if (h)
+        h->err = msg;
+    else
+        g_err = msg;
+    return code;
+}
+
+int hip_fail(dg_handle* h, hipError_t e, const char* what) {
+    return fail(h, DG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define DG_HIP(h, call, what)                                  \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail((h), e_, (what)); \
+    } while (0)
+
+int validate(const dg_config* c, std::string* why) {
+    if (!c) return (*why = "cfg is NULL", DG_EINVAL);
+    if (c->order < 2 || c->order > dgk::kMaxN) return (*why = "order must be in 2..5", DG_EUNSUPPORTED);
+    if (c->nx < 1 || c->ny < 1) return (*why = "nx, ny must be >= 1", DG_EINVAL);
+    if ((long long)c->nx * c->ny > (1LL << 31) - 1) return (*why = "too many elements", DG_EINVAL);
+    if (!(c->x1 > c->x0) || !(c->y1 > c->y0)) return (*why = "empty box", DG_EINVAL);
+    if (c->closure < 0 || c->closure > 2) return (*why = "unknown closure", DG_EINVAL);
+    if (c->nvar != (c->closure == DG_CLOSURE_ADIABATIC ? 4 : 3))
+        return (*why = "nvar must be 4 for the adiabatic closure and 3 otherwise", DG_EINVAL);
+    if (c->closure == DG_CLOSURE_ISOTHERMAL && !(c->cs > 0)) return (*why = "cs must be > 0", DG_EINVAL);
+    if (c->closure == DG_CLOSURE_LOCALLY_ISOTHERMAL && !(c->h > 0 && c->gm > 0 && c->r_core > 0))
+        return (*why = "h, gm, r_core must be > 0", DG_EINVAL);
+    if (c->closure == DG_CLOSURE_ADIABATIC && !(c->gamma > 1)) return (*why = "gamma must be > 1", DG_EINVAL);
+    if (c->bc != DG_BC_PERIODIC && c->bc != DG_BC_FIXED_INITIAL) return (*why = "unknown bc", DG_EINVAL);
+    if (c->star && !(c->gm > 0 && c->r_core > 0)) return (*why = "star needs gm, r_core > 0", DG_EINVAL);
+    if (c->q < 0 || (c->q > 0 && !(c->eps > 0 && c->rp > 0 && c->gm > 0)))
+        return (*why = "planet needs q >= 0, eps, rp, gm > 0", DG_EINVAL);
+    if (c->damping && !(c->rd_in >= 0 && c->rd_out > c->rd_in && c->gm > 0))
+        return (*why = "damping needs 0 <= rd_in < rd_out and gm > 0", DG_EINVAL);
+    if (!(c->cfl > 0)) return (*why = "cfl must be > 0", DG_EINVAL);
+    if (c->precision != DG_PRECISION_FP64) return (*why = "only FP64 precision is built", DG_EUNSUPPORTED);
+    if (c->limiter != DG_LIMITER_NONE) return (*why = "limiters are not built", DG_EUNSUPPORTED);
+    return DG_OK;
+}
+
+void make_geo(const dg_config* c, Geo* g) {
+    *g = Geo{};
+    g->nx = c->nx;
+    g->ny = c->ny;
+    g->E = (long long)c->nx * c->ny;
+    g->tiles_x = (c->nx + dgk::kWave - 1) / dgk::kWave;
+    g->tiles_total = g->tiles_x * c->ny;
+    g->x0 = c->x0;
+    g->y0 = c->y0;
+    g->dx = (c->x1 - c->x0) / c->nx;
+    g->dy = (c->y1 - c->y0) / c->ny;
+    g->rdx2 = 2.0 / g->dx;
+    g->rdy2 = 2.0 / g->dy;
+    g->idx = 1.0 / g->dx;
+    g->idy = 1.0 / g->dy;
+    g->closure = c->closure;
+    g->bc = c->bc;
+    g->star = c->star;
+    g->cs2 = c->cs * c->cs;
+    g->h2gm = c->h * c->h * c->gm;
+    g->gamma = c->gamma;
+    g->gm = c->gm;
+    g->r_core = c->r_core;
+    g->rc3inv = c->r_core > 0 ? c->gm / (c->r_core * c->r_core * c->r_core) : 0.0;
+    g->q = c->q;
+    g->eps2 = c->eps * c->eps;
+    g->rp = c->rp;
+    g->phi0 = c->phi0;
+    g->omp = c->rp > 0 ? std::sqrt(c->gm / (c->rp * c->rp * c->rp)) : 0.0;
+    g->damping = c->damping;
+    const double f = std::pow(1.15, 1.5);
+    const double pi = 3.141592653589793238462643;
+    g->rd_in = c->rd_in;
+    g->rd_out = c->rd_out;
+    g->rb_in = c->rd_in / f;
+    g->rb_out = c->rd_out * f;
+    g->td_in = c->gm > 0 ? 2.0 * pi * std::sqrt(c->rd_in * c->rd_in * c->rd_in / c->gm) : 0.0;
+    g->td_out = c->gm > 0 ? 2.0 * pi * std::sqrt(c->rd_out * c->rd_out * c->rd_out / c->gm) : 0.0;
+    g->cfl_fac = c->cfl / (2.0 * (c->order - 1) + 1.0);
+}
+
+void host_nodes(const dg_config* c, const Tables& T, std::vector<double>* x, std::vector<double>* y) {
+    const int n = c->order;
+    const double dx = (c->x1 - c->x0) / c->nx, dy = (c->y1 - c->y0) / c->ny;
+    const long long E = (long long)c->nx * c->ny;
+    x->resize((size_t)E * n * n);
+    y->resize((size_t)E * n * n);
+    for (long long e = 0; e < E; ++e) {
+        const int i = (int)(e % c->nx), j = (int)(e / c->nx);
+        const double xc = c->x0 + (i + 0.5) * dx, yc = c->y0 + (j + 0.5) * dy;
+        for (int q = 0; q < n; ++q)
+            for (int r = 0; r < n; ++r) {
+                (*x)[(size_t)e * n * n + q * n + r] = xc + 0.5 * dx * T.xi[q];
+                (*y)[(size_t)e * n * n + q * n + r] = yc + 0.5 * dy * T.xi[r];
+            }
+    }
+}
+
+void drop_events(dg_handle* h) {
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    h->ev.clear();
+}
+
+// launch one stage kernel, bracketed by events while profiling
+hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, const StageCoeffs* sc) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (h->prof) {
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        h->ev.push_back(a);
+        h->ev.push_back(b);
+        e = hipEventRecord(a, h->s);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = dgk::launch_stage(h->n, h->g, h->T, u, un, h->u0, out, sc, h->s);
+    if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
+    return e;
+}
+
+void release(dg_handle* h) {
+    if (!h) return;
+    drop_events(h);
+    (void)hipFree(h->u0);
+    (void)hipFree(h->ws1);
+    (void)hipFree(h->ws2);
+    (void)hipFree(h->sc_rhs);
+    (void)hipFree(h->sb);
+    (void)hipFree(h->damp_list);
+    (void)hipFree(h->tq_part);
+    h->u0 = h->ws1 = h->ws2 = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_get_nodes(const dg_config* cfg, double* x_host, double* y_host) {
+    std::string why;
+    if (!cfg || !x_host || !y_host) return fail(nullptr, DG_EINVAL, "NULL argument");
+    if (cfg->order < 2 || cfg->order > dgk::kMaxN) return fail(nullptr, DG_EUNSUPPORTED, "order must be in 2..5");
+    if (cfg->nx < 1 || cfg->ny < 1) return fail(nullptr, DG_EINVAL, "nx, ny must be >= 1");
+    Tables T;
+    dgk::make_tables(cfg->order, &T);
+    std::vector<double> x, y;
+    host_nodes(cfg, T, &x, &y);
+    std::memcpy(x_host, x.data(), x.size() * sizeof(double));
+    std::memcpy(y_host, y.data(), y.size() * sizeof(double));
+    return DG_OK;
+}
+
+int dg_init(const dg_config* cfg, const double* prim_nodes_host, const double* eq_prim_nodes_host, double* u0_dev,
+            void* hip_stream, dg_handle** out) {
+    (void)eq_prim_nodes_host;
+    if (!out) return fail(nullptr, DG_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    int rc = validate(cfg, &why);
+    if (rc != DG_OK) return fail(nullptr, rc, why);
+    if (!prim_nodes_host || !u0_dev) return fail(nullptr, DG_EINVAL, "NULL prim_nodes_host or u0_dev");
+
+    dg_handle* h = new (std::nothrow) dg_handle();
+    if (!h) return fail(nullptr, DG_ENOMEM, "host allocation failed");
+    h->cfg = *cfg;
+    h->n = cfg->order;
+    h->nvar = cfg->nvar;
+    h->E = (long long)cfg->nx * cfg->ny;
+    h->s = (hipStream_t)hip_stream;
+    make_geo(cfg, &h->g);
+    dgk::make_tables(h->n, &h->T);
+
+    auto bail = [&](int code) {
+        g_err = h->err;
+        release(h);
+        delete h;
+        return code;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) return bail(hip_fail(h, hipGetLastError(), "hipGetDevice"));
+
+    const size_t state_bytes = sizeof(double) * (size_t)h->nvar * h->n * h->n * (size_t)h->E;
+    double* prim_dev = nullptr;
+    hipError_t e;
+#define DG_ALLOC(ptr, bytes)                                                   \
+    e = hipMalloc((void**)&(ptr), (bytes));                                    \
+    if (e != hipSuccess) {                                                     \
+        (void)hipFree(prim_dev);                                                     \
+        return bail(fail(h, DG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e))); \
+    }
+    DG_ALLOC(h->u0, state_bytes);
+    DG_ALLOC(h->ws1, state_bytes);
+    DG_ALLOC(h->ws2, state_bytes);
+    DG_ALLOC(h->sc_rhs, sizeof(StageCoeffs));
+    DG_ALLOC(h->sb, sizeof(StepBlock));
+    h->tq_blocks = dgk::torque_blocks(h->g);
+    DG_ALLOC(h->tq_part, sizeof(double) * (size_t)h->tq_blocks);
+    DG_ALLOC(prim_dev, state_bytes);
+
+    // damped elements: any volume node with a non-zero ramp
+    if (cfg->damping) {
+        std::vector<double> x, y;
+        host_nodes(cfg, h->T, &x, &y);
+        std::vector<int> list;
+        const int nn = h->n * h->n;
+        for (long long el = 0; el < h->E; ++el) {
+            bool any = false;  // the ramp is positive exactly for r < rd_in or r > rd_out
+            for (int k = 0; k < nn && !any; ++k) {
+                const double r = std::sqrt(x[el * nn + k] * x[el * nn + k] + y[el * nn + k] * y[el * nn + k]);
+                any = r < cfg->rd_in || r > cfg->rd_out;
+            }
+            if (any) list.push_back((int)el);
+        }
+        h->ndamp = (int)list.size();
+        if (h->ndamp) {
+            DG_ALLOC(h->damp_list, sizeof(int) * list.size());
+            e = hipMemcpyAsync(h->damp_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, h->s);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->s);
+            if (e != hipSuccess) {
+                (void)hipFree(prim_dev);
+                return bail(hip_fail(h, e, "damping list upload"));
+            }
+        }
+    }
+#undef DG_ALLOC
+
+    StepBlock sb0{};
+    sb0.dtmin_bits = 0x7FF0000000000000ull;
+    e = hipMemcpyAsync(h->sb, &sb0, sizeof sb0, hipMemcpyHostToDevice, h->s);
+    if (e == hipSuccess) e = hipMemcpyAsync(prim_dev, prim_nodes_host, state_bytes, hipMemcpyHostToDevice, h->s);
+    if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, h->T, prim_dev, u0_dev, h->s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->u0, u0_dev, state_bytes, hipMemcpyDeviceToDevice, h->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->s);
+    (void)hipFree(prim_dev);
+    if (e != hipSuccess) return bail(hip_fail(h, e, "dg_init projection"));
+    *out = h;
+    return DG_OK;
+}
+
+int dg_rhs(dg_handle* h, double t, const double* u_dev, double* rhs_dev) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    if (!u_dev || !rhs_dev || u_dev == rhs_dev) return fail(h, DG_EINVAL, "u_dev and rhs_dev must be distinct device arrays");
+    DG_HIP(h, dgk::launch_set_coeffs(h->sc_rhs, h->g, t, 0.0, 0.0, 1.0, h->s), "dg_rhs coefficients");
+    DG_HIP(h, dgk::launch_stage(h->n, h->g, h->T, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, h->s), "dg_rhs stage");
+    return DG_OK;
+}
+
+int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, double* dt_used_dev) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    if (!u_dev || !t_dev) return fail(h, DG_EINVAL, "u_dev and t_dev are required");
+    if (!(dt_fixed == dt_fixed)) return fail(h, DG_EINVAL, "dt_fixed is NaN");
+    StepBlock* sb = h->sb;
+    DG_HIP(h, dgk::launch_dt(h->n, h->g, u_dev, sb, h->s), "CFL reduction");
+    DG_HIP(h, dgk::launch_step_begin(h->g, sb, t_dev, dt_fixed, dt_used_dev, h->s), "step begin");
+    DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
+    DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1]), "stage 2");
+    DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2]), "stage 3");
+    if (h->cfg.damping)
+        DG_HIP(h, dgk::launch_damp(h->n, h->g, h->T, u_dev, h->u0, h->damp_list, h->ndamp, &sb->st[0], h->s),
+               "damping");
+    return DG_OK;
+}
+
+int dg_torque(dg_handle* h, double t, const double* t_dev, const double* u_dev, double* torque_dev) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    if (!u_dev || !torque_dev) return fail(h, DG_EINVAL, "u_dev and torque_dev are required");
+    DG_HIP(h, dgk::launch_torque(h->n, h->g, h->T, t, t_dev, u_dev, h->tq_part, h->tq_blocks, torque_dev, h->s),
+           "torque");
+    return DG_OK;
+}
+
+int dg_sync(dg_handle* h) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    DG_HIP(h, hipStreamSynchronize(h->s), "hipStreamSynchronize");
+    unsigned int flags = 0;
+    DG_HIP(h, hipMemcpy(&flags, &h->sb->flags, sizeof flags, hipMemcpyDeviceToHost), "flag read");
+    if (flags) {
+        const unsigned int zero = 0;
+        DG_HIP(h, hipMemcpy(&h->sb->flags, &zero, sizeof zero, hipMemcpyHostToDevice), "flag reset");
+        return fail(h, DG_ENONFINITE, "non-finite or non-positive density mean detected");
+    }
+    return DG_OK;
+}
+
+int dg_profile_begin(dg_handle* h) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    DG_HIP(h, hipStreamSynchronize(h->s), "hipStreamSynchronize");
+    drop_events(h);
+    h->prof = true;
+    return DG_OK;
+}
+
+int dg_profile_end(dg_handle* h, double* stage_ms, int* stage_launches) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    h->prof = false;
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < h->ev.size(); k += 2) {
+        DG_HIP(h, hipEventSynchronize(h->ev[k + 1]), "hipEventSynchronize");
+        float ms = 0.0f;
+        DG_HIP(h, hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]), "hipEventElapsedTime");
+        tot += ms;
+    }
+    if (stage_ms) *stage_ms = tot;
+    if (stage_launches) *stage_launches = (int)(h->ev.size() / 2);
+    drop_events(h);
+    return DG_OK;
+}
+
+int dg_free(dg_handle* h) {
+    if (!h) return DG_OK;
+    (void)hipStreamSynchronize(h->s);
+    release(h);
+    delete h;
+    return DG_OK;
+}
+
+const char* dg_last_error(const dg_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal structures shared by the C-ABI layer and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgk {
+
+constexpr int kMaxN = 5;  // orders 2..5 (P1..P4)
+constexpr int kWave = 64;
+
+// Gauss-Legendre / Legendre tables, passed by value in the kernel argument
+// segment so every lookup is a uniform scalar load.
+struct Tables {
+    double phi[kMaxN][kMaxN];   // phi[a][q] = phi_a(xi_q)
+    double dphi[kMaxN][kMaxN];  // dphi[a][q] = phi_a'(xi_q)
+    double wh[kMaxN];           // Gauss weights / 2 (sum 1)
+    double xi[kMaxN];           // Gauss nodes on [-1, 1]
+    double pm[kMaxN];           // phi_a(-1)
+    double pp[kMaxN];           // phi_a(+1)
+};
+
+// Mesh, closure and gravity parameters.
+struct Geo {
+    int nx, ny;
+    long long E;
+    int tiles_x;       // 64-element row tiles per row
+    int tiles_total;   // tiles_x * ny
+    double x0, y0, dx, dy;
+    double rdx2, rdy2; // 2/dx, 2/dy
+    double idx, idy;   // 1/dx, 1/dy
+    int closure, bc, star;
+    double cs2;        // isothermal c_s^2
+    double h2gm;       // h^2 GM (locally isothermal)
+    double gamma;
+    double gm, r_core, rc3inv;  // GM / r_core^3
+    double q, eps2;
+    double rp, phi0, omp;       // planet orbit, Omega_p
+    // damping
+    int damping;
+    double rd_in, rd_out, rb_in, rb_out, td_in, td_out;
+    double cfl_fac;             // C / (2 N_p + 1)
+};
+
+// Per-stage coefficients: out = a0 * u^n + a1 * u + a2 * L(u, t)
+struct StageCoeffs {
+    double t;       // stage time
+    double xp, yp;  // planet position at t
+    double a0, a1, a2;
+    double dt;      // step size (damping)
+    double pad;
+};
+
+// Device-resident per-step block written by the step-begin kernel.
+struct StepBlock {
+    StageCoeffs st[3];
+    unsigned long long dtmin_bits;  // CFL reduction slot (order-preserving bits)
+    unsigned int flags;             // bit 0: non-finite / non-positive mean seen
+    unsigned int pad;
+};
+
+// host: library-own Gauss-Legendre generator and basis tables
+int make_tables(int n, Tables* t);
+double basis_phi(int a, double x);
+
+// launchers (all asynchronous on `s`)
+hipError_t launch_project(int n, int nvar, const Geo& g, const Tables& T, const double* prim_dev,
+                          double* u_dev, hipStream_t s);
+hipError_t launch_stage(int n, const Geo& g, const Tables& T, const double* u, const double* un,
+                        const double* u0, double* out, const StageCoeffs* sc, hipStream_t s);
+hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
+                             double a2, hipStream_t s);
+hipError_t launch_dt(int n, const Geo& g, const double* u, StepBlock* sb, hipStream_t s);
+hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double dt_fixed,
+                             double* dt_used_dev, hipStream_t s);
+hipError_t launch_damp(int n, const Geo& g, const Tables& T, double* u, const double* u0,
+                       const int* list, int nlist, const StageCoeffs* sc, hipStream_t s);
+hipError_t launch_torque(int n, const Geo& g, const Tables& T, double t, const double* t_dev,
+                         const double* u, double* partials, int nblocks, double* out,
+                         hipStream_t s);
+int torque_blocks(const Geo& g);
+
+}  // namespace dgk

@@ -1,0 +1,701 @@
+// gfx950 kernels of the modal DG right-hand side (Sec. 2.2 eq. (3)), the
+// SSP-RK3 stage update (Algorithm 1, Appendix A), the CFL reduction (Sec. 2.3),
+// wave-killing damping (Sec. 5.1) and the planet torque (Sec. 5.2 eq. (5)).
+//
+// Stage kernel layout: one thread per element, 64 consecutive elements of a
+// row per wavefront; the state is read plane by plane ([var][mode][element],
+// element fastest), so every load and store of a wavefront is one contiguous
+// 512-byte segment.  Each thread evaluates the Rusanov flux on its own four
+// edges; the neighbour's trace is recomputed from the neighbour's modes, which
+// the wavefront has just read (x neighbours: adjacent lanes) or the adjacent
+// row's wavefront reads on the same XCD (y neighbours), so the state crosses
+// HBM once per stage.  Volume integrals are sum-factorised per node column.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "dg_internal.h"
+
+namespace dgk {
+
+enum { CL_ISO = 0, CL_LOC = 1, CL_ADI = 2 };
+
+template <int CL>
+struct NVar {
+    static constexpr int value = CL == CL_ADI ? 4 : 3;
+};
+
+// Blocks are dealt to the 8 XCDs round-robin (block b on XCD b % 8).  Give
+// each XCD a contiguous band of tiles, so the rows above and below a tile are
+// being read through the same L2.
+__device__ __forceinline__ int remap_tile(int b, int total) {
+    if ((total & 7) != 0) return b;
+    const int per = total >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// pressure and sound speed of the conservative state U at (x, y); inv = 1/rho
+template <int CL>
+__device__ __forceinline__ void pressure(const Geo& g, const double* U, double inv, double x, double y,
+                                         double& p, double& c) {
+    if constexpr (CL == CL_ISO) {
+        p = g.cs2 * U[0];
+        c = sqrt(g.cs2);
+    } else if constexpr (CL == CL_LOC) {
+        const double r = sqrt(x * x + y * y);
+        const double cs2 = g.h2gm / (r > g.r_core ? r : g.r_core);
+        p = cs2 * U[0];
+        c = sqrt(cs2);
+    } else {
+        const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2]) * inv;
+        p = (g.gamma - 1.0) * (U[3] - ke);
+        c = sqrt(g.gamma * p * inv);
+    }
+}
+
+// gradient of the stellar (harmonic core inside r_core, point mass outside)
+// plus softened planet potential
+__device__ __forceinline__ void grad_phi(const Geo& g, double x, double y, double xp, double yp,
+                                         double& gx, double& gy) {
+    gx = 0.0;
+    gy = 0.0;
+    if (g.star) {
+        const double r2 = x * x + y * y;
+        const double r = sqrt(r2);
+        const double k = r < g.r_core ? g.rc3inv : g.gm / (r2 * r);
+        gx = k * x;
+        gy = k * y;
+    }
+    if (g.q > 0.0) {
+        const double dx = x - xp, dy = y - yp;
+        const double d2 = dx * dx + dy * dy + g.eps2;
+        const double k = g.q / (d2 * sqrt(d2));
+        gx += k * dx;
+        gy += k * dy;
+    }
+}
+
+// Rusanov flux through an axis-aligned edge with outward normal SGN * e_AX
+template <int CL, int AX, int SGN>
+__device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const double* Uo, double x,
+                                        double y, double* h) {
+    constexpr int NV = NVar<CL>::value;
+    const double ii = 1.0 / Ui[0], io = 1.0 / Uo[0];
+    double pi, ci, po, co;
+    pressure<CL>(g, Ui, ii, x, y, pi, ci);
+    pressure<CL>(g, Uo, io, x, y, po, co);
+    const double vni = SGN * Ui[1 + AX] * ii;
+    const double vno = SGN * Uo[1 + AX] * io;
+    double Fi[NV], Fo[NV];
+    Fi[0] = Ui[0] * vni;
+    Fo[0] = Uo[0] * vno;
+    Fi[1] = Ui[1] * vni + (AX == 0 ? SGN * pi : 0.0);
+    Fo[1] = Uo[1] * vno + (AX == 0 ? SGN * po : 0.0);
+    Fi[2] = Ui[2] * vni + (AX == 1 ? SGN * pi : 0.0);
+    Fo[2] = Uo[2] * vno + (AX == 1 ? SGN * po : 0.0);
+    if constexpr (NV == 4) {
+        Fi[3] = (Ui[3] + pi) * vni;
+        Fo[3] = (Uo[3] + po) * vno;
+    }
+    const double si = fabs(vni) + ci, so = fabs(vno) + co;
+    const double alpha = si > so ? si : so;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) h[v] = 0.5 * (Fi[v] + Fo[v]) - 0.5 * alpha * (Uo[v] - Ui[v]);
+}
+
+// Edge F (0 west, 1 east, 2 south, 3 north) of element (i, j): own trace from
+// registers, exterior trace from the neighbour's modes (or the initial state
+// at a fixed box edge), Rusanov flux at the n edge Gauss points, lifted into R.
+template <int N, int CL, int F>
+__device__ __forceinline__ void edge_term(const Geo& g, const Tables& T, const double (&U)[NVar<CL>::value][N * N],
+                                          double (&R)[NVar<CL>::value][N * N], const double* __restrict__ u,
+                                          const double* __restrict__ u0, int i, int j, long long e,
+                                          double xc, double yc) {
+    constexpr int NV = NVar<CL>::value;
+    constexpr int NN = N * N;
+    constexpr int AX = F < 2 ? 0 : 1;
+    constexpr int SGN = (F == 0 || F == 2) ? -1 : 1;
+    const long long E = g.E;
+
+    int in = i + (F == 1) - (F == 0);
+    int jn = j + (F == 3) - (F == 2);
+    const bool outside = in < 0 || in >= g.nx || jn < 0 || jn >= g.ny;
+    if (in < 0) in += g.nx;
+    if (in >= g.nx) in -= g.nx;
+    if (jn < 0) jn += g.ny;
+    if (jn >= g.ny) jn -= g.ny;
+    const bool fixed = outside && g.bc == 1;
+    const double* src = fixed ? u0 : u;
+    const long long en = fixed ? e : (long long)jn * g.nx + in;
+    // the neighbour sees the shared edge on its opposite side; a fixed box
+    // edge takes the element's own initial trace on the same side
+    const double* sown = SGN < 0 ? T.pm : T.pp;
+    const double* snb = fixed ? sown : (SGN < 0 ? T.pp : T.pm);
+
+    double ti[NV][N], to[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double ci[N], co[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            ci[k] = 0.0;
+            co[k] = 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                const double un = src[(long long)(v * NN + a * N + b) * E + en];
+                if constexpr (AX == 0) {  // collapse the x degree at xi = +-1
+                    ci[b] += sown[a] * U[v][a * N + b];
+                    co[b] += snb[a] * un;
+                } else {  // collapse the y degree at eta = +-1
+                    ci[a] += sown[b] * U[v][a * N + b];
+                    co[a] += snb[b] * un;
+                }
+            }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double si = 0.0, so = 0.0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                si += ci[m] * T.phi[m][k];
+                so += co[m] * T.phi[m][k];
+            }
+            ti[v][k] = si;
+            to[v][k] = so;
+        }
+    }
+    double gl[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < N; ++m) gl[v][m] = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double Ui[NV], Uo[NV], h[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Ui[v] = ti[v][k];
+            Uo[v] = to[v][k];
+        }
+        const double x = AX == 0 ? xc + SGN * 0.5 * g.dx : xc + 0.5 * g.dx * T.xi[k];
+        const double y = AX == 0 ? yc + 0.5 * g.dy * T.xi[k] : yc + SGN * 0.5 * g.dy;
+        rusanov<CL, AX, SGN>(g, Ui, Uo, x, y, h);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < N; ++m) gl[v][m] += T.wh[k] * h[v] * T.phi[m][k];
+    }
+    const double s = AX == 0 ? g.idx : g.idy;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                if constexpr (AX == 0)
+                    R[v][a * N + b] -= s * sown[a] * gl[v][b];
+                else
+                    R[v][a * N + b] -= s * sown[b] * gl[v][a];
+            }
+}
+
+// out = a0 u^n + a1 u + a2 L(u, t) for every element (a0 = 0: u^n not read).
+// `un` and `out` may alias (the last SSP stage updates u^n in place; each
+// thread reads and writes only its own element there).
+template <int N, int CL>
+__global__ void __launch_bounds__(64) k_stage(const Geo g, const Tables T, const double* __restrict__ u,
+                                              const double* un, const double* __restrict__ u0, double* out,
+                                              const StageCoeffs* __restrict__ scp) {
+    constexpr int NV = NVar<CL>::value;
+    constexpr int NN = N * N;
+    const int tile = remap_tile(blockIdx.x, g.tiles_total);
+    const int j = tile / g.tiles_x;
+    const int i = (tile - j * g.tiles_x) * kWave + threadIdx.x;
+    if (i >= g.nx) return;
+    const long long E = g.E;
+    const long long e = (long long)j * g.nx + i;
+    const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
+
+    double U[NV][NN], R[NV][NN];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NN; ++m) {
+            U[v][m] = u[(long long)(v * NN + m) * E + e];
+            R[v][m] = 0.0;
+        }
+    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+
+    // edge integrals
+    edge_term<N, CL, 0>(g, T, U, R, u, u0, i, j, e, xc, yc);
+    edge_term<N, CL, 1>(g, T, U, R, u, u0, i, j, e, xc, yc);
+    edge_term<N, CL, 2>(g, T, U, R, u, u0, i, j, e, xc, yc);
+    edge_term<N, CL, 3>(g, T, U, R, u, u0, i, j, e, xc, yc);
+
+    // volume integrals, one Gauss column xi_q at a time
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const double x = xc + 0.5 * g.dx * T.xi[q];
+        double c[NV][N];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < N; ++a) s += T.phi[a][q] * U[v][a * N + b];
+                c[v][b] = s;
+            }
+        double Ax[NV][N], By[NV][N];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                Ax[v][b] = 0.0;
+                By[v][b] = 0.0;
+            }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double W[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) s += c[v][b] * T.phi[b][r];
+                W[v] = s;
+            }
+            const double y = yc + 0.5 * g.dy * T.xi[r];
+            const double inv = 1.0 / W[0];
+            double p, cs;
+            pressure<CL>(g, W, inv, x, y, p, cs);
+            const double vx = W[1] * inv, vy = W[2] * inv;
+            double fx[NV], fy[NV], S[NV];
+            fx[0] = W[1];
+            fy[0] = W[2];
+            fx[1] = W[1] * vx + p;
+            fy[1] = W[1] * vy;
+            fx[2] = W[2] * vx;
+            fy[2] = W[2] * vy + p;
+            if constexpr (NV == 4) {
+                fx[3] = (W[3] + p) * vx;
+                fy[3] = (W[3] + p) * vy;
+            }
+            double gx, gy;
+            grad_phi(g, x, y, xp, yp, gx, gy);
+            S[0] = 0.0;
+            S[1] = -W[0] * gx;
+            S[2] = -W[0] * gy;
+            if constexpr (NV == 4) S[3] = -(W[1] * gx + W[2] * gy);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    Ax[v][b] += T.wh[r] * T.phi[b][r] * fx[v];
+                    By[v][b] += T.wh[r] * (g.rdy2 * T.dphi[b][r] * fy[v] + T.phi[b][r] * S[v]);
+                }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+                    R[v][a * N + b] += T.wh[q] * (g.rdx2 * T.dphi[a][q] * Ax[v][b] + T.phi[a][q] * By[v][b]);
+    }
+
+    // RK stage combination (Shu-Osher form of SSP(3,3)) or plain L(u)
+    if (a0 != 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NN; ++m) {
+                const long long idx = (long long)(v * NN + m) * E + e;
+                out[idx] = a0 * un[idx] + (a1 * U[v][m] + a2 * R[v][m]);
+            }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NN; ++m) out[(long long)(v * NN + m) * E + e] = a1 * U[v][m] + a2 * R[v][m];
+    }
+}
+
+// ------------------------------------------------------------------ init
+template <int N, int NV>
+__global__ void __launch_bounds__(64) k_project(const Geo g, const Tables T, const double* __restrict__ prim,
+                                                double* __restrict__ u) {
+    constexpr int NN = N * N;
+    const long long e = (long long)blockIdx.x * 64 + threadIdx.x;
+    if (e >= g.E) return;
+    const long long E = g.E;
+    double C[NV][NN];
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+        const double rho = prim[(0 * E + e) * NN + k];
+        const double vx = prim[(1 * E + e) * NN + k];
+        const double vy = prim[(2 * E + e) * NN + k];
+        C[0][k] = rho;
+        C[1][k] = rho * vx;
+        C[2][k] = rho * vy;
+        if constexpr (NV == 4) {
+            const double p = prim[(3 * E + e) * NN + k];
+            C[3][k] = p / (g.gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < N; ++q)
+#pragma unroll
+                    for (int r = 0; r < N; ++r)
+                        s += C[v][q * N + r] * (T.wh[q] * T.wh[r] * T.phi[a][q] * T.phi[b][r]);
+                u[(long long)(v * NN + a * N + b) * E + e] = s;
+            }
+}
+
+// ------------------------------------------------------------------ small kernels
+__device__ __forceinline__ void planet_at(const Geo& g, double t, double& xp, double& yp) {
+    double sn, cs;
+    sincos(g.omp * t + g.phi0, &sn, &cs);
+    xp = g.rp * cs;
+    yp = g.rp * sn;
+}
+
+__global__ void k_set_coeffs(StageCoeffs* sc, const Geo g, double t, double a0, double a1, double a2) {
+    StageCoeffs c;
+    c.t = t;
+    planet_at(g, t, c.xp, c.yp);
+    c.a0 = a0;
+    c.a1 = a1;
+    c.a2 = a2;
+    c.dt = 0.0;
+    c.pad = 0.0;
+    *sc = c;
+}
+
+__global__ void k_step_begin(const Geo g, StepBlock* sb, double* t_dev, double dt_fixed, double* dt_used) {
+    const double t = *t_dev;
+    const double dt = dt_fixed > 0.0 ? dt_fixed : __longlong_as_double((long long)sb->dtmin_bits);
+    sb->dtmin_bits = 0x7FF0000000000000ull;  // +inf: ready for the next reduction
+    const double cst[3] = {0.0, 1.0, 0.5};
+    const double a0[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double a1[3] = {1.0, 0.25, 2.0 / 3.0};
+    const double a2[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int s = 0; s < 3; ++s) {
+        StageCoeffs c;
+        c.t = t + cst[s] * dt;
+        planet_at(g, c.t, c.xp, c.yp);
+        c.a0 = a0[s];
+        c.a1 = a1[s];
+        c.a2 = a2[s] * dt;
+        c.dt = dt;
+        c.pad = 0.0;
+        sb->st[s] = c;
+    }
+    *t_dev = t + dt;
+    if (dt_used) *dt_used = dt;
+}
+
+// CFL step of Sec. 2.3 per element from its means; global minimum by an
+// atomic min on the (order-preserving) bit pattern of the positive double.
+template <int CL>
+__global__ void __launch_bounds__(256) k_dt(const Geo g, int nn, const double* __restrict__ u, StepBlock* sb) {
+    __shared__ double red[4];
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    double dte = INFINITY;
+    bool bad = false;
+    if (e < g.E) {
+        const long long E = g.E;
+        double U[4];
+        U[0] = u[e];
+        U[1] = u[(long long)nn * E + e];
+        U[2] = u[(long long)2 * nn * E + e];
+        U[3] = CL == CL_ADI ? u[(long long)3 * nn * E + e] : 0.0;
+        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+        double p, c;
+        pressure<CL>(g, U, 1.0 / U[0], xc, yc, p, c);
+        const double sx = (fabs(U[1] / U[0]) + c) / g.dx;
+        const double sy = (fabs(U[2] / U[0]) + c) / g.dy;
+        dte = g.cfl_fac / (sx + sy);
+        bad = !(U[0] > 0.0) || !(dte > 0.0) || !isfinite(dte);
+        if (bad) dte = INFINITY;
+    }
+    for (int off = 32; off > 0; off >>= 1) dte = fmin(dte, __shfl_xor(dte, off));
+    if (bad) atomicOr(&sb->flags, 1u);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = dte;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+        if (m < INFINITY) atomicMin(&sb->dtmin_bits, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// ------------------------------------------------------------------ damping
+// nodal values of NV variables from modes (sum-factorised)
+template <int N, int NV>
+__device__ __forceinline__ void eval_nodes(const Tables& T, const double (&M)[NV][N * N], double (&W)[NV][N * N]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            double c[N];
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < N; ++a) s += T.phi[a][q] * M[v][a * N + b];
+                c[b] = s;
+            }
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) s += c[b] * T.phi[b][r];
+                W[v][q * N + r] = s;
+            }
+        }
+}
+
+// ramp R(r) of the wave-killing zones and the zone's damping period T_d
+__device__ __forceinline__ double ramp(const Geo& g, double r, double& td) {
+    if (r < g.rd_in) {
+        const double s = (r - g.rd_in) / (g.rb_in - g.rd_in);
+        td = g.td_in;
+        return s > 1.0 ? 1.0 : s * s;
+    }
+    if (r > g.rd_out) {
+        const double s = (r - g.rd_out) / (g.rb_out - g.rd_out);
+        td = g.td_out;
+        return s > 1.0 ? 1.0 : s * s;
+    }
+    td = g.td_in;
+    return 0.0;
+}
+
+template <int N, int CL>
+__global__ void __launch_bounds__(64) k_damp(const Geo g, const Tables T, double* __restrict__ u,
+                                             const double* __restrict__ u0, const int* __restrict__ list, int nlist,
+                                             const StageCoeffs* __restrict__ scp) {
+    constexpr int NV = NVar<CL>::value;
+    constexpr int NN = N * N;
+    const int idx = blockIdx.x * 64 + threadIdx.x;
+    if (idx >= nlist) return;
+    const long long e = list[idx];
+    const long long E = g.E;
+    const double dt = scp->dt;
+    const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+    double M[NV][NN], W[NV][NN], W0[NV][NN];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NN; ++m) M[v][m] = u0[(long long)(v * NN + m) * E + e];
+    eval_nodes<N, NV>(T, M, W0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NN; ++m) M[v][m] = u[(long long)(v * NN + m) * E + e];
+    eval_nodes<N, NV>(T, M, W);
+    // nodal increments (written over W)
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const int k = q * N + r;
+            const double x = xc + 0.5 * g.dx * T.xi[q], y = yc + 0.5 * g.dy * T.xi[r];
+            double td;
+            const double R = ramp(g, sqrt(x * x + y * y), td);
+            if (R <= 0.0) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) W[v][k] = 0.0;
+                continue;
+            }
+            const double w = dt * R / (td + dt * R);
+            const double rho = W[0][k], vx = W[1][k] / rho, vy = W[2][k] / rho;
+            const double rho0 = W0[0][k], vx0 = W0[1][k] / rho0, vy0 = W0[2][k] / rho0;
+            const double drho = w * (rho0 - rho);
+            const double dvx = w * (vx0 - vx), dvy = w * (vy0 - vy);
+            const double vx1 = vx + dvx, vy1 = vy + dvy;
+            double D3 = 0.0;
+            if constexpr (NV == 4) {
+                const double gm1 = g.gamma - 1.0;
+                const double T1 = gm1 * (W[3][k] - 0.5 * rho * (vx * vx + vy * vy)) / rho;
+                const double T0 = gm1 * (W0[3][k] - 0.5 * rho0 * (vx0 * vx0 + vy0 * vy0)) / rho0;
+                const double dT = w * (T0 - T1);
+                const double dp = rho * dT + drho * (T1 + dT);
+                const double dke = 0.5 * (drho * (vx1 * vx1 + vy1 * vy1) + rho * (dvx * (vx1 + vx) + dvy * (vy1 + vy)));
+                D3 = dp / gm1 + dke;
+            }
+            W[0][k] = drho;
+            W[1][k] = rho * dvx + drho * vx1;
+            W[2][k] = rho * dvy + drho * vy1;
+            if constexpr (NV == 4) W[3][k] = D3;
+        }
+    // project the increments and add them to the modes
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            double c[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) s += T.wh[q] * T.phi[a][q] * W[v][q * N + r];
+                c[r] = s;
+            }
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < N; ++r) s += T.wh[r] * T.phi[b][r] * c[r];
+                M[v][a * N + b] += s;
+            }
+        }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NN; ++m) u[(long long)(v * NN + m) * E + e] = M[v][m];
+}
+
+// ------------------------------------------------------------------ torque
+constexpr int kTorqueBlock = 256;
+
+// deterministic block sum: fixed xor-butterfly inside each wavefront, then the
+// four wavefront sums in order
+__device__ __forceinline__ double block_sum_256(double s, double* red) {
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    return r;
+}
+
+template <int N>
+__global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, const Tables T, double t, const double* t_dev,
+                                                         const double* __restrict__ u, double* __restrict__ partials) {
+    __shared__ double red[4];
+    constexpr int NN = N * N;
+    const long long e = (long long)blockIdx.x * kTorqueBlock + threadIdx.x;
+    const double tt = t_dev ? *t_dev : t;
+    double xp, yp;
+    planet_at(g, tt, xp, yp);
+    double s = 0.0;
+    if (e < g.E) {
+        double M[1][NN], W[1][NN];
+#pragma unroll
+        for (int m = 0; m < NN; ++m) M[0][m] = u[(long long)m * g.E + e];
+        eval_nodes<N, 1>(T, M, W);
+        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+        const double area = g.dx * g.dy;
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                const double x = xc + 0.5 * g.dx * T.xi[q], y = yc + 0.5 * g.dy * T.xi[r];
+                const double m = W[0][q * N + r] * T.wh[q] * T.wh[r] * area;
+                const double dx = x - xp, dy = y - yp;
+                const double d2 = dx * dx + dy * dy + g.eps2;
+                const double k = m / (d2 * sqrt(d2));
+                s += xp * (k * dy) - yp * (k * dx);
+            }
+    }
+    const double b = block_sum_256(s, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+__global__ void __launch_bounds__(kTorqueBlock) k_torque_final(const double* __restrict__ partials, int nb,
+                                                               double* __restrict__ out) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kTorqueBlock) s += partials[k];
+    const double b = block_sum_256(s, red);
+    if (threadIdx.x == 0) *out = b;
+}
+
+// ------------------------------------------------------------------ launchers
+#define DG_DISPATCH_N(n, BODY)               \
+    switch (n) {                             \
+        case 2: { constexpr int NT = 2; BODY; } break; \
+        case 3: { constexpr int NT = 3; BODY; } break; \
+        case 4: { constexpr int NT = 4; BODY; } break; \
+        case 5: { constexpr int NT = 5; BODY; } break; \
+        default: return hipErrorInvalidValue;  \
+    }
+
+#define DG_DISPATCH_CL(cl, BODY)             \
+    switch (cl) {                            \
+        case CL_ISO: { constexpr int CT = CL_ISO; BODY; } break; \
+        case CL_LOC: { constexpr int CT = CL_LOC; BODY; } break; \
+        case CL_ADI: { constexpr int CT = CL_ADI; BODY; } break; \
+        default: return hipErrorInvalidValue;  \
+    }
+
+hipError_t launch_project(int n, int nvar, const Geo& g, const Tables& T, const double* prim, double* u,
+                          hipStream_t s) {
+    const int blocks = (int)((g.E + 63) / 64);
+    if (nvar == 4) {
+        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_project<NT, 4>), dim3(blocks), dim3(64), 0, s, g, T, prim, u));
+    } else {
+        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_project<NT, 3>), dim3(blocks), dim3(64), 0, s, g, T, prim, u));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(int n, const Geo& g, const Tables& T, const double* u, const double* un, const double* u0,
+                        double* out, const StageCoeffs* sc, hipStream_t s) {
+    DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_stage<NT, CT>), dim3(g.tiles_total), dim3(64), 0,
+                                                                  s, g, T, u, un, u0, out, sc)));
+    return hipGetLastError();
+}
+
+hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1, double a2,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_set_coeffs, dim3(1), dim3(1), 0, s, sc, g, t, a0, a1, a2);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(int n, const Geo& g, const double* u, StepBlock* sb, hipStream_t s) {
+    const int blocks = (int)((g.E + 255) / 256);
+    DG_DISPATCH_CL(g.closure, hipLaunchKernelGGL((k_dt<CT>), dim3(blocks), dim3(256), 0, s, g, n * n, u, sb));
+    return hipGetLastError();
+}
+
+hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double dt_fixed, double* dt_used,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, g, sb, t_dev, dt_fixed, dt_used);
+    return hipGetLastError();
+}
+
+hipError_t launch_damp(int n, const Geo& g, const Tables& T, double* u, const double* u0, const int* list, int nlist,
+                       const StageCoeffs* sc, hipStream_t s) {
+    if (nlist <= 0) return hipSuccess;
+    const int blocks = (nlist + 63) / 64;
+    DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_damp<NT, CT>), dim3(blocks), dim3(64), 0, s, g,
+                                                                  T, u, u0, list, nlist, sc)));
+    return hipGetLastError();
+}
+
+int torque_blocks(const Geo& g) { return (int)((g.E + kTorqueBlock - 1) / kTorqueBlock); }
+
+hipError_t launch_torque(int n, const Geo& g, const Tables& T, double t, const double* t_dev, const double* u,
+                         double* partials, int nblocks, double* out, hipStream_t s) {
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_torque<NT>), dim3(nblocks), dim3(kTorqueBlock), 0, s, g, T, t, t_dev, u,
+                                        partials));
+    hipLaunchKernelGGL(k_torque_final, dim3(1), dim3(kTorqueBlock), 0, s, partials, nblocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace dgk

@@ -1,0 +1,92 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, validates configurations before touching a device, and its
+node coordinates match the oracle's.  No kernel is launched here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1805_01443_amd import dg
+from paper_1805_01443_amd import configs as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(dg_\w+)\s*\(", txt, re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = dg.lib()
+    names = _declared_symbols()
+    assert {"dg_init", "dg_rhs", "dg_rk_step", "dg_torque"} <= names
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(dg.EXPORTS) <= names
+
+
+def test_nm_exports_are_c_symbols():
+    out = os.popen("nm -D --defined-only " + dg.LIB_PATH).read()
+    for n in _declared_symbols():
+        assert re.search(r"\bT\s+" + n + r"\b", out), n
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_nodes_match_oracle(order):
+    cfg = W.disc(nx=7, order=order).replace(ny=5)
+    x, y = dg.dg_get_nodes(cfg)
+    ox, oy = O.nodes(O.cfg(dataclass_fields(cfg)))
+    assert np.max(np.abs(x - ox)) < 1e-15 and np.max(np.abs(y - oy)) < 1e-15
+
+
+def dataclass_fields(cfg):
+    import dataclasses
+    return dataclasses.asdict(cfg)
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(order=7), dg.DG_EUNSUPPORTED),
+    (dict(order=1), dg.DG_EUNSUPPORTED),
+    (dict(nx=0), dg.DG_EINVAL),
+    (dict(nvar=4), dg.DG_EINVAL),
+    (dict(x1=-1.0), dg.DG_EINVAL),
+    (dict(cfl=0.0), dg.DG_EINVAL),
+    (dict(closure=9), dg.DG_EINVAL),
+    (dict(q=-1.0), dg.DG_EINVAL),
+])
+def test_init_rejects_bad_configs_without_a_device(bad, code):
+    cfg = W.wave(nx=8).replace(**bad)
+    prim = np.ones((3, 64, 9))
+    h = C.c_void_p()
+    c = cfg.to_c()
+    dp = C.POINTER(C.c_double)
+    rc = dg.lib().dg_init(C.byref(c), prim.ctypes.data_as(dp), None, C.c_void_p(8), None, C.byref(h))
+    assert rc == code
+    assert h.value is None
+    assert dg.lib().dg_last_error(None)
+
+
+def test_null_handle_calls_fail_cleanly():
+    L = dg.lib()
+    assert L.dg_rhs(None, 0.0, None, None) == dg.DG_EINVAL
+    assert L.dg_rk_step(None, None, None, 0.0, None) == dg.DG_EINVAL
+    assert L.dg_torque(None, 0.0, None, None, None) == dg.DG_EINVAL
+    assert L.dg_sync(None) == dg.DG_EINVAL
+    assert L.dg_free(None) == dg.DG_OK
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1805_01443_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"(import\s+oracle|from\s+oracle|liboracle|dg_oracle|or_rhs)", txt), fn

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 CPU oracle.
+
+Bar (FP64 path): per variable, max|gpu - oracle| / max|oracle| <= 1e-12 over
+all modes, for the initial projection, one right-hand side, and a few full
+steps; the torque within 1e-12 of the sum of |terms|.  Inputs are identical:
+primitive node values are generated once (seeded) from the oracle's node
+coordinates and handed to both sides.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1805_01443_amd import configs as W
+from paper_1805_01443_amd import dg
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU test needs a ROCm device"
+    return T
+
+
+def ocfg(cfg):
+    return O.cfg(dataclasses.asdict(cfg))
+
+
+def prim_oracle_nodes(cfg, kind, seed=None):
+    oc = ocfg(cfg)
+    x, y = O.nodes(oc)
+    return W.prim_for(cfg, kind, seed=seed, x=x, y=y)
+
+
+def relerr(a, b):
+    """per-variable relative max-norm error, as a list"""
+    out = []
+    for v in range(a.shape[0]):
+        den = max(np.max(np.abs(b[v])), 1e-300)
+        out.append(float(np.max(np.abs(a[v] - b[v])) / den))
+    return out
+
+
+def setup(cfg, kind, seed=None):
+    T = torch()
+    prim = prim_oracle_nodes(cfg, kind, seed)
+    h, u0 = dg.dg_init(cfg, prim)
+    T.cuda.synchronize()
+    uo = O.project(ocfg(cfg), prim)
+    return h, u0, uo
+
+
+CASES = [
+    # (name, config, initial data)
+    ("wave_p1", W.wave(nx=70, order=2).replace(ny=9), "wave"),
+    ("wave_p2", W.wave(nx=70, order=3).replace(ny=9), "wave"),
+    ("wave_p3", W.wave(nx=70, order=4).replace(ny=9), "wave"),
+    ("wave_p4", W.wave(nx=70, order=5).replace(ny=9), "wave"),
+    ("wave_1x1", W.wave(nx=1, order=3), "wave"),
+    ("wave_65x3", W.wave(nx=65, order=4).replace(ny=3), "wave"),
+    ("disc_p2", W.disc(nx=24, order=3, q=1e-3).replace(ny=20), "disc"),
+    ("disc_p4", W.disc(nx=24, order=5, q=1e-3).replace(ny=22), "disc"),
+    ("disc_p4_130", W.disc(nx=130, order=5, q=1e-3).replace(ny=6), "disc"),
+    ("ring_p3", W.disc_ring(nx=20, order=4).replace(ny=18), "disc_ring"),
+    ("ring_p1", W.disc_ring(nx=33, order=2).replace(ny=17), "disc_ring"),
+]
+
+
+@pytest.mark.parametrize("name,cfg,kind", CASES, ids=[c[0] for c in CASES])
+def test_projection_and_rhs_parity(name, cfg, kind):
+    T = torch()
+    print(f"[parity] {name} order={cfg.order} nx={cfg.nx} ny={cfg.ny}", flush=True)
+    h, u0, uo = setup(cfg, kind, seed=3 if kind == "disc" else None)
+    assert max(relerr(u0.cpu().numpy(), uo)) <= TOL
+    t = 0.37
+    rhs = T.empty_like(u0)
+    dg.dg_rhs(h, t, u0, rhs)
+    T.cuda.synchronize()
+    ro = O.rhs(ocfg(cfg), t, uo, u0=uo)
+    err = relerr(rhs.cpu().numpy(), ro)
+    print("  rhs rel err", err, flush=True)
+    assert max(err) <= TOL
+    h.close()
+
+
+@pytest.mark.parametrize("name,cfg,kind,nsteps", [
+    ("wave_p2", W.wave(nx=70, order=3).replace(ny=9), "wave", 5),
+    ("wave_p4", W.wave(nx=40, order=5).replace(ny=12), "wave", 3),
+    ("disc_p4_damped", W.disc(nx=26, order=5, q=1e-3), "disc", 3),
+    ("ring_p3", W.disc_ring(nx=20, order=4).replace(ny=18), "disc_ring", 3),
+])
+def test_rk_steps_parity(name, cfg, kind, nsteps):
+    T = torch()
+    print(f"[steps] {name} order={cfg.order} nx={cfg.nx} ny={cfg.ny} steps={nsteps}", flush=True)
+    h, u, uo = setup(cfg, kind)
+    u0o = uo.copy()
+    oc = ocfg(cfg)
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    t = 0.0
+    for s in range(nsteps):
+        dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
+        dg.dg_sync(h)
+        uo_new, dto = O.step(oc, uo, t, 0.0, u0=u0o)
+        assert abs(dt_dev.item() - dto) <= 1e-14 * dto
+        # both sides continue with the oracle's dt and time so the comparison
+        # isolates one step at a time
+        uo = uo_new
+        t += dto
+        assert abs(t_dev.item() - t) <= 1e-14 * max(t, 1.0)
+        err = relerr(u.cpu().numpy(), uo)
+        print(f"  step {s}: rel err {err}", flush=True)
+        assert max(err) <= TOL
+    h.close()
+
+
+def test_torque_parity_and_determinism():
+    T = torch()
+    cfg = W.disc(nx=48, order=5, q=1e-5)
+    h, u0, uo = setup(cfg, "disc", seed=1)
+    out = T.zeros(2, dtype=T.float64, device="cuda")
+    tdev = T.full((1,), 0.8, dtype=T.float64, device="cuda")
+    dg.dg_torque(h, u0, out[0:1], t=0.8)
+    dg.dg_torque(h, u0, out[1:2], t_dev=tdev)
+    T.cuda.synchronize()
+    g, sabs = O.torque(ocfg(cfg), 0.8, uo)
+    res = out.cpu().numpy()
+    assert res[0] == res[1]  # same bits from the host time and the device time
+    assert abs(res[0] - g) <= TOL * sabs, (res[0], g, sabs)
+    h.close()
+
+
+def test_cfl_dt_matches_closed_form_cfg1():
+    T = torch()
+    cfg = W.wave(nx=64, order=3)
+    h, u, _ = setup(cfg, "wave")
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
+    dg.dg_sync(h)
+    assert abs(dt_dev.item() - 0.2 / 5 / (4 * 64)) < 1e-18
+    h.close()
+
+
+def test_rk_step_is_deterministic():
+    T = torch()
+    cfg = W.disc(nx=40, order=4, q=1e-4)
+    h, u, _ = setup(cfg, "disc", seed=2)
+    a = u.clone()
+    b = u.clone()
+    for x in (a, b):
+        t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+        for _ in range(2):
+            dg.dg_rk_step(h, x, t_dev, 0.0, None)
+    dg.dg_sync(h)
+    assert T.equal(a, b)
+    h.close()
+
+
+def test_nonfinite_state_is_reported():
+    T = torch()
+    cfg = W.wave(nx=16, order=3)
+    h, u, _ = setup(cfg, "wave")
+    u[0, 0, 5] = -1.0  # negative mean density in one element (host-made state)
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dg.dg_rk_step(h, u, t_dev, 1e-4, None)
+    with pytest.raises(dg.DGError) as ei:
+        dg.dg_sync(h)
+    assert ei.value.code == dg.DG_ENONFINITE
+    dg.dg_sync(h)  # flag cleared
+    h.close()
+
+
+@pytest.mark.slow
+def test_full_size_disc_step_parity():
+    """512 x 512, order 5 (the benchmark's configuration): one full step
+    (CFL dt, three stages, damping) and the torque, against the oracle."""
+    T = torch()
+    cfg = W.disc(nx=512, order=5)
+    print("[full] disc 512x512 order 5, one step", flush=True)
+    h, u, uo = setup(cfg, "disc")
+    u0o = uo.copy()
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dg.dg_rk_step(h, u, t_dev, 0.0, None)
+    tq = T.zeros(1, dtype=T.float64, device="cuda")
+    dg.dg_torque(h, u, tq, t_dev=t_dev)
+    dg.dg_sync(h)
+    uo, dto = O.step(ocfg(cfg), uo, 0.0, 0.0, u0=u0o)
+    err = relerr(u.cpu().numpy(), uo)
+    print("  rel err", err, flush=True)
+    assert max(err) <= TOL
+    g, sabs = O.torque(ocfg(cfg), dto, uo)
+    assert abs(tq.item() - g) <= TOL * sabs
+    h.close()
