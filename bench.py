@@ -37,7 +37,26 @@ def parse():
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain 2 GiB device-to-device copy, five times: the PMC byte counters of
+    this kernel, divided by 2 GiB, give the counter-to-HBM-bytes factors."""
+    import torch
+    n = 1 << 28  # doubles: 2 GiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8,
+                      "launches": 5, "GBps_read_plus_write": 2 * 5 * n * 8 / el / 1e9}), flush=True)
 
 
 def kernel_source_hash():
@@ -84,6 +103,9 @@ def cpu_baseline(cfg, prim):
 
 def main():
     a = parse()
+    if a.calibrate_copy:
+        calibrate_copy()
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note "
                                    "(see DESIGN.md), not an implemented path", "n_gpus": a.gpus}))

@@ -10,19 +10,18 @@
 #include <string>
 #include <vector>
 
+#include "dg_basis.h"
 #include "dg_internal.h"
 
 using dgk::Geo;
 using dgk::StageCoeffs;
 using dgk::StepBlock;
-using dgk::Tables;
 
 struct dg_handle {
     dg_config cfg{};
     int n = 0, nvar = 0;
     long long E = 0;
     Geo g{};
-    Tables T{};
     hipStream_t s = nullptr;
     int device = 0;
     double* u0 = nullptr;   // initial modes: fixed exterior state and damping target
@@ -127,8 +126,9 @@ void make_geo(const dg_config* c, Geo* g) {
     g->cfl_fac = c->cfl / (2.0 * (c->order - 1) + 1.0);
 }
 
-void host_nodes(const dg_config* c, const Tables& T, std::vector<double>* x, std::vector<double>* y) {
+void host_nodes(const dg_config* c, std::vector<double>* x, std::vector<double>* y) {
     const int n = c->order;
+    const dgk::BasisTab T = dgk::make_basis(n);
     const double dx = (c->x1 - c->x0) / c->nx, dy = (c->y1 - c->y0) / c->ny;
     const long long E = (long long)c->nx * c->ny;
     x->resize((size_t)E * n * n);
@@ -161,7 +161,7 @@ hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, c
         e = hipEventRecord(a, h->s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = dgk::launch_stage(h->n, h->g, h->T, u, un, h->u0, out, sc, h->s);
+    hipError_t e = dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, h->s);
     if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
     return e;
 }
@@ -188,10 +188,8 @@ int dg_get_nodes(const dg_config* cfg, double* x_host, double* y_host) {
     if (!cfg || !x_host || !y_host) return fail(nullptr, DG_EINVAL, "NULL argument");
     if (cfg->order < 2 || cfg->order > dgk::kMaxN) return fail(nullptr, DG_EUNSUPPORTED, "order must be in 2..5");
     if (cfg->nx < 1 || cfg->ny < 1) return fail(nullptr, DG_EINVAL, "nx, ny must be >= 1");
-    Tables T;
-    dgk::make_tables(cfg->order, &T);
     std::vector<double> x, y;
-    host_nodes(cfg, T, &x, &y);
+    host_nodes(cfg, &x, &y);
     std::memcpy(x_host, x.data(), x.size() * sizeof(double));
     std::memcpy(y_host, y.data(), y.size() * sizeof(double));
     return DG_OK;
@@ -215,7 +213,6 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, const double* e
     h->E = (long long)cfg->nx * cfg->ny;
     h->s = (hipStream_t)hip_stream;
     make_geo(cfg, &h->g);
-    dgk::make_tables(h->n, &h->T);
 
     auto bail = [&](int code) {
         g_err = h->err;
@@ -246,7 +243,7 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, const double* e
     // damped elements: any volume node with a non-zero ramp
     if (cfg->damping) {
         std::vector<double> x, y;
-        host_nodes(cfg, h->T, &x, &y);
+        host_nodes(cfg, &x, &y);
         std::vector<int> list;
         const int nn = h->n * h->n;
         for (long long el = 0; el < h->E; ++el) {
@@ -274,7 +271,7 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, const double* e
     sb0.dtmin_bits = 0x7FF0000000000000ull;
     e = hipMemcpyAsync(h->sb, &sb0, sizeof sb0, hipMemcpyHostToDevice, h->s);
     if (e == hipSuccess) e = hipMemcpyAsync(prim_dev, prim_nodes_host, state_bytes, hipMemcpyHostToDevice, h->s);
-    if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, h->T, prim_dev, u0_dev, h->s);
+    if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, u0_dev, h->s);
     if (e == hipSuccess) e = hipMemcpyAsync(h->u0, u0_dev, state_bytes, hipMemcpyDeviceToDevice, h->s);
     if (e == hipSuccess) e = hipStreamSynchronize(h->s);
     (void)hipFree(prim_dev);
@@ -287,7 +284,7 @@ int dg_rhs(dg_handle* h, double t, const double* u_dev, double* rhs_dev) {
     if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
     if (!u_dev || !rhs_dev || u_dev == rhs_dev) return fail(h, DG_EINVAL, "u_dev and rhs_dev must be distinct device arrays");
     DG_HIP(h, dgk::launch_set_coeffs(h->sc_rhs, h->g, t, 0.0, 0.0, 1.0, h->s), "dg_rhs coefficients");
-    DG_HIP(h, dgk::launch_stage(h->n, h->g, h->T, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, h->s), "dg_rhs stage");
+    DG_HIP(h, dgk::launch_stage(h->n, h->g, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, h->s), "dg_rhs stage");
     return DG_OK;
 }
 
@@ -302,7 +299,7 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1]), "stage 2");
     DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2]), "stage 3");
     if (h->cfg.damping)
-        DG_HIP(h, dgk::launch_damp(h->n, h->g, h->T, u_dev, h->u0, h->damp_list, h->ndamp, &sb->st[0], h->s),
+        DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->damp_list, h->ndamp, &sb->st[0], h->s),
                "damping");
     return DG_OK;
 }
@@ -310,7 +307,7 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
 int dg_torque(dg_handle* h, double t, const double* t_dev, const double* u_dev, double* torque_dev) {
     if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
     if (!u_dev || !torque_dev) return fail(h, DG_EINVAL, "u_dev and torque_dev are required");
-    DG_HIP(h, dgk::launch_torque(h->n, h->g, h->T, t, t_dev, u_dev, h->tq_part, h->tq_blocks, torque_dev, h->s),
+    DG_HIP(h, dgk::launch_torque(h->n, h->g, t, t_dev, u_dev, h->tq_part, h->tq_blocks, torque_dev, h->s),
            "torque");
     return DG_OK;
 }

@@ -10,17 +10,6 @@ namespace dgk {
 constexpr int kMaxN = 5;  // orders 2..5 (P1..P4)
 constexpr int kWave = 64;
 
-// Gauss-Legendre / Legendre tables, passed by value in the kernel argument
-// segment so every lookup is a uniform scalar load.
-struct Tables {
-    double phi[kMaxN][kMaxN];   // phi[a][q] = phi_a(xi_q)
-    double dphi[kMaxN][kMaxN];  // dphi[a][q] = phi_a'(xi_q)
-    double wh[kMaxN];           // Gauss weights / 2 (sum 1)
-    double xi[kMaxN];           // Gauss nodes on [-1, 1]
-    double pm[kMaxN];           // phi_a(-1)
-    double pp[kMaxN];           // phi_a(+1)
-};
-
 // Mesh, closure and gravity parameters.
 struct Geo {
     int nx, ny;
@@ -60,25 +49,20 @@ struct StepBlock {
     unsigned int pad;
 };
 
-// host: library-own Gauss-Legendre generator and basis tables
-int make_tables(int n, Tables* t);
-double basis_phi(int a, double x);
-
 // launchers (all asynchronous on `s`)
-hipError_t launch_project(int n, int nvar, const Geo& g, const Tables& T, const double* prim_dev,
-                          double* u_dev, hipStream_t s);
-hipError_t launch_stage(int n, const Geo& g, const Tables& T, const double* u, const double* un,
-                        const double* u0, double* out, const StageCoeffs* sc, hipStream_t s);
+hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim_dev, double* u_dev,
+                          hipStream_t s);
+hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0,
+                        double* out, const StageCoeffs* sc, hipStream_t s);
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
 hipError_t launch_dt(int n, const Geo& g, const double* u, StepBlock* sb, hipStream_t s);
 hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double dt_fixed,
                              double* dt_used_dev, hipStream_t s);
-hipError_t launch_damp(int n, const Geo& g, const Tables& T, double* u, const double* u0,
-                       const int* list, int nlist, const StageCoeffs* sc, hipStream_t s);
-hipError_t launch_torque(int n, const Geo& g, const Tables& T, double t, const double* t_dev,
-                         const double* u, double* partials, int nblocks, double* out,
-                         hipStream_t s);
+hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const int* list, int nlist,
+                       const StageCoeffs* sc, hipStream_t s);
+hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u,
+                         double* partials, int nblocks, double* out, hipStream_t s);
 int torque_blocks(const Geo& g);
 
 }  // namespace dgk

@@ -10,11 +10,13 @@
 // the wavefront has just read (x neighbours: adjacent lanes) or the adjacent
 // row's wavefront reads on the same XCD (y neighbours), so the state crosses
 // HBM once per stage.  Volume integrals are sum-factorised per node column.
+// Quadrature and basis tables are compile-time constants (dg_basis.h).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
 
+#include "dg_basis.h"
 #include "dg_internal.h"
 
 namespace dgk {
@@ -105,17 +107,19 @@ __device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const do
 }
 
 // Edge F (0 west, 1 east, 2 south, 3 north) of element (i, j): own trace from
-// registers, exterior trace from the neighbour's modes (or the initial state
-// at a fixed box edge), Rusanov flux at the n edge Gauss points, lifted into R.
+// the lane's LDS column, exterior trace from the neighbour's modes in global
+// memory (or the initial state at a fixed box edge), Rusanov flux at the n
+// edge Gauss points, lifted into R.
 template <int N, int CL, int F>
-__device__ __forceinline__ void edge_term(const Geo& g, const Tables& T, const double (&U)[NVar<CL>::value][N * N],
+__device__ __forceinline__ void edge_term(const Geo& g, const double* __restrict__ sU,
                                           double (&R)[NVar<CL>::value][N * N], const double* __restrict__ u,
-                                          const double* __restrict__ u0, int i, int j, long long e,
-                                          double xc, double yc) {
+                                          const double* __restrict__ u0, int i, int j, long long e, double xc,
+                                          double yc) {
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int AX = F < 2 ? 0 : 1;
     constexpr int SGN = (F == 0 || F == 2) ? -1 : 1;
+    constexpr BasisTab B = make_basis(N);
     const long long E = g.E;
 
     int in = i + (F == 1) - (F == 0);
@@ -130,42 +134,38 @@ __device__ __forceinline__ void edge_term(const Geo& g, const Tables& T, const d
     const long long en = fixed ? e : (long long)jn * g.nx + in;
     // the neighbour sees the shared edge on its opposite side; a fixed box
     // edge takes the element's own initial trace on the same side
-    const double* sown = SGN < 0 ? T.pm : T.pp;
-    const double* snb = fixed ? sown : (SGN < 0 ? T.pp : T.pm);
+    const bool same_side = fixed;
 
-    double ti[NV][N], to[NV][N];
+    // collapse the normal degree at the edge: ci (own), co (exterior)
+    double ci[NV][N], co[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        double ci[N], co[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            ci[k] = 0.0;
-            co[k] = 0.0;
+            ci[v][k] = 0.0;
+            co[v][k] = 0.0;
         }
 #pragma unroll
         for (int a = 0; a < N; ++a)
 #pragma unroll
             for (int b = 0; b < N; ++b) {
-                const double un = src[(long long)(v * NN + a * N + b) * E + en];
-                if constexpr (AX == 0) {  // collapse the x degree at xi = +-1
-                    ci[b] += sown[a] * U[v][a * N + b];
-                    co[b] += snb[a] * un;
-                } else {  // collapse the y degree at eta = +-1
-                    ci[a] += sown[b] * U[v][a * N + b];
-                    co[a] += snb[b] * un;
+                const int m = v * NN + a * N + b;
+                const double uo = src[(long long)m * E + en];
+                const double ui = sU[m * kWave];
+                // own side value of the collapsed basis function, and the
+                // exterior element's (opposite side unless a fixed box edge)
+                if constexpr (AX == 0) {
+                    const double so = SGN < 0 ? B.pm[a] : B.pp[a];
+                    const double sx = SGN < 0 ? B.pp[a] : B.pm[a];
+                    ci[v][b] += so * ui;
+                    co[v][b] += (same_side ? so : sx) * uo;
+                } else {
+                    const double so = SGN < 0 ? B.pm[b] : B.pp[b];
+                    const double sx = SGN < 0 ? B.pp[b] : B.pm[b];
+                    ci[v][a] += so * ui;
+                    co[v][a] += (same_side ? so : sx) * uo;
                 }
             }
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            double si = 0.0, so = 0.0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                si += ci[m] * T.phi[m][k];
-                so += co[m] * T.phi[m][k];
-            }
-            ti[v][k] = si;
-            to[v][k] = so;
-        }
     }
     double gl[NV][N];
 #pragma unroll
@@ -177,16 +177,22 @@ __device__ __forceinline__ void edge_term(const Geo& g, const Tables& T, const d
         double Ui[NV], Uo[NV], h[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            Ui[v] = ti[v][k];
-            Uo[v] = to[v][k];
+            double si = 0.0, so = 0.0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                si += ci[v][m] * B.phi[m][k];
+                so += co[v][m] * B.phi[m][k];
+            }
+            Ui[v] = si;
+            Uo[v] = so;
         }
-        const double x = AX == 0 ? xc + SGN * 0.5 * g.dx : xc + 0.5 * g.dx * T.xi[k];
-        const double y = AX == 0 ? yc + 0.5 * g.dy * T.xi[k] : yc + SGN * 0.5 * g.dy;
+        const double x = AX == 0 ? xc + SGN * 0.5 * g.dx : xc + 0.5 * g.dx * B.xi[k];
+        const double y = AX == 0 ? yc + 0.5 * g.dy * B.xi[k] : yc + SGN * 0.5 * g.dy;
         rusanov<CL, AX, SGN>(g, Ui, Uo, x, y, h);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < N; ++m) gl[v][m] += T.wh[k] * h[v] * T.phi[m][k];
+            for (int m = 0; m < N; ++m) gl[v][m] += B.wphi[m][k] * h[v];
     }
     const double s = AX == 0 ? g.idx : g.idy;
 #pragma unroll
@@ -195,22 +201,33 @@ __device__ __forceinline__ void edge_term(const Geo& g, const Tables& T, const d
         for (int a = 0; a < N; ++a)
 #pragma unroll
             for (int b = 0; b < N; ++b) {
-                if constexpr (AX == 0)
-                    R[v][a * N + b] -= s * sown[a] * gl[v][b];
-                else
-                    R[v][a * N + b] -= s * sown[b] * gl[v][a];
+                if constexpr (AX == 0) {
+                    const double so = SGN < 0 ? B.pm[a] : B.pp[a];
+                    R[v][a * N + b] -= (s * so) * gl[v][b];
+                } else {
+                    const double so = SGN < 0 ? B.pm[b] : B.pp[b];
+                    R[v][a * N + b] -= (s * so) * gl[v][a];
+                }
             }
 }
 
 // out = a0 u^n + a1 u + a2 L(u, t) for every element (a0 = 0: u^n not read).
 // `un` and `out` may alias (the last SSP stage updates u^n in place; each
 // thread reads and writes only its own element there).
+//
+// One thread per element.  The element's modes are staged in the lane's own
+// column of LDS (no lane reads another lane's column, so no barrier), which
+// keeps the residual R in registers without spilling.  The density residual
+// is the exact modal form of its volume integral, (2/dx) D mx + (2/dy) my D^T
+// with D the Legendre derivative matrix, and is written out first.
 template <int N, int CL>
-__global__ void __launch_bounds__(64) k_stage(const Geo g, const Tables T, const double* __restrict__ u,
-                                              const double* un, const double* __restrict__ u0, double* out,
+__global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restrict__ u, const double* un,
+                                              const double* __restrict__ u0, double* out,
                                               const StageCoeffs* __restrict__ scp) {
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
+    constexpr BasisTab B = make_basis(N);
+    __shared__ double sAll[NV * NN * kWave];
     const int tile = remap_tile(blockIdx.x, g.tiles_total);
     const int j = tile / g.tiles_x;
     const int i = (tile - j * g.tiles_x) * kWave + threadIdx.x;
@@ -218,27 +235,70 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const Tables T, const
     const long long E = g.E;
     const long long e = (long long)j * g.nx + i;
     const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
+    double* sU = sAll + threadIdx.x;  // this lane's column: sU[m * kWave]
 
-    double U[NV][NN], R[NV][NN];
+#pragma unroll
+    for (int m = 0; m < NV * NN; ++m) sU[m * kWave] = u[(long long)m * E + e];
+
+    double R[NV][NN];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int m = 0; m < NN; ++m) {
-            U[v][m] = u[(long long)(v * NN + m) * E + e];
-            R[v][m] = 0.0;
-        }
+        for (int m = 0; m < NN; ++m) R[v][m] = 0.0;
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
 
-    // edge integrals
-    edge_term<N, CL, 0>(g, T, U, R, u, u0, i, j, e, xc, yc);
-    edge_term<N, CL, 1>(g, T, U, R, u, u0, i, j, e, xc, yc);
-    edge_term<N, CL, 2>(g, T, U, R, u, u0, i, j, e, xc, yc);
-    edge_term<N, CL, 3>(g, T, U, R, u, u0, i, j, e, xc, yc);
+    // edge integrals, one edge per iteration of a runtime loop so that the
+    // four edges' neighbour loads and temporaries are never live together
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+        asm volatile("" ::: "memory");
+        if (f == 0)
+            edge_term<N, CL, 0>(g, sU, R, u, u0, i, j, e, xc, yc);
+        else if (f == 1)
+            edge_term<N, CL, 1>(g, sU, R, u, u0, i, j, e, xc, yc);
+        else if (f == 2)
+            edge_term<N, CL, 2>(g, sU, R, u, u0, i, j, e, xc, yc);
+        else
+            edge_term<N, CL, 3>(g, sU, R, u, u0, i, j, e, xc, yc);
+    }
 
-    // volume integrals, one Gauss column xi_q at a time
+    // density: volume term in modal form, then the stage update
 #pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            double sx = 0.0, sy = 0.0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                if (B.D[a][c] != 0.0) sx += B.D[a][c] * sU[(1 * NN + c * N + b) * kWave];
+                if (B.D[b][c] != 0.0) sy += B.D[b][c] * sU[(2 * NN + a * N + c) * kWave];
+            }
+            R[0][a * N + b] += g.rdx2 * sx + g.rdy2 * sy;
+        }
+#pragma unroll
+    for (int m = 0; m < NN; ++m) {
+        const long long idx = (long long)m * E + e;
+        const double base = a1 * sU[m * kWave] + a2 * R[0][m];
+        out[idx] = a0 != 0.0 ? a0 * un[idx] + base : base;
+    }
+
+    // momentum (and energy): volume integrals one Gauss column xi_q at a time
+#pragma unroll 1
     for (int q = 0; q < N; ++q) {
-        const double x = xc + 0.5 * g.dx * T.xi[q];
+        asm volatile("" ::: "memory");
+        double xiq = 0.0, wpq[N], wdpq[N], phq[N];
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq)
+            if (qq == q) {
+                xiq = B.xi[qq];
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    wpq[a] = B.wphi[a][qq];
+                    wdpq[a] = B.wdphi[a][qq];
+                    phq[a] = B.phi[a][qq];
+                }
+            }
+        const double x = xc + 0.5 * g.dx * xiq;
         double c[NV][N];
 #pragma unroll
         for (int v = 0; v < NV; ++v)
@@ -246,12 +306,12 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const Tables T, const
             for (int b = 0; b < N; ++b) {
                 double s = 0.0;
 #pragma unroll
-                for (int a = 0; a < N; ++a) s += T.phi[a][q] * U[v][a * N + b];
+                for (int a = 0; a < N; ++a) s += phq[a] * sU[(v * NN + a * N + b) * kWave];
                 c[v][b] = s;
             }
         double Ax[NV][N], By[NV][N];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+        for (int v = 1; v < NV; ++v)
 #pragma unroll
             for (int b = 0; b < N; ++b) {
                 Ax[v][b] = 0.0;
@@ -264,70 +324,64 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const Tables T, const
             for (int v = 0; v < NV; ++v) {
                 double s = 0.0;
 #pragma unroll
-                for (int b = 0; b < N; ++b) s += c[v][b] * T.phi[b][r];
+                for (int b = 0; b < N; ++b) s += c[v][b] * B.phi[b][r];
                 W[v] = s;
             }
-            const double y = yc + 0.5 * g.dy * T.xi[r];
+            const double y = yc + 0.5 * g.dy * B.xi[r];
             const double inv = 1.0 / W[0];
             double p, cs;
             pressure<CL>(g, W, inv, x, y, p, cs);
             const double vx = W[1] * inv, vy = W[2] * inv;
-            double fx[NV], fy[NV], S[NV];
-            fx[0] = W[1];
-            fy[0] = W[2];
+            double gx, gy;
+            grad_phi(g, x, y, xp, yp, gx, gy);
+            double fx[NV], sy[NV], fy[NV];
             fx[1] = W[1] * vx + p;
             fy[1] = W[1] * vy;
             fx[2] = W[2] * vx;
             fy[2] = W[2] * vy + p;
+            sy[1] = -W[0] * gx;
+            sy[2] = -W[0] * gy;
             if constexpr (NV == 4) {
                 fx[3] = (W[3] + p) * vx;
                 fy[3] = (W[3] + p) * vy;
+                sy[3] = -(W[1] * gx + W[2] * gy);
             }
-            double gx, gy;
-            grad_phi(g, x, y, xp, yp, gx, gy);
-            S[0] = 0.0;
-            S[1] = -W[0] * gx;
-            S[2] = -W[0] * gy;
-            if constexpr (NV == 4) S[3] = -(W[1] * gx + W[2] * gy);
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+            for (int v = 1; v < NV; ++v) {
+                const double fyy = g.rdy2 * fy[v];
 #pragma unroll
                 for (int b = 0; b < N; ++b) {
-                    Ax[v][b] += T.wh[r] * T.phi[b][r] * fx[v];
-                    By[v][b] += T.wh[r] * (g.rdy2 * T.dphi[b][r] * fy[v] + T.phi[b][r] * S[v]);
+                    Ax[v][b] += B.wphi[b][r] * fx[v];
+                    By[v][b] += B.wdphi[b][r] * fyy + B.wphi[b][r] * sy[v];
                 }
+            }
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+        for (int v = 1; v < NV; ++v)
 #pragma unroll
             for (int a = 0; a < N; ++a)
 #pragma unroll
                 for (int b = 0; b < N; ++b)
-                    R[v][a * N + b] += T.wh[q] * (g.rdx2 * T.dphi[a][q] * Ax[v][b] + T.phi[a][q] * By[v][b]);
+                    R[v][a * N + b] += (g.rdx2 * wdpq[a]) * Ax[v][b] + wpq[a] * By[v][b];
     }
 
     // RK stage combination (Shu-Osher form of SSP(3,3)) or plain L(u)
-    if (a0 != 0.0) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+    for (int v = 1; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < NN; ++m) {
-                const long long idx = (long long)(v * NN + m) * E + e;
-                out[idx] = a0 * un[idx] + (a1 * U[v][m] + a2 * R[v][m]);
-            }
-    } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int m = 0; m < NN; ++m) out[(long long)(v * NN + m) * E + e] = a1 * U[v][m] + a2 * R[v][m];
-    }
+        for (int m = 0; m < NN; ++m) {
+            const long long idx = (long long)(v * NN + m) * E + e;
+            const double base = a1 * sU[(v * NN + m) * kWave] + a2 * R[v][m];
+            out[idx] = a0 != 0.0 ? a0 * un[idx] + base : base;
+        }
 }
 
 // ------------------------------------------------------------------ init
 template <int N, int NV>
-__global__ void __launch_bounds__(64) k_project(const Geo g, const Tables T, const double* __restrict__ prim,
+__global__ void __launch_bounds__(64) k_project(const Geo g, const double* __restrict__ prim,
                                                 double* __restrict__ u) {
     constexpr int NN = N * N;
+    constexpr BasisTab T = make_basis(N);
     const long long e = (long long)blockIdx.x * 64 + threadIdx.x;
     if (e >= g.E) return;
     const long long E = g.E;
@@ -443,7 +497,8 @@ __global__ void __launch_bounds__(256) k_dt(const Geo g, int nn, const double* _
 // ------------------------------------------------------------------ damping
 // nodal values of NV variables from modes (sum-factorised)
 template <int N, int NV>
-__device__ __forceinline__ void eval_nodes(const Tables& T, const double (&M)[NV][N * N], double (&W)[NV][N * N]) {
+__device__ __forceinline__ void eval_nodes(const double (&M)[NV][N * N], double (&W)[NV][N * N]) {
+    constexpr BasisTab T = make_basis(N);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -483,9 +538,10 @@ __device__ __forceinline__ double ramp(const Geo& g, double r, double& td) {
 }
 
 template <int N, int CL>
-__global__ void __launch_bounds__(64) k_damp(const Geo g, const Tables T, double* __restrict__ u,
+__global__ void __launch_bounds__(64) k_damp(const Geo g, double* __restrict__ u,
                                              const double* __restrict__ u0, const int* __restrict__ list, int nlist,
                                              const StageCoeffs* __restrict__ scp) {
+    constexpr BasisTab T = make_basis(N);
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     const int idx = blockIdx.x * 64 + threadIdx.x;
@@ -500,12 +556,12 @@ __global__ void __launch_bounds__(64) k_damp(const Geo g, const Tables T, double
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int m = 0; m < NN; ++m) M[v][m] = u0[(long long)(v * NN + m) * E + e];
-    eval_nodes<N, NV>(T, M, W0);
+    eval_nodes<N, NV>(M, W0);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int m = 0; m < NN; ++m) M[v][m] = u[(long long)(v * NN + m) * E + e];
-    eval_nodes<N, NV>(T, M, W);
+    eval_nodes<N, NV>(M, W);
     // nodal increments (written over W)
 #pragma unroll
     for (int q = 0; q < N; ++q)
@@ -583,8 +639,9 @@ __device__ __forceinline__ double block_sum_256(double s, double* red) {
 }
 
 template <int N>
-__global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, const Tables T, double t, const double* t_dev,
+__global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, double t, const double* t_dev,
                                                          const double* __restrict__ u, double* __restrict__ partials) {
+    constexpr BasisTab T = make_basis(N);
     __shared__ double red[4];
     constexpr int NN = N * N;
     const long long e = (long long)blockIdx.x * kTorqueBlock + threadIdx.x;
@@ -596,7 +653,7 @@ __global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, const Tabl
         double M[1][NN], W[1][NN];
 #pragma unroll
         for (int m = 0; m < NN; ++m) M[0][m] = u[(long long)m * g.E + e];
-        eval_nodes<N, 1>(T, M, W);
+        eval_nodes<N, 1>(M, W);
         const int i = (int)(e % g.nx), j = (int)(e / g.nx);
         const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
         const double area = g.dx * g.dy;
@@ -643,21 +700,20 @@ __global__ void __launch_bounds__(kTorqueBlock) k_torque_final(const double* __r
         default: return hipErrorInvalidValue;  \
     }
 
-hipError_t launch_project(int n, int nvar, const Geo& g, const Tables& T, const double* prim, double* u,
-                          hipStream_t s) {
+hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim, double* u, hipStream_t s) {
     const int blocks = (int)((g.E + 63) / 64);
     if (nvar == 4) {
-        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_project<NT, 4>), dim3(blocks), dim3(64), 0, s, g, T, prim, u));
+        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_project<NT, 4>), dim3(blocks), dim3(64), 0, s, g, prim, u));
     } else {
-        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_project<NT, 3>), dim3(blocks), dim3(64), 0, s, g, T, prim, u));
+        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_project<NT, 3>), dim3(blocks), dim3(64), 0, s, g, prim, u));
     }
     return hipGetLastError();
 }
 
-hipError_t launch_stage(int n, const Geo& g, const Tables& T, const double* u, const double* un, const double* u0,
-                        double* out, const StageCoeffs* sc, hipStream_t s) {
+hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0, double* out,
+                        const StageCoeffs* sc, hipStream_t s) {
     DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_stage<NT, CT>), dim3(g.tiles_total), dim3(64), 0,
-                                                                  s, g, T, u, un, u0, out, sc)));
+                                                                  s, g, u, un, u0, out, sc)));
     return hipGetLastError();
 }
 
@@ -679,20 +735,20 @@ hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double 
     return hipGetLastError();
 }
 
-hipError_t launch_damp(int n, const Geo& g, const Tables& T, double* u, const double* u0, const int* list, int nlist,
+hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const int* list, int nlist,
                        const StageCoeffs* sc, hipStream_t s) {
     if (nlist <= 0) return hipSuccess;
     const int blocks = (nlist + 63) / 64;
     DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_damp<NT, CT>), dim3(blocks), dim3(64), 0, s, g,
-                                                                  T, u, u0, list, nlist, sc)));
+                                                                  u, u0, list, nlist, sc)));
     return hipGetLastError();
 }
 
 int torque_blocks(const Geo& g) { return (int)((g.E + kTorqueBlock - 1) / kTorqueBlock); }
 
-hipError_t launch_torque(int n, const Geo& g, const Tables& T, double t, const double* t_dev, const double* u,
-                         double* partials, int nblocks, double* out, hipStream_t s) {
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_torque<NT>), dim3(nblocks), dim3(kTorqueBlock), 0, s, g, T, t, t_dev, u,
+hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, double* partials,
+                         int nblocks, double* out, hipStream_t s) {
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_torque<NT>), dim3(nblocks), dim3(kTorqueBlock), 0, s, g, t, t_dev, u,
                                         partials));
     hipLaunchKernelGGL(k_torque_final, dim3(1), dim3(kTorqueBlock), 0, s, partials, nblocks, out);
     return hipGetLastError();

@@ -65,8 +65,10 @@ CASES = [
     ("disc_p2", W.disc(nx=24, order=3, q=1e-3).replace(ny=20), "disc"),
     ("disc_p4", W.disc(nx=24, order=5, q=1e-3).replace(ny=22), "disc"),
     ("disc_p4_130", W.disc(nx=130, order=5, q=1e-3).replace(ny=6), "disc"),
-    ("ring_p3", W.disc_ring(nx=20, order=4).replace(ny=18), "disc_ring"),
-    ("ring_p1", W.disc_ring(nx=33, order=2).replace(ny=17), "disc_ring"),
+    # the adiabatic ring needs ~0.1 resolution: coarser grids give negative
+    # pressure at edge points in the oracle too
+    ("ring_p3", W.disc_ring(nx=40, order=4), "disc_ring"),
+    ("ring_p1", W.disc_ring(nx=64, order=2).replace(ny=48), "disc_ring"),
 ]
 
 
@@ -91,7 +93,7 @@ def test_projection_and_rhs_parity(name, cfg, kind):
     ("wave_p2", W.wave(nx=70, order=3).replace(ny=9), "wave", 5),
     ("wave_p4", W.wave(nx=40, order=5).replace(ny=12), "wave", 3),
     ("disc_p4_damped", W.disc(nx=26, order=5, q=1e-3), "disc", 3),
-    ("ring_p3", W.disc_ring(nx=20, order=4).replace(ny=18), "disc_ring", 3),
+    ("ring_p3", W.disc_ring(nx=40, order=4), "disc_ring", 3),
 ])
 def test_rk_steps_parity(name, cfg, kind, nsteps):
     T = torch()
