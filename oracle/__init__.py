@@ -16,15 +16,16 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "dg_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "dg_oracle_limiter.c")]
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(
-            os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "dg_oracle.h"))):
+            [os.path.getmtime(f) for f in _SRCS] + [os.path.getmtime(os.path.join(_HERE, "dg_oracle.h"))]):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off",
-                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -71,6 +72,19 @@ def lib():
         _lib.or_torque.argtypes = [cp, C.c_double, P, P]
         _lib.or_torque.restype = C.c_double
         _lib.or_planet_pos.argtypes = [cp, C.c_double, P, P]
+        U8 = C.POINTER(C.c_ubyte)
+        _lib.or_indicator.argtypes = [cp, P, P]
+        _lib.or_minmod.argtypes = [cp, P, P, U8, U8]
+        _lib.or_step_limited.argtypes = [cp, P, C.c_double, C.c_double, P, C.c_double]
+        _lib.or_step_limited.restype = C.c_double
+        _lib.or_mlp_features.argtypes = [cp, P, P, P]
+        _lib.or_bf16.argtypes = [C.c_double]
+        _lib.or_bf16.restype = C.c_double
+        _lib.or_mlp_forward.argtypes = [P, P, C.c_long, C.c_int, P, P, P]
+        _lib.or_mlp_loss_grad.argtypes = [P, P, P, C.c_long, C.c_double, C.c_int, P]
+        _lib.or_mlp_loss_grad.restype = C.c_double
+        _lib.or_adam.argtypes = [P, P, P, P, C.c_long, C.c_long, C.c_double, C.c_double, C.c_double,
+                                 C.c_double]
     return _lib
 
 
@@ -216,3 +230,68 @@ def planet_pos(c, t):
     y = C.c_double()
     lib().or_planet_pos(C.byref(c), float(t), C.byref(x), C.byref(y))
     return x.value, y.value
+
+
+# ---------------------------------------------------------------- troubled cells
+MLP_NPARAM = 3169
+
+
+def _u8(a):
+    return a.ctypes.data_as(C.POINTER(C.c_ubyte))
+
+
+def indicator(c, u):
+    s = np.zeros(n_elem(c))
+    lib().or_indicator(C.byref(c), _p(_f64(u)), _p(s))
+    return s
+
+
+def minmod(c, u, u0, flags):
+    """returns (limited u, changed mask)"""
+    u = _f64(u).copy()
+    fl = np.ascontiguousarray(flags, dtype=np.uint8)
+    ch = np.zeros(n_elem(c), dtype=np.uint8)
+    lib().or_minmod(C.byref(c), _p(u), _p(_f64(u0)), _u8(fl), _u8(ch))
+    return u, ch.astype(bool)
+
+
+def step_limited(c, u, t, dt_fixed, u0, s0):
+    u = _f64(u).copy()
+    d = lib().or_step_limited(C.byref(c), _p(u), float(t), float(dt_fixed), _p(_f64(u0)), float(s0))
+    return u, d
+
+
+def mlp_features(c, u, scale):
+    f = np.zeros((n_elem(c), c.nvar * c.n * c.n))
+    lib().or_mlp_features(C.byref(c), _p(_f64(u)), _p(_f64(scale)), _p(f))
+    return f
+
+
+def bf16(x):
+    return lib().or_bf16(float(x))
+
+
+def mlp_forward(par, x, bf16=True):
+    x = _f64(x)
+    nb = x.shape[0]
+    z = np.zeros(nb)
+    h1 = np.zeros((nb, 32))
+    h2 = np.zeros((nb, 32))
+    lib().or_mlp_forward(_p(_f64(par)), _p(x), nb, int(bf16), _p(z), _p(h1), _p(h2))
+    return z, h1, h2
+
+
+def mlp_loss_grad(par, x, y, pos_weight=1.0, bf16=True):
+    x = _f64(x)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().or_mlp_loss_grad(_p(_f64(par)), _p(x), _p(_f64(y)), x.shape[0], float(pos_weight),
+                                  int(bf16), _p(g))
+    return loss, g
+
+
+def adam(par, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    par = _f64(par).copy()
+    m = _f64(m).copy()
+    v = _f64(v).copy()
+    lib().or_adam(_p(par), _p(_f64(grad)), _p(m), _p(v), par.size, int(t), lr, b1, b2, eps)
+    return par, m, v

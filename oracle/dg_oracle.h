@@ -81,6 +81,48 @@ double or_torque(const or_cfg *c, double t, const double *u, double *sum_abs);
 /* planet position at time t */
 void or_planet_pos(const or_cfg *c, double t, double *xp, double *yp);
 
+/* ---- troubled cells: plain indicator, minmod limiter, learned indicator ---- */
+
+/* modal-decay smoothness of the density of every element:
+ * s[e] = log10( sum_{max(a,b) = N_p} u_ab^2 / sum_ab u_ab^2 ) (Parseval, the
+ * basis is orthonormal); -300 for an all-zero element */
+void or_indicator(const or_cfg *c, const double *u, double *s);
+/* Cockburn-Shu TVD minmod limiter on the linear modes of the flagged elements
+ * (flag[e] != 0), component-wise on the conservative variables, with the
+ * neighbour means (exterior mean = own initial mean at a fixed box edge, from
+ * u0).  An element whose slopes change in any variable keeps its means, takes
+ * the limited slopes and drops every other mode; changed[e] = 1 then. */
+void or_minmod(const or_cfg *c, double *u, const double *u0, const unsigned char *flag,
+               unsigned char *changed);
+/* one SSP-RK3 step in Shu-Osher form with the limiter after every stage
+ * (flags from or_indicator > s0); returns dt */
+double or_step_limited(const or_cfg *c, double *u, double t, double dt_fixed, const double *u0,
+                       double s0);
+
+/* learned indicator: 64 -> 32 -> 32 -> 1 MLP, ReLU hidden, sigmoid output.
+ * Parameters (FP32 master values held as doubles), flat:
+ * W1[32][64], b1[32], W2[32][32], b2[32], w3[32], b3[1]  (3169 values). */
+#define OR_MLP_NPARAM 3169
+/* features f[e][v*n*n + m] = u_vm / (|u_v00| + scale[v]) */
+void or_mlp_features(const or_cfg *c, const double *u, const double *scale, double *f);
+/* round to the nearest bfloat16 (ties to even), returned as a double */
+double or_bf16(double x);
+/* forward pass of nb samples x[nb][64]: with bf16 != 0 the weights, inputs
+ * and hidden activations are rounded to bfloat16 before each product and the
+ * pre-activations to float32 (the kernel's precision) before rounding; z
+ * receives the logits.  h1, h2 (nb x 32, may be NULL) receive the hidden
+ * activations as fed to the next layer. */
+void or_mlp_forward(const double *par, const double *x, long nb, int bf16, double *z, double *h1,
+                    double *h2);
+/* BCE-with-logits loss, mean over the batch, positives weighted by pos_weight;
+ * grad (3169 values) receives d loss / d params, back-propagated through the
+ * forward values of or_mlp_forward (the rounding treated as identity) */
+double or_mlp_loss_grad(const double *par, const double *x, const double *y, long nb,
+                        double pos_weight, int bf16, double *grad);
+/* Adam update (Kingma & Ba 2015) in place: m, v moments, step t >= 1 */
+void or_adam(double *par, const double *grad, double *m, double *v, long n, long t, double lr,
+             double b1, double b2, double eps);
+
 #ifdef __cplusplus
 }
 #endif
