@@ -64,6 +64,7 @@ typedef struct dg_config {
     double rd_in, rd_out;
     double cfl;           /* C of the CFL condition (Sec. 2.3) */
     int precision;        /* DG_PRECISION_* */
+    double sigma0;        /* deviation form: equilibrium disc Sigma0 (see dg_init) */
     int limiter;          /* DG_LIMITER_* */
     double limiter_s0;    /* modal-decay threshold on log10 of the top-mode energy share */
     double mlp_theta;     /* learned indicator: flag when sigmoid output > theta */
@@ -80,13 +81,24 @@ int dg_get_nodes(const dg_config *cfg, double *x_host, double *y_host);
  * [var][e][node], host memory read during the call only.  The projected modes
  * are written to the caller's device array u0_dev (layout above) on
  * hip_stream (a hipStream_t; NULL = default stream), and the library keeps its
- * own copy as the fixed exterior state and the damping target.  With
- * precision DG_PRECISION_MIXED, eq_prim_nodes_host gives the equilibrium
- * primitive state that the deviation form expands about (NULL: the initial
- * state); u0_dev then receives the full state u as in FP64 mode.  The handle
- * owns all workspace it allocates; dg_free releases it. */
-int dg_init(const dg_config *cfg, const double *prim_nodes_host, const double *eq_prim_nodes_host,
-            double *u0_dev, void *hip_stream, dg_handle **out);
+ * own copy as the fixed exterior state and the damping target.  The handle
+ * owns all workspace it allocates; dg_free releases it.
+ *
+ * Deviation form (precision DG_PRECISION_MIXED; locally isothermal disc with
+ * stellar gravity only): the state is written as u = u_eq + du about the
+ * rotational equilibrium of the disc set-up (Sec. 5.1 with the readings of
+ * the Sigma profile and harmonic core: Sigma = sigma0 max(r, r_core)^(-1/2),
+ * v_phi^2 = r dPhi_star/dr + (r/Sigma) d(c_s^2 Sigma)/dr), projected in FP64 by the
+ * library.  Every state array of the handle (u0_dev, the u_dev of dg_rhs,
+ * dg_rk_step, dg_torque) then holds the FP64 deviation du, and dg_rhs returns
+ * L(u_eq + du); dg_full_state reconstructs u.  The right-hand side is
+ * L(u_eq) (FP64, computed once, kept in FP32) plus the deviation part in FP32. */
+int dg_init(const dg_config *cfg, const double *prim_nodes_host, double *u0_dev, void *hip_stream,
+            dg_handle **out);
+
+/* Deviation form only: full = u_eq + dev (device arrays, state layout; they
+ * may alias).  FP64 mode: full = dev. */
+int dg_full_state(dg_handle *h, const double *dev_dev, double *full_dev);
 
 /* Right-hand side of eq. (3), rhs = L(u) at time t (planet at its position
  * at t), without limiter or damping.  u_dev, rhs_dev: device arrays in the

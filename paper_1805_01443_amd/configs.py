@@ -18,7 +18,7 @@ import numpy as np
 
 from . import synth
 from .dg import (BC_FIXED_INITIAL, BC_PERIODIC, CLOSURE_ADIABATIC, CLOSURE_ISOTHERMAL,
-                 CLOSURE_LOCALLY_ISOTHERMAL, Config, dg_get_nodes)
+                 CLOSURE_LOCALLY_ISOTHERMAL, PRECISION_MIXED, Config, dg_get_nodes)
 
 
 def wave(nx=64, order=3):
@@ -35,6 +35,12 @@ def disc(nx=512, order=5, q=1e-5, h=0.05):
 
 def disc_sweep(nx=1024, order=5):
     return disc(nx=nx, order=order, q=3e-5)
+
+
+def disc_mixed(nx=1024, order=5, seed=0, q=3e-5):
+    """The sweep disc in the mixed-precision deviation form about the
+    equilibrium with the seed's Sigma0."""
+    return disc(nx=nx, order=order, q=q).replace(precision=PRECISION_MIXED, sigma0=sigma0_of(seed))
 
 
 def disc_ring(nx=1024, order=4):

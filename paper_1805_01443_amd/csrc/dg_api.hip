@@ -24,7 +24,11 @@ struct dg_handle {
     Geo g{};
     hipStream_t s = nullptr;
     int device = 0;
-    double* u0 = nullptr;   // initial modes: fixed exterior state and damping target
+    double* u0 = nullptr;   // initial modes (full state): fixed exterior state and damping target
+    bool dev = false;       // deviation form (DG_PRECISION_MIXED)
+    double* eq = nullptr;   // deviation form: projected equilibrium u_eq (FP64)
+    double* du0 = nullptr;  // deviation form: initial deviation (fixed exterior state)
+    float* leq = nullptr;   // deviation form: L(u_eq) without the planet, FP32
     double* ws1 = nullptr;  // SSP stage states u^(1), u^(2)
     double* ws2 = nullptr;
     StageCoeffs* sc_rhs = nullptr;
@@ -80,7 +84,12 @@ int validate(const dg_config* c, std::string* why) {
     if (c->damping && !(c->rd_in >= 0 && c->rd_out > c->rd_in && c->gm > 0))
         return (*why = "damping needs 0 <= rd_in < rd_out and gm > 0", DG_EINVAL);
     if (!(c->cfl > 0)) return (*why = "cfl must be > 0", DG_EINVAL);
-    if (c->precision != DG_PRECISION_FP64) return (*why = "only FP64 precision is built", DG_EUNSUPPORTED);
+    if (c->precision != DG_PRECISION_FP64 && c->precision != DG_PRECISION_MIXED)
+        return (*why = "unknown precision", DG_EINVAL);
+    if (c->precision == DG_PRECISION_MIXED &&
+        !(c->closure == DG_CLOSURE_LOCALLY_ISOTHERMAL && c->star && c->sigma0 > 0))
+        return (*why = "the deviation form is built for the locally isothermal disc with stellar gravity and sigma0 > 0",
+                DG_EUNSUPPORTED);
     if (c->limiter != DG_LIMITER_NONE) return (*why = "limiters are not built", DG_EUNSUPPORTED);
     return DG_OK;
 }
@@ -124,7 +133,9 @@ void make_geo(const dg_config* c, Geo* g) {
     g->td_in = c->gm > 0 ? 2.0 * pi * std::sqrt(c->rd_in * c->rd_in * c->rd_in / c->gm) : 0.0;
     g->td_out = c->gm > 0 ? 2.0 * pi * std::sqrt(c->rd_out * c->rd_out * c->rd_out / c->gm) : 0.0;
     g->cfl_fac = c->cfl / (2.0 * (c->order - 1) + 1.0);
+    g->sigma0 = c->sigma0;
 }
+
 
 void host_nodes(const dg_config* c, std::vector<double>* x, std::vector<double>* y) {
     const int n = c->order;
@@ -161,9 +172,30 @@ hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, c
         e = hipEventRecord(a, h->s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, h->s);
+    hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, out, sc, h->s)
+                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, h->s);
     if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
     return e;
+}
+
+// primitive node values of the disc's rotational equilibrium (reading of the
+// Sec. 5.1 set-up: Sigma = sigma0 max(r, r_core)^(-1/2), locally isothermal
+// pressure, harmonic stellar core), layout [var][e][node]
+void equilibrium_prim(const dg_config* c, std::vector<double>* prim) {
+    std::vector<double> x, y;
+    host_nodes(c, &x, &y);
+    const size_t M = x.size();
+    prim->assign(3 * M, 0.0);
+    for (size_t k = 0; k < M; ++k) {
+        const double r = std::sqrt(x[k] * x[k] + y[k] * y[k]);
+        const double rr = r > c->r_core ? r : c->r_core;
+        const double om2 = r < c->r_core ? c->gm / (c->r_core * c->r_core * c->r_core)
+                                         : c->gm * (1.0 - 1.5 * c->h * c->h) / (r * r * r);
+        const double om = std::sqrt(om2);
+        (*prim)[k] = c->sigma0 / std::sqrt(rr);
+        (*prim)[M + k] = -om * y[k];
+        (*prim)[2 * M + k] = om * x[k];
+    }
 }
 
 void release(dg_handle* h) {
@@ -176,7 +208,11 @@ void release(dg_handle* h) {
     (void)hipFree(h->sb);
     (void)hipFree(h->damp_list);
     (void)hipFree(h->tq_part);
-    h->u0 = h->ws1 = h->ws2 = nullptr;
+    (void)hipFree(h->eq);
+    (void)hipFree(h->du0);
+    (void)hipFree(h->leq);
+    h->u0 = h->ws1 = h->ws2 = h->eq = h->du0 = nullptr;
+    h->leq = nullptr;
 }
 
 }  // namespace
@@ -195,9 +231,7 @@ int dg_get_nodes(const dg_config* cfg, double* x_host, double* y_host) {
     return DG_OK;
 }
 
-int dg_init(const dg_config* cfg, const double* prim_nodes_host, const double* eq_prim_nodes_host, double* u0_dev,
-            void* hip_stream, dg_handle** out) {
-    (void)eq_prim_nodes_host;
+int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev, void* hip_stream, dg_handle** out) {
     if (!out) return fail(nullptr, DG_EINVAL, "out is NULL");
     *out = nullptr;
     std::string why;
@@ -212,6 +246,7 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, const double* e
     h->nvar = cfg->nvar;
     h->E = (long long)cfg->nx * cfg->ny;
     h->s = (hipStream_t)hip_stream;
+    h->dev = cfg->precision == DG_PRECISION_MIXED;
     make_geo(cfg, &h->g);
 
     auto bail = [&](int code) {
@@ -239,6 +274,11 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, const double* e
     h->tq_blocks = dgk::torque_blocks(h->g);
     DG_ALLOC(h->tq_part, sizeof(double) * (size_t)h->tq_blocks);
     DG_ALLOC(prim_dev, state_bytes);
+    if (h->dev) {
+        DG_ALLOC(h->eq, state_bytes);
+        DG_ALLOC(h->du0, state_bytes);
+        DG_ALLOC(h->leq, state_bytes / 2);
+    }
 
     // damped elements: any volume node with a non-zero ramp
     if (cfg->damping) {
@@ -284,7 +324,9 @@ int dg_rhs(dg_handle* h, double t, const double* u_dev, double* rhs_dev) {
     if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
     if (!u_dev || !rhs_dev || u_dev == rhs_dev) return fail(h, DG_EINVAL, "u_dev and rhs_dev must be distinct device arrays");
     DG_HIP(h, dgk::launch_set_coeffs(h->sc_rhs, h->g, t, 0.0, 0.0, 1.0, h->s), "dg_rhs coefficients");
-    DG_HIP(h, dgk::launch_stage(h->n, h->g, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, h->s), "dg_rhs stage");
+    DG_HIP(h, h->dev ? dgk::launch_stage_dev(h->n, h->g, u_dev, nullptr, h->du0, h->leq, rhs_dev, h->sc_rhs, h->s)
+                     : dgk::launch_stage(h->n, h->g, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, h->s),
+           "dg_rhs stage");
     return DG_OK;
 }
 
@@ -293,13 +335,13 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     if (!u_dev || !t_dev) return fail(h, DG_EINVAL, "u_dev and t_dev are required");
     if (!(dt_fixed == dt_fixed)) return fail(h, DG_EINVAL, "dt_fixed is NaN");
     StepBlock* sb = h->sb;
-    DG_HIP(h, dgk::launch_dt(h->n, h->g, u_dev, sb, h->s), "CFL reduction");
+    DG_HIP(h, dgk::launch_dt(h->n, h->g, u_dev, h->eq, sb, h->s), "CFL reduction");
     DG_HIP(h, dgk::launch_step_begin(h->g, sb, t_dev, dt_fixed, dt_used_dev, h->s), "step begin");
     DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
     DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1]), "stage 2");
     DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2]), "stage 3");
     if (h->cfg.damping)
-        DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->damp_list, h->ndamp, &sb->st[0], h->s),
+        DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
                "damping");
     return DG_OK;
 }
@@ -307,8 +349,20 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
 int dg_torque(dg_handle* h, double t, const double* t_dev, const double* u_dev, double* torque_dev) {
     if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
     if (!u_dev || !torque_dev) return fail(h, DG_EINVAL, "u_dev and torque_dev are required");
-    DG_HIP(h, dgk::launch_torque(h->n, h->g, t, t_dev, u_dev, h->tq_part, h->tq_blocks, torque_dev, h->s),
+    DG_HIP(h, dgk::launch_torque(h->n, h->g, t, t_dev, u_dev, h->eq, h->tq_part, h->tq_blocks, torque_dev, h->s),
            "torque");
+    return DG_OK;
+}
+
+int dg_full_state(dg_handle* h, const double* dev_dev, double* full_dev) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    if (!dev_dev || !full_dev) return fail(h, DG_EINVAL, "NULL state");
+    const long long ns = (long long)h->nvar * h->n * h->n * h->E;
+    if (h->dev) {
+        DG_HIP(h, dgk::launch_add_state(h->eq, dev_dev, full_dev, 1.0, ns, h->s), "full state");
+    } else if (dev_dev != full_dev) {
+        DG_HIP(h, hipMemcpyAsync(full_dev, dev_dev, sizeof(double) * ns, hipMemcpyDeviceToDevice, h->s), "copy");
+    }
     return DG_OK;
 }
 

@@ -30,6 +30,7 @@ struct Geo {
     int damping;
     double rd_in, rd_out, rb_in, rb_out, td_in, td_out;
     double cfl_fac;             // C / (2 N_p + 1)
+    double sigma0;              // deviation form: equilibrium Sigma0
 };
 
 // Per-stage coefficients: out = a0 * u^n + a1 * u + a2 * L(u, t)
@@ -56,13 +57,18 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
                         double* out, const StageCoeffs* sc, hipStream_t s);
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
-hipError_t launch_dt(int n, const Geo& g, const double* u, StepBlock* sb, hipStream_t s);
+hipError_t launch_dt(int n, const Geo& g, const double* u, const double* eq, StepBlock* sb, hipStream_t s);
 hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double dt_fixed,
                              double* dt_used_dev, hipStream_t s);
-hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const int* list, int nlist,
-                       const StageCoeffs* sc, hipStream_t s);
-hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u,
+hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const double* eq, const int* list,
+                       int nlist, const StageCoeffs* sc, hipStream_t s);
+hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,
                          double* partials, int nblocks, double* out, hipStream_t s);
+hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double* dun, const double* du0,
+                            const float* leq, double* out, const StageCoeffs* sc, hipStream_t s);
+hipError_t launch_add_state(const double* a, const double* b, double* out, double sign, long long n,
+                            hipStream_t s);
+hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
 int torque_blocks(const Geo& g);
 
 }  // namespace dgk

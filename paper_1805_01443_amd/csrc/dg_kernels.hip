@@ -28,6 +28,30 @@ struct NVar {
     static constexpr int value = CL == CL_ADI ? 4 : 3;
 };
 
+// State arrays are read and written through buffer resources: the array base
+// lives in scalar registers, a mode plane is a scalar offset and the lane's
+// element is one shared 32-bit vector offset.  (With plain pointers the
+// compiler keeps a private 64-bit address per mode plane alive from the loads
+// to the stores, which alone costs ~150 registers at order 5.)  Byte offsets
+// are 32-bit: a state array is at most 4 GiB, checked at init.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base) {
+    // raw buffer, no swizzle; range checking is not relied on (all accesses
+    // are in bounds by construction)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ double ld64(rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, (int)soff, 0));
+}
+__device__ __forceinline__ float ld32(rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, (int)soff, 0));
+}
+__device__ __forceinline__ void st64(rsrc_t r, unsigned voff, unsigned soff, double v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, (int)soff, 0);
+}
+
 // Blocks are dealt to the 8 XCDs round-robin (block b on XCD b % 8).  Give
 // each XCD a contiguous band of tiles, so the rows above and below a tile are
 // being read through the same L2.
@@ -112,9 +136,8 @@ __device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const do
 // edge Gauss points, lifted into R.
 template <int N, int CL, int F>
 __device__ __forceinline__ void edge_term(const Geo& g, const double* __restrict__ sU,
-                                          double (&R)[NVar<CL>::value][N * N], const double* __restrict__ u,
-                                          const double* __restrict__ u0, int i, int j, long long e, double xc,
-                                          double yc) {
+                                          double (&R)[NVar<CL>::value][N * N], rsrc_t ru, rsrc_t ru0, int i, int j,
+                                          long long e, double xc, double yc) {
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int AX = F < 2 ? 0 : 1;
@@ -130,8 +153,10 @@ __device__ __forceinline__ void edge_term(const Geo& g, const double* __restrict
     if (jn < 0) jn += g.ny;
     if (jn >= g.ny) jn -= g.ny;
     const bool fixed = outside && g.bc == 1;
-    const double* src = fixed ? u0 : u;
-    const long long en = fixed ? e : (long long)jn * g.nx + in;
+    const bool wave_fixed = __any(fixed);  // only box-edge waves read the initial state
+    const unsigned eoff = (unsigned)e * 8u;
+    const unsigned noff = ((unsigned)jn * (unsigned)g.nx + (unsigned)in) * 8u;
+    const unsigned pstride = (unsigned)E * 8u;
     // the neighbour sees the shared edge on its opposite side; a fixed box
     // edge takes the element's own initial trace on the same side
     const bool same_side = fixed;
@@ -150,7 +175,11 @@ __device__ __forceinline__ void edge_term(const Geo& g, const double* __restrict
 #pragma unroll
             for (int b = 0; b < N; ++b) {
                 const int m = v * NN + a * N + b;
-                const double uo = src[(long long)m * E + en];
+                double uo = ld64(ru, noff, (unsigned)m * pstride);
+                if (wave_fixed) {
+                    const double u0v = ld64(ru0, eoff, (unsigned)m * pstride);
+                    uo = fixed ? u0v : uo;
+                }
                 const double ui = sU[m * kWave];
                 // own side value of the collapsed basis function, and the
                 // exterior element's (opposite side unless a fixed box edge)
@@ -172,27 +201,40 @@ __device__ __forceinline__ void edge_term(const Geo& g, const double* __restrict
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int m = 0; m < N; ++m) gl[v][m] = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < N; ++k) {
+        // tables at edge point k, selected at run time so they live only here
+        double phk[N], wpk[N];
+        double xik = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < N; ++kk)
+            if (kk == k) {
+                xik = B.xi[kk];
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    phk[m] = B.phi[m][kk];
+                    wpk[m] = B.wphi[m][kk];
+                }
+            }
         double Ui[NV], Uo[NV], h[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             double si = 0.0, so = 0.0;
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                si += ci[v][m] * B.phi[m][k];
-                so += co[v][m] * B.phi[m][k];
+                si += ci[v][m] * phk[m];
+                so += co[v][m] * phk[m];
             }
             Ui[v] = si;
             Uo[v] = so;
         }
-        const double x = AX == 0 ? xc + SGN * 0.5 * g.dx : xc + 0.5 * g.dx * B.xi[k];
-        const double y = AX == 0 ? yc + 0.5 * g.dy * B.xi[k] : yc + SGN * 0.5 * g.dy;
+        const double x = AX == 0 ? xc + SGN * 0.5 * g.dx : xc + 0.5 * g.dx * xik;
+        const double y = AX == 0 ? yc + 0.5 * g.dy * xik : yc + SGN * 0.5 * g.dy;
         rusanov<CL, AX, SGN>(g, Ui, Uo, x, y, h);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < N; ++m) gl[v][m] += B.wphi[m][k] * h[v];
+            for (int m = 0; m < N; ++m) gl[v][m] += wpk[m] * h[v];
     }
     const double s = AX == 0 ? g.idx : g.idy;
 #pragma unroll
@@ -236,9 +278,11 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restr
     const long long e = (long long)j * g.nx + i;
     const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
     double* sU = sAll + threadIdx.x;  // this lane's column: sU[m * kWave]
+    const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), rout = make_rsrc(out), run = make_rsrc(un);
+    const unsigned eoff = (unsigned)e * 8u, pstride = (unsigned)E * 8u;
 
 #pragma unroll
-    for (int m = 0; m < NV * NN; ++m) sU[m * kWave] = u[(long long)m * E + e];
+    for (int m = 0; m < NV * NN; ++m) sU[m * kWave] = ld64(ru, eoff, (unsigned)m * pstride);
 
     double R[NV][NN];
 #pragma unroll
@@ -253,13 +297,13 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restr
     for (int f = 0; f < 4; ++f) {
         asm volatile("" ::: "memory");
         if (f == 0)
-            edge_term<N, CL, 0>(g, sU, R, u, u0, i, j, e, xc, yc);
+            edge_term<N, CL, 0>(g, sU, R, ru, ru0, i, j, e, xc, yc);
         else if (f == 1)
-            edge_term<N, CL, 1>(g, sU, R, u, u0, i, j, e, xc, yc);
+            edge_term<N, CL, 1>(g, sU, R, ru, ru0, i, j, e, xc, yc);
         else if (f == 2)
-            edge_term<N, CL, 2>(g, sU, R, u, u0, i, j, e, xc, yc);
+            edge_term<N, CL, 2>(g, sU, R, ru, ru0, i, j, e, xc, yc);
         else
-            edge_term<N, CL, 3>(g, sU, R, u, u0, i, j, e, xc, yc);
+            edge_term<N, CL, 3>(g, sU, R, ru, ru0, i, j, e, xc, yc);
     }
 
     // density: volume term in modal form, then the stage update
@@ -277,9 +321,9 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restr
         }
 #pragma unroll
     for (int m = 0; m < NN; ++m) {
-        const long long idx = (long long)m * E + e;
+        const unsigned po = (unsigned)m * pstride;
         const double base = a1 * sU[m * kWave] + a2 * R[0][m];
-        out[idx] = a0 != 0.0 ? a0 * un[idx] + base : base;
+        st64(rout, eoff, po, a0 != 0.0 ? a0 * ld64(run, eoff, po) + base : base);
     }
 
     // momentum (and energy): volume integrals one Gauss column xi_q at a time
@@ -370,10 +414,347 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restr
     for (int v = 1; v < NV; ++v)
 #pragma unroll
         for (int m = 0; m < NN; ++m) {
-            const long long idx = (long long)(v * NN + m) * E + e;
+            const unsigned po = (unsigned)(v * NN + m) * pstride;
             const double base = a1 * sU[(v * NN + m) * kWave] + a2 * R[v][m];
-            out[idx] = a0 != 0.0 ? a0 * un[idx] + base : base;
+            st64(rout, eoff, po, a0 != 0.0 ? a0 * ld64(run, eoff, po) + base : base);
         }
+}
+
+// ------------------------------------------------------------------ deviation form
+// u = u_eq + du about the disc's rotational equilibrium (locally isothermal,
+// stellar harmonic core inside r_core).  The FP64 state du is converted to
+// FP32 on load; contractions, fluxes and the lift run in FP32 on the
+// deviation; L = L(u_eq) (FP64, precomputed, stored FP32) + dL, and the stage
+// combination is FP64.  Deviation fluxes are written without cancellation:
+// with the equilibrium velocity v and w = dm - v drho,
+//   d(m_a m_b / rho) = v_a v_b drho + v_a w_b + v_b w_a + w_a w_b / (rho + drho).
+struct EqPoint {
+    float rho, vx, vy, c2;
+};
+
+__device__ __forceinline__ EqPoint eq_at(const Geo& g, double xd, double yd) {
+    const float x = (float)xd, y = (float)yd;
+    const float r = sqrtf(x * x + y * y);
+    const float rr = fmaxf(r, (float)g.r_core);
+    EqPoint q;
+    q.rho = (float)g.sigma0 * rsqrtf(rr);
+    q.c2 = (float)g.h2gm / rr;
+    const float om2 = r < (float)g.r_core ? (float)g.rc3inv : (float)(g.gm * (1.0 - 1.5 * g.h2gm / g.gm)) / (r * r * r);
+    const float om = sqrtf(om2);
+    q.vx = -om * y;
+    q.vy = om * x;
+    return q;
+}
+
+// deviation flux along axis AX (0: f_x, 1: f_y) of the deviation d = (drho, dmx, dmy)
+template <int AX>
+__device__ __forceinline__ void dflux(const EqPoint& q, const float* d, float inv1, float* f) {
+    const float wx = d[1] - q.vx * d[0], wy = d[2] - q.vy * d[0];
+    const float dxy = q.vx * q.vy * d[0] + q.vx * wy + q.vy * wx + wx * wy * inv1;
+    if constexpr (AX == 0) {
+        f[0] = d[1];
+        f[1] = q.vx * q.vx * d[0] + 2.0f * q.vx * wx + wx * wx * inv1 + q.c2 * d[0];
+        f[2] = dxy;
+    } else {
+        f[0] = d[2];
+        f[1] = dxy;
+        f[2] = q.vy * q.vy * d[0] + 2.0f * q.vy * wy + wy * wy * inv1 + q.c2 * d[0];
+    }
+}
+
+// normal velocity of the full state along SGN * e_AX
+template <int AX, int SGN>
+__device__ __forceinline__ float vnorm(const EqPoint& q, const float* d, float inv1) {
+    const float v = AX == 0 ? q.vx + (d[1] - q.vx * d[0]) * inv1 : q.vy + (d[2] - q.vy * d[0]) * inv1;
+    return SGN * v;
+}
+
+template <int N, int F>
+__device__ __forceinline__ void edge_term_dev(const Geo& g, const float* __restrict__ sD, float (&R)[3][N * N],
+                                              rsrc_t rdu, rsrc_t rdu0, int i, int j, long long e, double xc,
+                                              double yc) {
+    constexpr int NN = N * N;
+    constexpr int AX = F < 2 ? 0 : 1;
+    constexpr int SGN = (F == 0 || F == 2) ? -1 : 1;
+    constexpr BasisTab B = make_basis(N);
+    const long long E = g.E;
+    int in = i + (F == 1) - (F == 0);
+    int jn = j + (F == 3) - (F == 2);
+    const bool outside = in < 0 || in >= g.nx || jn < 0 || jn >= g.ny;
+    if (in < 0) in += g.nx;
+    if (in >= g.nx) in -= g.nx;
+    if (jn < 0) jn += g.ny;
+    if (jn >= g.ny) jn -= g.ny;
+    const bool fixed = outside && g.bc == 1;
+    const bool wave_fixed = __any(fixed);
+    const unsigned eoff = (unsigned)e * 8u;
+    const unsigned noff = ((unsigned)jn * (unsigned)g.nx + (unsigned)in) * 8u;
+    const unsigned pstride = (unsigned)E * 8u;
+    float ci[3][N], co[3][N];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            ci[v][k] = 0.0f;
+            co[v][k] = 0.0f;
+        }
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                const int m = v * NN + a * N + b;
+                double uod = ld64(rdu, noff, (unsigned)m * pstride);
+                if (wave_fixed) {
+                    const double u0v = ld64(rdu0, eoff, (unsigned)m * pstride);
+                    uod = fixed ? u0v : uod;
+                }
+                const float uo = (float)uod;
+                const float ui = sD[m * kWave];
+                if constexpr (AX == 0) {
+                    const float so = (float)(SGN < 0 ? B.pm[a] : B.pp[a]);
+                    const float sx = (float)(SGN < 0 ? B.pp[a] : B.pm[a]);
+                    ci[v][b] += so * ui;
+                    co[v][b] += (fixed ? so : sx) * uo;
+                } else {
+                    const float so = (float)(SGN < 0 ? B.pm[b] : B.pp[b]);
+                    const float sx = (float)(SGN < 0 ? B.pp[b] : B.pm[b]);
+                    ci[v][a] += so * ui;
+                    co[v][a] += (fixed ? so : sx) * uo;
+                }
+            }
+    }
+    float gl[3][N];
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < N; ++m) gl[v][m] = 0.0f;
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+        // tables at edge point k, selected at run time so they live only here
+        float phk[N], wpk[N];
+        double xik = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < N; ++kk)
+            if (kk == k) {
+                xik = B.xi[kk];
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    phk[m] = (float)B.phi[m][kk];
+                    wpk[m] = (float)B.wphi[m][kk];
+                }
+            }
+        float di[3], dd[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            float si = 0.0f, so = 0.0f;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                si += ci[v][m] * phk[m];
+                so += co[v][m] * phk[m];
+            }
+            di[v] = si;
+            dd[v] = so;
+        }
+        const double x = AX == 0 ? xc + SGN * 0.5 * g.dx : xc + 0.5 * g.dx * xik;
+        const double y = AX == 0 ? yc + 0.5 * g.dy * xik : yc + SGN * 0.5 * g.dy;
+        const EqPoint q = eq_at(g, x, y);
+        const float ii = 1.0f / (q.rho + di[0]), io = 1.0f / (q.rho + dd[0]);
+        float fi[3], fo[3];
+        dflux<AX>(q, di, ii, fi);
+        dflux<AX>(q, dd, io, fo);
+        const float c = sqrtf(q.c2);
+        const float alpha = fmaxf(fabsf(vnorm<AX, SGN>(q, di, ii)), fabsf(vnorm<AX, SGN>(q, dd, io))) + c;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const float h = 0.5f * SGN * (fi[v] + fo[v]) - 0.5f * alpha * (dd[v] - di[v]);
+#pragma unroll
+            for (int m = 0; m < N; ++m) gl[v][m] += wpk[m] * h;
+        }
+    }
+    const float s = (float)(AX == 0 ? g.idx : g.idy);
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                if constexpr (AX == 0) {
+                    const float so = (float)(SGN < 0 ? B.pm[a] : B.pp[a]);
+                    R[v][a * N + b] -= (s * so) * gl[v][b];
+                } else {
+                    const float so = (float)(SGN < 0 ? B.pm[b] : B.pp[b]);
+                    R[v][a * N + b] -= (s * so) * gl[v][a];
+                }
+            }
+}
+
+// deviation-form stage: out = a0 du^n + a1 du + a2 (L_eq + dL(du, t))
+template <int N>
+__global__ void __launch_bounds__(64) k_stage_dev(const Geo g, const double* __restrict__ du, const double* dun,
+                                                  const double* __restrict__ du0, const float* __restrict__ leq,
+                                                  double* out, const StageCoeffs* __restrict__ scp) {
+    constexpr int NN = N * N;
+    constexpr BasisTab B = make_basis(N);
+    __shared__ float sAll[3 * NN * kWave];
+    const int tile = remap_tile(blockIdx.x, g.tiles_total);
+    const int j = tile / g.tiles_x;
+    const int i = (tile - j * g.tiles_x) * kWave + threadIdx.x;
+    if (i >= g.nx) return;
+    const long long E = g.E;
+    const long long e = (long long)j * g.nx + i;
+    const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
+    float* sD = sAll + threadIdx.x;
+    const rsrc_t rdu = make_rsrc(du), rdu0 = make_rsrc(du0), rdun = make_rsrc(dun), rout = make_rsrc(out),
+                 rleq = make_rsrc(leq);
+    const unsigned eoff = (unsigned)e * 8u, eoff4 = (unsigned)e * 4u, pstride = (unsigned)E * 8u,
+                   pstride4 = (unsigned)E * 4u;
+#pragma unroll
+    for (int m = 0; m < 3 * NN; ++m) sD[m * kWave] = (float)ld64(rdu, eoff, (unsigned)m * pstride);
+    float R[3][NN];
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < NN; ++m) R[v][m] = 0.0f;
+    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+        asm volatile("" ::: "memory");
+        if (f == 0)
+            edge_term_dev<N, 0>(g, sD, R, rdu, rdu0, i, j, e, xc, yc);
+        else if (f == 1)
+            edge_term_dev<N, 1>(g, sD, R, rdu, rdu0, i, j, e, xc, yc);
+        else if (f == 2)
+            edge_term_dev<N, 2>(g, sD, R, rdu, rdu0, i, j, e, xc, yc);
+        else
+            edge_term_dev<N, 3>(g, sD, R, rdu, rdu0, i, j, e, xc, yc);
+    }
+
+    // density: modal volume term (linear in the momentum deviation)
+    const float rdx2 = (float)g.rdx2, rdy2 = (float)g.rdy2;
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            float sx = 0.0f, sy = 0.0f;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                if (B.D[a][c] != 0.0) sx += (float)B.D[a][c] * sD[(1 * NN + c * N + b) * kWave];
+                if (B.D[b][c] != 0.0) sy += (float)B.D[b][c] * sD[(2 * NN + a * N + c) * kWave];
+            }
+            R[0][a * N + b] += rdx2 * sx + rdy2 * sy;
+        }
+#pragma unroll
+    for (int m = 0; m < NN; ++m) {
+        const unsigned po = (unsigned)m * pstride;
+        const double L = (double)ld32(rleq, eoff4, (unsigned)m * pstride4) + (double)R[0][m];
+        const double base = a1 * ld64(rdu, eoff, po) + a2 * L;
+        st64(rout, eoff, po, a0 != 0.0 ? a0 * ld64(rdun, eoff, po) + base : base);
+    }
+
+#pragma unroll 1
+    for (int q = 0; q < N; ++q) {
+        asm volatile("" ::: "memory");
+        double xiq = 0.0;
+        float wpq[N], wdpq[N], phq[N];
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq)
+            if (qq == q) {
+                xiq = B.xi[qq];
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    wpq[a] = (float)B.wphi[a][qq];
+                    wdpq[a] = (float)B.wdphi[a][qq];
+                    phq[a] = (float)B.phi[a][qq];
+                }
+            }
+        const double x = xc + 0.5 * g.dx * xiq;
+        float c[3][N];
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                float s = 0.0f;
+#pragma unroll
+                for (int a = 0; a < N; ++a) s += phq[a] * sD[(v * NN + a * N + b) * kWave];
+                c[v][b] = s;
+            }
+        float Ax[3][N], By[3][N];
+#pragma unroll
+        for (int v = 1; v < 3; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                Ax[v][b] = 0.0f;
+                By[v][b] = 0.0f;
+            }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            float d[3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                float s = 0.0f;
+#pragma unroll
+                for (int b = 0; b < N; ++b) s += c[v][b] * (float)B.phi[b][r];
+                d[v] = s;
+            }
+            const double y = yc + 0.5 * g.dy * B.xi[r];
+            const EqPoint qe = eq_at(g, x, y);
+            const float inv1 = 1.0f / (qe.rho + d[0]);
+            float fx[3], fy[3];
+            dflux<0>(qe, d, inv1, fx);
+            dflux<1>(qe, d, inv1, fy);
+            // stellar pull on the density deviation, planet on the full density
+            const float xf = (float)x, yf = (float)y;
+            const float r2 = xf * xf + yf * yf, rr = sqrtf(r2);
+            const float ks = rr < (float)g.r_core ? (float)g.rc3inv : (float)g.gm / (r2 * rr);
+            float sx = -d[0] * ks * xf, sy = -d[0] * ks * yf;
+            if (g.q > 0.0) {
+                const float dx = (float)(x - xp), dy = (float)(y - yp);
+                const float d2 = dx * dx + dy * dy + (float)g.eps2;
+                const float kp = (float)g.q * rsqrtf(d2) / d2;
+                const float rho = qe.rho + d[0];
+                sx -= rho * kp * dx;
+                sy -= rho * kp * dy;
+            }
+            const float fyy1 = rdy2 * fy[1], fyy2 = rdy2 * fy[2];
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                const float wp = (float)B.wphi[b][r], wd = (float)B.wdphi[b][r];
+                Ax[1][b] += wp * fx[1];
+                Ax[2][b] += wp * fx[2];
+                By[1][b] += wd * fyy1 + wp * sx;
+                By[2][b] += wd * fyy2 + wp * sy;
+            }
+        }
+#pragma unroll
+        for (int v = 1; v < 3; ++v)
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+                    R[v][a * N + b] += (rdx2 * wdpq[a]) * Ax[v][b] + wpq[a] * By[v][b];
+    }
+#pragma unroll
+    for (int v = 1; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < NN; ++m) {
+            const unsigned po = (unsigned)(v * NN + m) * pstride;
+            const double L = (double)ld32(rleq, eoff4, (unsigned)(v * NN + m) * pstride4) + (double)R[v][m];
+            const double base = a1 * ld64(rdu, eoff, po) + a2 * L;
+            st64(rout, eoff, po, a0 != 0.0 ? a0 * ld64(rdun, eoff, po) + base : base);
+        }
+}
+
+// out = a + sign * b, elementwise over a state array (out may alias b)
+__global__ void k_add_state(const double* __restrict__ a, const double* b, double* out, double sign, long long n) {
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) out[k] = a[k] + sign * b[k];
+}
+
+// float copy of an FP64 array
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) b[k] = (float)a[k];
 }
 
 // ------------------------------------------------------------------ init
@@ -461,7 +842,8 @@ __global__ void k_step_begin(const Geo g, StepBlock* sb, double* t_dev, double d
 // CFL step of Sec. 2.3 per element from its means; global minimum by an
 // atomic min on the (order-preserving) bit pattern of the positive double.
 template <int CL>
-__global__ void __launch_bounds__(256) k_dt(const Geo g, int nn, const double* __restrict__ u, StepBlock* sb) {
+__global__ void __launch_bounds__(256) k_dt(const Geo g, int nn, const double* __restrict__ u,
+                                            const double* __restrict__ eq, StepBlock* sb) {
     __shared__ double red[4];
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     double dte = INFINITY;
@@ -473,6 +855,11 @@ __global__ void __launch_bounds__(256) k_dt(const Geo g, int nn, const double* _
         U[1] = u[(long long)nn * E + e];
         U[2] = u[(long long)2 * nn * E + e];
         U[3] = CL == CL_ADI ? u[(long long)3 * nn * E + e] : 0.0;
+        if (eq) {  // deviation form: means of u_eq + du
+            U[0] += eq[e];
+            U[1] += eq[(long long)nn * E + e];
+            U[2] += eq[(long long)2 * nn * E + e];
+        }
         const int i = (int)(e % g.nx), j = (int)(e / g.nx);
         const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
         double p, c;
@@ -539,7 +926,8 @@ __device__ __forceinline__ double ramp(const Geo& g, double r, double& td) {
 
 template <int N, int CL>
 __global__ void __launch_bounds__(64) k_damp(const Geo g, double* __restrict__ u,
-                                             const double* __restrict__ u0, const int* __restrict__ list, int nlist,
+                                             const double* __restrict__ u0, const double* __restrict__ eq,
+                                             const int* __restrict__ list, int nlist,
                                              const StageCoeffs* __restrict__ scp) {
     constexpr BasisTab T = make_basis(N);
     constexpr int NV = NVar<CL>::value;
@@ -560,7 +948,10 @@ __global__ void __launch_bounds__(64) k_damp(const Geo g, double* __restrict__ u
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int m = 0; m < NN; ++m) M[v][m] = u[(long long)(v * NN + m) * E + e];
+        for (int m = 0; m < NN; ++m) {
+            const long long idx = (long long)(v * NN + m) * E + e;
+            M[v][m] = eq ? eq[idx] + u[idx] : u[idx];  // full state (deviation form: u_eq + du)
+        }
     eval_nodes<N, NV>(M, W);
     // nodal increments (written over W)
 #pragma unroll
@@ -615,13 +1006,10 @@ __global__ void __launch_bounds__(64) k_damp(const Geo g, double* __restrict__ u
                 double s = 0.0;
 #pragma unroll
                 for (int r = 0; r < N; ++r) s += T.wh[r] * T.phi[b][r] * c[r];
-                M[v][a * N + b] += s;
+                const long long idx = (long long)(v * NN + a * N + b) * E + e;
+                u[idx] = u[idx] + s;
             }
         }
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int m = 0; m < NN; ++m) u[(long long)(v * NN + m) * E + e] = M[v][m];
 }
 
 // ------------------------------------------------------------------ torque
@@ -640,7 +1028,8 @@ __device__ __forceinline__ double block_sum_256(double s, double* red) {
 
 template <int N>
 __global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, double t, const double* t_dev,
-                                                         const double* __restrict__ u, double* __restrict__ partials) {
+                                                         const double* __restrict__ u, const double* __restrict__ eq,
+                                                         double* __restrict__ partials) {
     constexpr BasisTab T = make_basis(N);
     __shared__ double red[4];
     constexpr int NN = N * N;
@@ -652,7 +1041,10 @@ __global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, double t, 
     if (e < g.E) {
         double M[1][NN], W[1][NN];
 #pragma unroll
-        for (int m = 0; m < NN; ++m) M[0][m] = u[(long long)m * g.E + e];
+        for (int m = 0; m < NN; ++m) {
+            const long long idx = (long long)m * g.E + e;
+            M[0][m] = eq ? eq[idx] + u[idx] : u[idx];
+        }
         eval_nodes<N, 1>(M, W);
         const int i = (int)(e % g.nx), j = (int)(e / g.nx);
         const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
@@ -723,9 +1115,9 @@ hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0,
     return hipGetLastError();
 }
 
-hipError_t launch_dt(int n, const Geo& g, const double* u, StepBlock* sb, hipStream_t s) {
+hipError_t launch_dt(int n, const Geo& g, const double* u, const double* eq, StepBlock* sb, hipStream_t s) {
     const int blocks = (int)((g.E + 255) / 256);
-    DG_DISPATCH_CL(g.closure, hipLaunchKernelGGL((k_dt<CT>), dim3(blocks), dim3(256), 0, s, g, n * n, u, sb));
+    DG_DISPATCH_CL(g.closure, hipLaunchKernelGGL((k_dt<CT>), dim3(blocks), dim3(256), 0, s, g, n * n, u, eq, sb));
     return hipGetLastError();
 }
 
@@ -735,20 +1127,40 @@ hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double 
     return hipGetLastError();
 }
 
-hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const int* list, int nlist,
-                       const StageCoeffs* sc, hipStream_t s) {
+hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const double* eq, const int* list,
+                       int nlist, const StageCoeffs* sc, hipStream_t s) {
     if (nlist <= 0) return hipSuccess;
     const int blocks = (nlist + 63) / 64;
     DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_damp<NT, CT>), dim3(blocks), dim3(64), 0, s, g,
-                                                                  u, u0, list, nlist, sc)));
+                                                                  u, u0, eq, list, nlist, sc)));
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double* dun, const double* du0,
+                            const float* leq, double* out, const StageCoeffs* sc, hipStream_t s) {
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_stage_dev<NT>), dim3(g.tiles_total), dim3(64), 0, s, g, du, dun, du0, leq,
+                                        out, sc));
+    return hipGetLastError();
+}
+
+hipError_t launch_add_state(const double* a, const double* b, double* out, double sign, long long n,
+                            hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_add_state, dim3(blocks), dim3(256), 0, s, a, b, out, sign, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks), dim3(256), 0, s, a, b, n);
     return hipGetLastError();
 }
 
 int torque_blocks(const Geo& g) { return (int)((g.E + kTorqueBlock - 1) / kTorqueBlock); }
 
-hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, double* partials,
-                         int nblocks, double* out, hipStream_t s) {
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_torque<NT>), dim3(nblocks), dim3(kTorqueBlock), 0, s, g, t, t_dev, u,
+hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,
+                         double* partials, int nblocks, double* out, hipStream_t s) {
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_torque<NT>), dim3(nblocks), dim3(kTorqueBlock), 0, s, g, t, t_dev, u, eq,
                                         partials));
     hipLaunchKernelGGL(k_torque_final, dim3(1), dim3(kTorqueBlock), 0, s, partials, nblocks, out);
     return hipGetLastError();

@@ -37,7 +37,7 @@ class dg_config(C.Structure):
         ("bc", C.c_int), ("star", C.c_int), ("gm", C.c_double), ("r_core", C.c_double),
         ("q", C.c_double), ("eps", C.c_double), ("rp", C.c_double), ("phi0", C.c_double),
         ("damping", C.c_int), ("rd_in", C.c_double), ("rd_out", C.c_double),
-        ("cfl", C.c_double), ("precision", C.c_int), ("limiter", C.c_int),
+        ("cfl", C.c_double), ("precision", C.c_int), ("sigma0", C.c_double), ("limiter", C.c_int),
         ("limiter_s0", C.c_double), ("mlp_theta", C.c_double),
     ]
 
@@ -70,6 +70,7 @@ class Config:
     rd_out: float = 2.3
     cfl: float = 0.2
     precision: int = PRECISION_FP64
+    sigma0: float = 1.0
     limiter: int = LIMITER_NONE
     limiter_s0: float = 0.0
     mlp_theta: float = 0.5
@@ -108,7 +109,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, dp, cp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(dg_config)
         L.dg_get_nodes.argtypes = [cp, dp, dp]
-        L.dg_init.argtypes = [cp, dp, dp, vp, vp, C.POINTER(vp)]
+        L.dg_init.argtypes = [cp, dp, vp, vp, C.POINTER(vp)]
+        L.dg_full_state.argtypes = [vp, vp, vp]
         L.dg_rhs.argtypes = [vp, C.c_double, vp, vp]
         L.dg_rk_step.argtypes = [vp, vp, vp, C.c_double, vp]
         L.dg_torque.argtypes = [vp, C.c_double, vp, vp, vp]
@@ -119,14 +121,14 @@ def lib():
         L.dg_last_error.argtypes = [vp]
         L.dg_last_error.restype = C.c_char_p
         for name in ("dg_get_nodes", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
-                     "dg_profile_begin", "dg_profile_end"):
+                     "dg_profile_begin", "dg_profile_end", "dg_full_state"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
 
 
 EXPORTS = ("dg_get_nodes", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
-           "dg_last_error", "dg_profile_begin", "dg_profile_end")
+           "dg_last_error", "dg_profile_begin", "dg_profile_end", "dg_full_state")
 
 
 def _check(rc, h=None):
@@ -173,24 +175,19 @@ class Handle:
             pass
 
 
-def dg_init(cfg: Config, prim, eq_prim=None, device="cuda"):
+def dg_init(cfg: Config, prim, device="cuda"):
     """Project primitive node values ``prim`` ([var][E][n^2], host float64) and
-    return (handle, u0) with u0 a device tensor in the state layout."""
+    return (handle, u0) with u0 a device tensor in the state layout (the
+    deviation from the equilibrium in the mixed-precision form)."""
     import torch
     prim = np.ascontiguousarray(prim, dtype=np.float64)
     if prim.shape != (cfg.nvar, cfg.n_elem, cfg.order ** 2):
         raise ValueError(f"prim has shape {prim.shape}, expected {(cfg.nvar, cfg.n_elem, cfg.order ** 2)}")
-    eq = None
-    if eq_prim is not None:
-        eq = np.ascontiguousarray(eq_prim, dtype=np.float64)
-        if eq.shape != prim.shape:
-            raise ValueError("eq_prim must have the shape of prim")
     u0 = torch.empty(cfg.state_shape, dtype=torch.float64, device=device)
     h = C.c_void_p()
     c = cfg.to_c()
     dp = C.POINTER(C.c_double)
-    rc = lib().dg_init(C.byref(c), prim.ctypes.data_as(dp), eq.ctypes.data_as(dp) if eq is not None else None,
-                       _ptr(u0), _stream(), C.byref(h))
+    rc = lib().dg_init(C.byref(c), prim.ctypes.data_as(dp), _ptr(u0), _stream(), C.byref(h))
     _check(rc)
     return Handle(h, cfg), u0
 
@@ -217,6 +214,10 @@ def dg_profile_end(h: Handle):
     n = C.c_int()
     _check(lib().dg_profile_end(h.ptr, C.byref(ms), C.byref(n)), h.ptr)
     return ms.value, n.value
+
+
+def dg_full_state(h: Handle, dev, full):
+    _check(lib().dg_full_state(h.ptr, _ptr(dev), _ptr(full)), h.ptr)
 
 
 def dg_sync(h: Handle):

@@ -68,7 +68,7 @@ def test_init_rejects_bad_configs_without_a_device(bad, code):
     h = C.c_void_p()
     c = cfg.to_c()
     dp = C.POINTER(C.c_double)
-    rc = dg.lib().dg_init(C.byref(c), prim.ctypes.data_as(dp), None, C.c_void_p(8), None, C.byref(h))
+    rc = dg.lib().dg_init(C.byref(c), prim.ctypes.data_as(dp), C.c_void_p(8), None, C.byref(h))
     assert rc == code
     assert h.value is None
     assert dg.lib().dg_last_error(None)
