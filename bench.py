@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -101,6 +102,39 @@ def cpu_baseline(cfg, prim):
                       f"({threads} threads), {el:.1f} s"}
 
 
+def run_disc(cfg, prim, steps, warmup, profile):
+    """Warm up, then time `steps` SSP-RK3 steps + torque; returns timings, the
+    torque series of the timed steps and the final full state (device)."""
+    import torch
+
+    from paper_1805_01443_amd import dg
+    h, u = dg.dg_init(cfg, prim)
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    torques = torch.zeros(steps + warmup, dtype=torch.float64, device="cuda")
+    for k in range(warmup):
+        dg.dg_rk_step(h, u, t_dev, 0.0, None)
+        dg.dg_torque(h, u, torques[k:k + 1], t_dev=t_dev)
+    dg.dg_sync(h)
+    if profile:
+        dg.dg_profile_begin(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        dg.dg_rk_step(h, u, t_dev, 0.0, None)
+        dg.dg_torque(h, u, torques[warmup + k:warmup + k + 1], t_dev=t_dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms, launches = dg.dg_profile_end(h) if profile else (0.0, 0)
+    dg.dg_sync(h)
+    full = torch.empty_like(u)
+    dg.dg_full_state(h, u, full)
+    torch.cuda.synchronize()
+    res = {"elapsed": t1 - t0, "stage_ms": stage_ms, "launches": launches, "torques": torques[warmup:].clone(),
+           "full": full, "t_end": float(t_dev.item())}
+    h.close()
+    return res
+
+
 def main():
     a = parse()
     if a.calibrate_copy:
@@ -118,31 +152,15 @@ def main():
     torch.cuda.set_device(0)
     cfg = W.disc(nx=a.nx, order=a.order)
     prim = W.prim_for(cfg, "disc")
-    h, u = dg.dg_init(cfg, prim)
-    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-    torques = torch.zeros(a.steps + a.warmup, dtype=torch.float64, device="cuda")
-    for k in range(a.warmup):
-        dg.dg_rk_step(h, u, t_dev, 0.0, None)
-        dg.dg_torque(h, u, torques[k:k + 1], t_dev=t_dev)
-    dg.dg_sync(h)
-    dg.dg_profile_begin(h)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        dg.dg_rk_step(h, u, t_dev, 0.0, None)
-        dg.dg_torque(h, u, torques[a.warmup + k:a.warmup + k + 1], t_dev=t_dev)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stage_ms, launches = dg.dg_profile_end(h)
-    dg.dg_sync(h)
-    el = t1 - t0
+    r64 = run_disc(cfg, prim, a.steps, a.warmup, profile=True)
+    el = r64["elapsed"]
     dofs = W.dofs(cfg)
     value = dofs * 3 * a.steps / el
     state_bytes = cfg.nvar * cfg.order ** 2 * cfg.n_elem * 8
     # algorithmic bytes of the three stage launches of a step: read u^(i),
     # read u^n (stages 2 and 3), write u^(i+1): 2 + 3 + 3 state passes
     alg_bytes_per_launch = state_bytes * 8.0 / 3.0
-    avg_launch_s = stage_ms / 1e3 / max(launches, 1)
+    avg_launch_s = r64["stage_ms"] / 1e3 / max(r64["launches"], 1)
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9
     workload = f"disc{cfg.nx}_p{cfg.order - 1}_fp64"
     traffic = measured_traffic(workload)
@@ -162,15 +180,29 @@ def main():
         "config": {"workload": workload, "nx": cfg.nx, "ny": cfg.ny, "order": cfg.order,
                    "closure": "locally_isothermal", "h": cfg.h, "q": cfg.q, "eps": cfg.eps,
                    "dofs": dofs, "stages_per_step": 3, "torque_every_step": True,
-                   "final_torque": float(torques[-1].item()), "t_end": float(t_dev.item())},
+                   "final_torque": float(r64["torques"][-1].item()), "t_end": r64["t_end"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "k_stage (fused RK stage)", "avg_launch_us": avg_launch_s * 1e6,
                      "alg_bytes_per_launch": alg_bytes_per_launch},
     }
-    h.close()
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, W.prim_for(cfg, "disc"))
+    if not a.no_mixed:
+        # the same workload in the mixed-precision deviation form
+        cm = cfg.replace(precision=dg.PRECISION_MIXED, sigma0=1.0)
+        rm = run_disc(cm, prim, a.steps, a.warmup, profile=True)
+        g64, gm = r64["torques"], rm["torques"]
+        rho64 = r64["full"][0]
+        rhom = rm["full"][0]
+        dens_l2 = float(((rhom - rho64) ** 2).sum().sqrt() / (rho64 ** 2).sum().sqrt())
+        tq_err = float((gm - g64).abs().max() / g64.abs().max())
+        out["forms"] = {
+            "mixed": {"value": dofs * 3 * a.steps / rm["elapsed"], "unit": "DOF-stage/s",
+                      "speedup_vs_fp64": el / rm["elapsed"],
+                      "stage_kernel_us": rm["stage_ms"] * 1e3 / max(rm["launches"], 1),
+                      "torque_series_rel_err_vs_fp64": tq_err, "density_rel_L2_err_vs_fp64": dens_l2,
+                      "note": "FP32 deviation arithmetic about the projected equilibrium; FP64 state, "
+                              "stage combination, damping, dt and torque"}}
+    del r64
     print(json.dumps(out), flush=True)
 
 

@@ -121,6 +121,56 @@ int dg_rk_step(dg_handle *h, double *u_dev, double *t_dev, double dt_fixed, doub
  * give identical bits. */
 int dg_torque(dg_handle *h, double t, const double *t_dev, const double *u_dev, double *torque_dev);
 
+/* ---- troubled cells (limiter DG_LIMITER_MODAL_DECAY or DG_LIMITER_LEARNED) ----
+ *
+ * The limiter is the minmod slope limiter of the Cockburn-Shu RKDG scheme the
+ * paper follows (Sec. 2.2): on a troubled element the linear modes are
+ * replaced by minmod(own slope, forward and backward differences of the
+ * neighbour means), component-wise per conservative variable; if any slope
+ * changes, every higher mode is dropped.  Means are never changed.  The plain
+ * indicator flags an element when log10 of the share of its density energy
+ * in the modes of top degree (max(a, b) = N_p) exceeds cfg->limiter_s0.  The
+ * learned indicator is a 64 -> 32 -> 32 -> 1 MLP (ReLU, sigmoid output; bf16
+ * weights and inputs, FP32 accumulation on MFMA) on the element features
+ * f[v*16 + m] = u_vm / (|u_v00| + s_v) (order 4, four variables); it flags
+ * when the sigmoid exceeds cfg->mlp_theta.  With a limiter configured,
+ * dg_rk_step limits each stage state after its update (Shu-Osher form). */
+
+/* Plain indicator and minmod on u_dev: apply != 0 limits in place.  Outputs
+ * (device arrays of E entries, each may be NULL): flag_dev (indicator fired),
+ * changed_dev (minmod alters a slope: the training label), sensor_dev (log10
+ * energy share, float). */
+int dg_troubled(dg_handle *h, double *u_dev, int apply, unsigned char *flag_dev, unsigned char *changed_dev,
+                float *sensor_dev);
+/* Feature scales s_v (RMS of the initial element means of variable v), host
+ * array of nvar doubles. */
+int dg_mlp_feature_scales(dg_handle *h, double *scales_host);
+/* bf16 features of every element, feat_dev[e*64 + v*16 + m] (needs order 4,
+ * nvar 4). */
+int dg_mlp_features(dg_handle *h, const double *u_dev, unsigned short *feat_dev);
+/* Set (set_host != NULL; resets the Adam moments and step) and/or read
+ * (get_host != NULL) the 3169 FP32 master parameters, layout W1[32][64], b1[32],
+ * W2[32][32], b2[32], w3[32], b3.  Host arrays. */
+int dg_mlp_params(dg_handle *h, const float *set_host, float *get_host);
+/* Logits of n feature rows (device arrays). */
+int dg_mlp_forward(dg_handle *h, const unsigned short *feat_dev, long n, float *logit_dev);
+/* One training step on n samples: forward, BCE-with-logits (mean, positives
+ * weighted by pos_weight) backward, and Adam (beta 0.9 / 0.999, eps 1e-8) with
+ * learning rate lr (lr <= 0: gradient only, parameters unchanged).  loss_dev
+ * (1 float) and grad_dev (3169 floats) may be NULL.  Device arrays; the
+ * handle keeps the workspace for the largest n seen. */
+int dg_mlp_train_step(dg_handle *h, const unsigned short *feat_dev, const float *label_dev, long n, float pos_weight,
+                      float lr, float *loss_dev, float *grad_dev);
+
+/* One-shot capture for training data and indicator evaluation: the next
+ * dg_rk_step records, for the state of its last stage before limiting, the bf16
+ * features (feat_dev, E x 64), the plain indicator's flags (flag_dev) and
+ * labels (label_dev: flagged and minmod alters a slope), and with the learned
+ * limiter its flags (mlp_flag_dev).  Device arrays of E entries; any may be
+ * NULL.  Needs a configured limiter. */
+int dg_capture(dg_handle *h, unsigned short *feat_dev, unsigned char *flag_dev, unsigned char *label_dev,
+               unsigned char *mlp_flag_dev);
+
 /* Wait for the handle's stream; returns DG_ENONFINITE if a kernel flagged a
  * non-finite or non-positive density mean since the last dg_sync. */
 int dg_sync(dg_handle *h);

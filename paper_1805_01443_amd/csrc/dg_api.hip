@@ -37,6 +37,18 @@ struct dg_handle {
     int ndamp = 0;
     double* tq_part = nullptr;
     int tq_blocks = 0;
+    // troubled cells / learned indicator
+    double* scale_dev = nullptr;     // feature scales (nvar)
+    double scale_host[4] = {0, 0, 0, 0};
+    unsigned char* flags = nullptr;  // E
+    unsigned short* feat = nullptr;  // E * 64 (learned limiter)
+    float* mlp = nullptr;            // parameters, Adam m, Adam v (3 * nparam)
+    long long adam_t = 0;
+    long long tr_cap = 0;            // training workspace capacity (samples)
+    float* tr_ws = nullptr;          // z, h1, h2, dz, d1, d2, loss partials, grad
+    bool cap = false;                // one-shot capture armed for the next step's last stage
+    unsigned short* cap_feat = nullptr;
+    unsigned char *cap_flag = nullptr, *cap_label = nullptr, *cap_mlp = nullptr;
     bool prof = false;               // bracket stage launches with events
     std::vector<hipEvent_t> ev;      // start/stop pairs
     std::string err;
@@ -90,7 +102,15 @@ int validate(const dg_config* c, std::string* why) {
         !(c->closure == DG_CLOSURE_LOCALLY_ISOTHERMAL && c->star && c->sigma0 > 0))
         return (*why = "the deviation form is built for the locally isothermal disc with stellar gravity and sigma0 > 0",
                 DG_EUNSUPPORTED);
-    if (c->limiter != DG_LIMITER_NONE) return (*why = "limiters are not built", DG_EUNSUPPORTED);
+    if (c->limiter < DG_LIMITER_NONE || c->limiter > DG_LIMITER_LEARNED) return (*why = "unknown limiter", DG_EINVAL);
+    if (c->limiter != DG_LIMITER_NONE && c->precision != DG_PRECISION_FP64)
+        return (*why = "limiters are built for the FP64 form", DG_EUNSUPPORTED);
+    if (c->limiter == DG_LIMITER_LEARNED && !(c->order == 4 && c->nvar == 4))
+        return (*why = "the learned indicator takes 16 modes x 4 variables (order 4, nvar 4)", DG_EUNSUPPORTED);
+    if (c->limiter == DG_LIMITER_LEARNED && !(c->mlp_theta > 0 && c->mlp_theta < 1))
+        return (*why = "mlp_theta must be in (0, 1)", DG_EINVAL);
+    if ((double)c->nvar * c->order * c->order * (double)c->nx * c->ny * 8.0 >= 4294967296.0)
+        return (*why = "state arrays are limited to 4 GiB (32-bit buffer offsets)", DG_EUNSUPPORTED);
     return DG_OK;
 }
 
@@ -198,6 +218,36 @@ void equilibrium_prim(const dg_config* c, std::vector<double>* prim) {
     }
 }
 
+// configured limiter on a stage state, in place; `last` marks the last stage
+// of a step (where an armed capture records the pre-limiter state)
+hipError_t limit(dg_handle* h, double* u, bool last) {
+    const int lim = h->cfg.limiter;
+    if (lim == DG_LIMITER_NONE) return hipSuccess;
+    hipError_t e = hipSuccess;
+    const bool cap = last && h->cap;
+    if (cap) {
+        h->cap = false;
+        if (h->cap_feat) e = dgk::launch_features(h->n, h->nvar, h->g, u, h->scale_dev, h->cap_feat, h->s);
+        if (e == hipSuccess && (h->cap_flag || h->cap_label))
+            e = dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, h->cfg.limiter_s0, 0, 0, nullptr, h->cap_flag,
+                                     h->cap_label, nullptr, h->s);
+        if (e != hipSuccess) return e;
+    }
+    if (lim == DG_LIMITER_MODAL_DECAY)
+        return dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, h->cfg.limiter_s0, 0, 1, nullptr, nullptr, nullptr,
+                                    nullptr, h->s);
+    const float th = (float)h->cfg.mlp_theta;
+    const float zthr = std::log(th / (1.0f - th));  // sigmoid(z) > theta  <=>  z > logit(theta)
+    e = dgk::launch_features(h->n, h->nvar, h->g, u, h->scale_dev, h->feat, h->s);
+    if (e == hipSuccess)
+        e = dgk::launch_mlp_forward(h->feat, h->E, h->mlp, nullptr, nullptr, nullptr, h->flags, zthr, h->s);
+    if (e == hipSuccess && cap && h->cap_mlp)
+        e = hipMemcpyAsync(h->cap_mlp, h->flags, (size_t)h->E, hipMemcpyDeviceToDevice, h->s);
+    if (e == hipSuccess)
+        e = dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, 0.0, 1, 1, h->flags, nullptr, nullptr, nullptr, h->s);
+    return e;
+}
+
 void release(dg_handle* h) {
     if (!h) return;
     drop_events(h);
@@ -211,6 +261,11 @@ void release(dg_handle* h) {
     (void)hipFree(h->eq);
     (void)hipFree(h->du0);
     (void)hipFree(h->leq);
+    (void)hipFree(h->scale_dev);
+    (void)hipFree(h->flags);
+    (void)hipFree(h->feat);
+    (void)hipFree(h->mlp);
+    (void)hipFree(h->tr_ws);
     h->u0 = h->ws1 = h->ws2 = h->eq = h->du0 = nullptr;
     h->leq = nullptr;
 }
@@ -274,6 +329,10 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     h->tq_blocks = dgk::torque_blocks(h->g);
     DG_ALLOC(h->tq_part, sizeof(double) * (size_t)h->tq_blocks);
     DG_ALLOC(prim_dev, state_bytes);
+    DG_ALLOC(h->scale_dev, sizeof(double) * 4);
+    DG_ALLOC(h->flags, (size_t)h->E);
+    DG_ALLOC(h->mlp, sizeof(float) * 3 * (size_t)dgk::mlp_nparam());
+    if (cfg->limiter == DG_LIMITER_LEARNED) DG_ALLOC(h->feat, sizeof(unsigned short) * 64 * (size_t)h->E);
     if (h->dev) {
         DG_ALLOC(h->eq, state_bytes);
         DG_ALLOC(h->du0, state_bytes);
@@ -316,6 +375,20 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     if (e == hipSuccess) e = hipStreamSynchronize(h->s);
     (void)hipFree(prim_dev);
     if (e != hipSuccess) return bail(hip_fail(h, e, "dg_init projection"));
+    // feature scales: RMS of the initial element means of each variable
+    {
+        std::vector<double> means((size_t)h->E);
+        const size_t nn = (size_t)h->n * h->n;
+        for (int v = 0; v < h->nvar && e == hipSuccess; ++v) {
+            e = hipMemcpy(means.data(), h->u0 + v * nn * h->E, sizeof(double) * h->E, hipMemcpyDeviceToHost);
+            double ss = 0.0;
+            for (double m : means) ss += m * m;
+            h->scale_host[v] = std::sqrt(ss / (double)h->E);
+        }
+        if (e == hipSuccess) e = hipMemcpy(h->scale_dev, h->scale_host, sizeof(double) * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(h->mlp, 0, sizeof(float) * 3 * (size_t)dgk::mlp_nparam());
+        if (e != hipSuccess) return bail(hip_fail(h, e, "dg_init feature scales"));
+    }
     *out = h;
     return DG_OK;
 }
@@ -338,8 +411,11 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     DG_HIP(h, dgk::launch_dt(h->n, h->g, u_dev, h->eq, sb, h->s), "CFL reduction");
     DG_HIP(h, dgk::launch_step_begin(h->g, sb, t_dev, dt_fixed, dt_used_dev, h->s), "step begin");
     DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
+    DG_HIP(h, limit(h, h->ws1, false), "limiter");
     DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1]), "stage 2");
+    DG_HIP(h, limit(h, h->ws2, false), "limiter");
     DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2]), "stage 3");
+    DG_HIP(h, limit(h, u_dev, true), "limiter");
     if (h->cfg.damping)
         DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
                "damping");
@@ -351,6 +427,101 @@ int dg_torque(dg_handle* h, double t, const double* t_dev, const double* u_dev, 
     if (!u_dev || !torque_dev) return fail(h, DG_EINVAL, "u_dev and torque_dev are required");
     DG_HIP(h, dgk::launch_torque(h->n, h->g, t, t_dev, u_dev, h->eq, h->tq_part, h->tq_blocks, torque_dev, h->s),
            "torque");
+    return DG_OK;
+}
+
+int dg_troubled(dg_handle* h, double* u_dev, int apply, unsigned char* flag_dev, unsigned char* changed_dev,
+                float* sensor_dev) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    if (!u_dev) return fail(h, DG_EINVAL, "NULL state");
+    if (h->dev) return fail(h, DG_EUNSUPPORTED, "the limiter runs on the FP64 form");
+    DG_HIP(h, dgk::launch_troubled(h->n, h->nvar, h->g, u_dev, h->u0, h->cfg.limiter_s0, 0, apply ? 1 : 0, nullptr,
+                                   flag_dev, changed_dev, sensor_dev, h->s),
+           "troubled cells");
+    return DG_OK;
+}
+
+int dg_capture(dg_handle* h, unsigned short* feat_dev, unsigned char* flag_dev, unsigned char* label_dev,
+               unsigned char* mlp_flag_dev) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    if (h->cfg.limiter == DG_LIMITER_NONE) return fail(h, DG_EINVAL, "capture needs a configured limiter");
+    if (feat_dev && !(h->n == 4 && h->nvar == 4)) return fail(h, DG_EUNSUPPORTED, "features need order 4 and nvar 4");
+    h->cap = true;
+    h->cap_feat = feat_dev;
+    h->cap_flag = flag_dev;
+    h->cap_label = label_dev;
+    h->cap_mlp = mlp_flag_dev;
+    return DG_OK;
+}
+
+int dg_mlp_feature_scales(dg_handle* h, double* scales_host) {
+    if (!h || !scales_host) return fail(h, DG_EINVAL, "NULL argument");
+    for (int v = 0; v < h->nvar; ++v) scales_host[v] = h->scale_host[v];
+    return DG_OK;
+}
+
+int dg_mlp_features(dg_handle* h, const double* u_dev, unsigned short* feat_dev) {
+    if (!h || !u_dev || !feat_dev) return fail(h, DG_EINVAL, "NULL argument");
+    if (!(h->n == 4 && h->nvar == 4)) return fail(h, DG_EUNSUPPORTED, "features need order 4 and nvar 4");
+    DG_HIP(h, dgk::launch_features(h->n, h->nvar, h->g, u_dev, h->scale_dev, feat_dev, h->s), "features");
+    return DG_OK;
+}
+
+int dg_mlp_params(dg_handle* h, const float* set_host, float* get_host) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    const size_t np = (size_t)dgk::mlp_nparam();
+    if (set_host) {
+        DG_HIP(h, hipStreamSynchronize(h->s), "sync");
+        DG_HIP(h, hipMemcpy(h->mlp, set_host, sizeof(float) * np, hipMemcpyHostToDevice), "set params");
+        DG_HIP(h, hipMemset(h->mlp + np, 0, sizeof(float) * 2 * np), "reset moments");
+        h->adam_t = 0;
+    }
+    if (get_host) {
+        DG_HIP(h, hipStreamSynchronize(h->s), "sync");
+        DG_HIP(h, hipMemcpy(get_host, h->mlp, sizeof(float) * np, hipMemcpyDeviceToHost), "get params");
+    }
+    return DG_OK;
+}
+
+int dg_mlp_forward(dg_handle* h, const unsigned short* feat_dev, long n, float* logit_dev) {
+    if (!h || !feat_dev || !logit_dev || n < 0) return fail(h, DG_EINVAL, "bad argument");
+    if (n == 0) return DG_OK;
+    DG_HIP(h, dgk::launch_mlp_forward(feat_dev, n, h->mlp, logit_dev, nullptr, nullptr, nullptr, 0.f, h->s), "forward");
+    return DG_OK;
+}
+
+int dg_mlp_train_step(dg_handle* h, const unsigned short* feat_dev, const float* label_dev, long n, float pos_weight,
+                      float lr, float* loss_dev, float* grad_dev) {
+    if (!h || !feat_dev || !label_dev || n <= 0) return fail(h, DG_EINVAL, "bad argument");
+    const long long nb = dgk::mlp_delta_blocks(n);
+    const size_t np = (size_t)dgk::mlp_nparam();
+    if (n > h->tr_cap) {
+        DG_HIP(h, hipStreamSynchronize(h->s), "sync");
+        (void)hipFree(h->tr_ws);
+        h->tr_ws = nullptr;
+        const size_t need = (size_t)n * (1 + 32 + 32 + 1 + 32 + 32) + (size_t)nb + np;
+        hipError_t e = hipMalloc((void**)&h->tr_ws, sizeof(float) * need);
+        if (e != hipSuccess) {
+            h->tr_cap = 0;
+            return fail(h, DG_ENOMEM, "training workspace");
+        }
+        h->tr_cap = n;
+    }
+    float* z = h->tr_ws;
+    float* h1 = z + n;
+    float* h2 = h1 + (size_t)n * 32;
+    float* dz = h2 + (size_t)n * 32;
+    float* d1 = dz + n;
+    float* d2 = d1 + (size_t)n * 32;
+    float* lp = d2 + (size_t)n * 32;
+    float* grad = grad_dev ? grad_dev : lp + nb;
+    DG_HIP(h, dgk::launch_mlp_forward(feat_dev, n, h->mlp, z, h1, h2, nullptr, 0.f, h->s), "forward");
+    DG_HIP(h, dgk::launch_mlp_backward(feat_dev, label_dev, n, pos_weight, h->mlp, z, h1, h2, dz, d1, d2, lp, grad, h->s),
+           "backward");
+    if (lr > 0.f) ++h->adam_t;
+    DG_HIP(h, dgk::launch_mlp_adam(grad, lp, (int)nb, h->mlp, h->mlp + np, h->mlp + 2 * np, h->adam_t, lr, 0.9f, 0.999f,
+                                   1e-8f, loss_dev, h->s),
+           "adam");
     return DG_OK;
 }
 

@@ -71,4 +71,20 @@ hipError_t launch_add_state(const double* a, const double* b, double* out, doubl
 hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
 int torque_blocks(const Geo& g);
 
+// troubled cells and the learned indicator
+hipError_t launch_troubled(int n, int nvar, const Geo& g, double* u, const double* u0, double s0, int mode, int apply,
+                           const unsigned char* flag_in, unsigned char* flag_out, unsigned char* changed_out,
+                           float* sensor_out, hipStream_t s);
+hipError_t launch_features(int n, int nvar, const Geo& g, const double* u, const double* scale, unsigned short* f,
+                           hipStream_t s);
+hipError_t launch_mlp_forward(const unsigned short* x, long long n, const float* par, float* z, float* h1, float* h2,
+                              unsigned char* flags, float zthr, hipStream_t s);
+int mlp_delta_blocks(long long n);
+int mlp_nparam();
+hipError_t launch_mlp_backward(const unsigned short* x, const float* y, long long n, float pos_weight,
+                               const float* par, const float* z, const float* h1, const float* h2, float* dz,
+                               float* d1, float* d2, float* loss_part, float* grad, hipStream_t s);
+hipError_t launch_mlp_adam(const float* grad, const float* loss_part, int nblk, float* par, float* m, float* v,
+                           long long t, float lr, float b1, float b2, float eps, float* loss_out, hipStream_t s);
+
 }  // namespace dgk

@@ -118,17 +118,29 @@ def lib():
         L.dg_free.argtypes = [vp]
         L.dg_profile_begin.argtypes = [vp]
         L.dg_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.dg_troubled.argtypes = [vp, vp, C.c_int, vp, vp, vp]
+        L.dg_mlp_feature_scales.argtypes = [vp, dp]
+        L.dg_mlp_features.argtypes = [vp, vp, vp]
+        L.dg_mlp_params.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.dg_mlp_forward.argtypes = [vp, vp, C.c_long, vp]
+        L.dg_mlp_train_step.argtypes = [vp, vp, vp, C.c_long, C.c_float, C.c_float, vp, vp]
+        L.dg_capture.argtypes = [vp, vp, vp, vp, vp]
         L.dg_last_error.argtypes = [vp]
         L.dg_last_error.restype = C.c_char_p
         for name in ("dg_get_nodes", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
-                     "dg_profile_begin", "dg_profile_end", "dg_full_state"):
+                     "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled",
+                     "dg_mlp_feature_scales", "dg_mlp_features", "dg_mlp_params", "dg_mlp_forward",
+                     "dg_mlp_train_step", "dg_capture"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
 
 
 EXPORTS = ("dg_get_nodes", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
-           "dg_last_error", "dg_profile_begin", "dg_profile_end", "dg_full_state")
+           "dg_last_error", "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled",
+           "dg_mlp_feature_scales", "dg_mlp_features", "dg_mlp_params", "dg_mlp_forward", "dg_mlp_train_step",
+           "dg_capture")
+MLP_NPARAM = 3169
 
 
 def _check(rc, h=None):
@@ -218,6 +230,46 @@ def dg_profile_end(h: Handle):
 
 def dg_full_state(h: Handle, dev, full):
     _check(lib().dg_full_state(h.ptr, _ptr(dev), _ptr(full)), h.ptr)
+
+
+def dg_troubled(h: Handle, u, apply=False, flags=None, changed=None, sensor=None):
+    _check(lib().dg_troubled(h.ptr, _ptr(u), int(bool(apply)), _ptr(flags), _ptr(changed), _ptr(sensor)), h.ptr)
+
+
+def dg_mlp_feature_scales(h: Handle):
+    out = np.zeros(h.cfg.nvar)
+    _check(lib().dg_mlp_feature_scales(h.ptr, out.ctypes.data_as(C.POINTER(C.c_double))), h.ptr)
+    return out
+
+
+def dg_mlp_features(h: Handle, u, feat):
+    """feat: int16/uint16 device tensor [E, 64] receiving bf16 bit patterns"""
+    _check(lib().dg_mlp_features(h.ptr, _ptr(u), _ptr(feat)), h.ptr)
+
+
+def dg_mlp_params(h: Handle, set_params=None, get=False):
+    fp = C.POINTER(C.c_float)
+    src = None
+    if set_params is not None:
+        src = np.ascontiguousarray(set_params, dtype=np.float32)
+        assert src.size == MLP_NPARAM
+    out = np.zeros(MLP_NPARAM, dtype=np.float32) if get else None
+    _check(lib().dg_mlp_params(h.ptr, src.ctypes.data_as(fp) if src is not None else None,
+                               out.ctypes.data_as(fp) if out is not None else None), h.ptr)
+    return out
+
+
+def dg_mlp_forward(h: Handle, feat, n, logits):
+    _check(lib().dg_mlp_forward(h.ptr, _ptr(feat), int(n), _ptr(logits)), h.ptr)
+
+
+def dg_mlp_train_step(h: Handle, feat, labels, n, pos_weight=1.0, lr=1e-3, loss=None, grad=None):
+    _check(lib().dg_mlp_train_step(h.ptr, _ptr(feat), _ptr(labels), int(n), float(pos_weight), float(lr),
+                                   _ptr(loss), _ptr(grad)), h.ptr)
+
+
+def dg_capture(h: Handle, feat=None, flags=None, labels=None, mlp_flags=None):
+    _check(lib().dg_capture(h.ptr, _ptr(feat), _ptr(flags), _ptr(labels), _ptr(mlp_flags)), h.ptr)
 
 
 def dg_sync(h: Handle):

@@ -1,0 +1,179 @@
+"""GPU parity of the troubled-cell path and the learned indicator against the
+oracle.  Integer decisions (flags, labels) are compared exactly; the limited
+state to 1e-12; bf16 features bitwise.  MLP values: the GPU accumulates bf16
+products in FP32 on MFMA in its own order while the oracle accumulates in FP64
+and rounds the pre-activation to FP32, so a hidden activation near a bf16
+rounding tie can land on the neighbouring bf16 value (one bf16 ulp, 2^-8
+relative).  The logits must agree to 1e-4 of max|z| on at least 99.5 % of the
+samples and to 2e-2 everywhere; the batch gradient, where a few such samples
+average out, to 1e-3 of its max-norm."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1805_01443_amd import configs as W
+from paper_1805_01443_amd import dg
+
+pytestmark = pytest.mark.gpu
+
+
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+def ocfg(cfg):
+    return O.cfg(dataclasses.asdict(cfg))
+
+
+def ring_setup(nx=48, order=4, s0=-2.4, limiter=dg.LIMITER_MODAL_DECAY):
+    T = torch()
+    cfg = W.disc_ring(nx=nx, order=order).replace(limiter=limiter, limiter_s0=s0)
+    oc = ocfg(cfg)
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, "disc_ring", x=x, y=y)
+    h, u = dg.dg_init(cfg, prim)
+    T.cuda.synchronize()
+    return cfg, oc, h, u, O.project(oc, prim)
+
+
+def test_indicator_flags_labels_and_limited_state():
+    T = torch()
+    cfg, oc, h, u, uo = ring_setup()
+    # a state with sharp features: a few RK steps of the ring without limiting
+    u0 = uo.copy()
+    for k in range(3):
+        uo, _ = O.step(oc, uo, 0.01 * k, 2e-3, u0=u0)
+    ug = T.tensor(uo, device="cuda")
+    E = cfg.n_elem
+    fl = T.zeros(E, dtype=T.uint8, device="cuda")
+    ch = T.zeros(E, dtype=T.uint8, device="cuda")
+    sn = T.zeros(E, dtype=T.float32, device="cuda")
+    dg.dg_troubled(h, ug, apply=True, flags=fl, changed=ch, sensor=sn)
+    T.cuda.synchronize()
+    s = O.indicator(oc, uo)
+    assert np.max(np.abs(sn.cpu().numpy() - s.astype(np.float32))) <= 1e-6 * np.max(np.abs(s))
+    fo = s > cfg.limiter_s0
+    assert 0 < fo.sum() < E
+    assert np.array_equal(fl.cpu().numpy().astype(bool), fo)
+    ul, cho = O.minmod(oc, uo, u0, fo)
+    assert np.array_equal(ch.cpu().numpy().astype(bool), cho)
+    err = np.max(np.abs(ug.cpu().numpy() - ul)) / np.max(np.abs(ul))
+    assert err <= 1e-15
+    h.close()
+
+
+def test_limited_steps_parity():
+    T = torch()
+    cfg, oc, h, u, uo = ring_setup(nx=40, s0=-3.0)
+    u0 = uo.copy()
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    t = 0.0
+    for k in range(3):
+        dg.dg_rk_step(h, u, t_dev, 1e-3, None)
+        dg.dg_sync(h)
+        uo, _ = O.step_limited(oc, uo, t, 1e-3, u0, cfg.limiter_s0)
+        t += 1e-3
+        a = u.cpu().numpy()
+        err = max(np.max(np.abs(a[v] - uo[v])) / np.max(np.abs(uo[v])) for v in range(cfg.nvar))
+        print(f"[limited step {k}] rel err {err:.3e}", flush=True)
+        assert err <= 1e-12
+    h.close()
+
+
+def test_features_bitwise():
+    T = torch()
+    cfg, oc, h, u, uo = ring_setup(nx=24)
+    E = cfg.n_elem
+    f = T.zeros((E, 64), dtype=T.int16, device="cuda")
+    dg.dg_mlp_features(h, u, f)
+    T.cuda.synchronize()
+    sc = dg.dg_mlp_feature_scales(h)
+    means = uo[:, 0, :]
+    assert np.allclose(sc, np.sqrt(np.mean(means ** 2, axis=1)), rtol=1e-14, atol=0)
+    fo = O.mlp_features(oc, uo, sc)
+    fo16 = np.array([O.bf16(v) for v in fo.ravel()]).reshape(fo.shape)
+    got = (f.cpu().numpy().astype(np.int32) & 0xFFFF).astype(np.uint32) << 16
+    got = got.view(np.float32).astype(np.float64)
+    assert np.array_equal(got, fo16)
+    h.close()
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(dg.MLP_NPARAM)
+    p[:2048] = rng.normal(0, 1 / 8, 2048)
+    p[2048:2080] = rng.normal(0, 0.1, 32)
+    p[2080:3104] = rng.normal(0, 1 / np.sqrt(32), 1024)
+    p[3104:3136] = rng.normal(0, 0.1, 32)
+    p[3136:3168] = rng.normal(0, 1 / np.sqrt(32), 32)
+    p[3168] = 0.05
+    return p.astype(np.float32).astype(np.float64)
+
+
+def _bf16_rows(rng, n):
+    x = rng.normal(0, 1, (n, 64))
+    x16 = np.array([O.bf16(v) for v in x.ravel()]).reshape(x.shape)
+    bits = (x16.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+    return x16, bits
+
+
+def test_mlp_forward_and_gradient_against_oracle():
+    T = torch()
+    cfg, oc, h, u, uo = ring_setup(nx=8, limiter=dg.LIMITER_NONE)
+    rng = np.random.default_rng(7)
+    p = _params(7)
+    dg.dg_mlp_params(h, set_params=p)
+    n = 1000
+    x16, bits = _bf16_rows(rng, n)
+    y = (rng.random(n) < 0.3).astype(np.float64)
+    xf = T.tensor(bits, device="cuda")
+    z = T.zeros(n, dtype=T.float32, device="cuda")
+    dg.dg_mlp_forward(h, xf, n, z)
+    T.cuda.synchronize()
+    zo, _, _ = O.mlp_forward(p, x16, bf16=True)
+    d = np.abs(z.cpu().numpy() - zo) / np.max(np.abs(zo))
+    print(f"[mlp forward] max rel {d.max():.2e}, 99.5% {np.quantile(d, 0.995):.2e}", flush=True)
+    assert np.quantile(d, 0.995) <= 1e-4 and d.max() <= 2e-2
+    g = T.zeros(dg.MLP_NPARAM, dtype=T.float32, device="cuda")
+    loss = T.zeros(1, dtype=T.float32, device="cuda")
+    yl = T.tensor(y, dtype=T.float32, device="cuda")
+    dg.dg_mlp_train_step(h, xf, yl, n, pos_weight=2.5, lr=0.0, loss=loss, grad=g)
+    T.cuda.synchronize()
+    lo, go = O.mlp_loss_grad(p, x16, y, pos_weight=2.5, bf16=True)
+    ge = np.max(np.abs(g.cpu().numpy() - go)) / np.max(np.abs(go))
+    print(f"[mlp grad] rel max-norm err {ge:.2e}, loss {loss.item():.6f} vs {lo:.6f}", flush=True)
+    assert ge <= 1e-3 and abs(loss.item() - lo) <= 1e-4 * abs(lo)
+    # parameters unchanged with lr = 0
+    assert np.array_equal(dg.dg_mlp_params(h, get=True), p.astype(np.float32))
+    # one Adam step equals the oracle's Adam applied to the GPU gradient
+    dg.dg_mlp_train_step(h, xf, yl, n, pos_weight=2.5, lr=1e-2, grad=g)
+    T.cuda.synchronize()
+    p1, _, _ = O.adam(p, g.cpu().numpy().astype(np.float64), np.zeros_like(p), np.zeros_like(p), 1, lr=1e-2)
+    got = dg.dg_mlp_params(h, get=True).astype(np.float64)
+    assert np.max(np.abs(got - p1)) <= 1e-6
+    h.close()
+
+
+def test_mlp_training_reduces_loss_on_a_separable_problem():
+    T = torch()
+    cfg, oc, h, u, uo = ring_setup(nx=8, limiter=dg.LIMITER_NONE)
+    rng = np.random.default_rng(11)
+    dg.dg_mlp_params(h, set_params=_params(11))
+    n = 4096
+    x16, bits = _bf16_rows(rng, n)
+    y = (x16[:, 3] + 0.5 * x16[:, 17] > 0.2).astype(np.float32)
+    xf = T.tensor(bits, device="cuda")
+    yl = T.tensor(y, device="cuda")
+    loss = T.zeros(1, dtype=T.float32, device="cuda")
+    hist = []
+    for it in range(300):
+        dg.dg_mlp_train_step(h, xf, yl, n, pos_weight=1.0, lr=3e-3, loss=loss)
+        if it % 50 == 0 or it == 299:
+            hist.append(loss.item())
+    print("[mlp train] loss", hist, flush=True)
+    assert hist[-1] < 0.5 * hist[0]
+    h.close()
