@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
+    ap.add_argument("--seed", type=int, default=None,
+                    help="seeded disc: Sigma0 and 1e-4 density noise from the seed, q = 3e-5")
+    ap.add_argument("--sweep", action="store_true",
+                    help="orders 2..5 at --nx (FP64): per-order throughput and roofline fraction")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -135,6 +139,32 @@ def run_disc(cfg, prim, steps, warmup, profile):
     return res
 
 
+def disc_workload(a, order):
+    from paper_1805_01443_amd import configs as W
+    if a.seed is None:
+        cfg = W.disc(nx=a.nx, order=order)
+        return cfg, W.prim_for(cfg, "disc"), 1.0
+    cfg = W.disc_sweep(nx=a.nx, order=order)
+    return cfg, W.prim_for(cfg, "disc", seed=a.seed), W.sigma0_of(a.seed)
+
+
+def sweep(a):
+    """FP64 throughput per order at the chosen resolution."""
+    rows = []
+    for order in (2, 3, 4, 5):
+        cfg, prim, _ = disc_workload(a, order)
+        r = run_disc(cfg, prim, a.steps, a.warmup, profile=True)
+        state_bytes = cfg.nvar * order ** 2 * cfg.n_elem * 8
+        avg = r["stage_ms"] / 1e3 / max(r["launches"], 1)
+        ach = state_bytes * 8.0 / 3.0 / avg / 1e9
+        rows.append({"order": order, "p": order - 1, "dofs": cfg.n_elem * order ** 2,
+                     "dof_stage_per_s": cfg.n_elem * order ** 2 * 3 * a.steps / r["elapsed"],
+                     "ms_per_step": r["elapsed"] * 1e3 / a.steps, "stage_kernel_us": avg * 1e6,
+                     "hbm_GBps_alg": ach, "hbm_frac": ach / HBM_PEAK_GBPS})
+        del r
+    print(json.dumps({"sweep": rows, "nx": a.nx, "steps": a.steps, "seed": a.seed}), flush=True)
+
+
 def main():
     a = parse()
     if a.calibrate_copy:
@@ -150,8 +180,10 @@ def main():
     from paper_1805_01443_amd import dg
 
     torch.cuda.set_device(0)
-    cfg = W.disc(nx=a.nx, order=a.order)
-    prim = W.prim_for(cfg, "disc")
+    if a.sweep:
+        sweep(a)
+        return
+    cfg, prim, sigma0 = disc_workload(a, a.order)
     r64 = run_disc(cfg, prim, a.steps, a.warmup, profile=True)
     el = r64["elapsed"]
     dofs = W.dofs(cfg)
@@ -162,7 +194,7 @@ def main():
     alg_bytes_per_launch = state_bytes * 8.0 / 3.0
     avg_launch_s = r64["stage_ms"] / 1e3 / max(r64["launches"], 1)
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9
-    workload = f"disc{cfg.nx}_p{cfg.order - 1}_fp64"
+    workload = f"disc{cfg.nx}_p{cfg.order - 1}_fp64" + ("" if a.seed is None else f"_seed{a.seed}")
     traffic = measured_traffic(workload)
     out = {
         "metric": "DOF-stage updates/s (p=4, FP64) at parity 1e-12 vs FP64 oracle",
@@ -188,7 +220,7 @@ def main():
     }
     if not a.no_mixed:
         # the same workload in the mixed-precision deviation form
-        cm = cfg.replace(precision=dg.PRECISION_MIXED, sigma0=1.0)
+        cm = cfg.replace(precision=dg.PRECISION_MIXED, sigma0=sigma0)
         rm = run_disc(cm, prim, a.steps, a.warmup, profile=True)
         g64, gm = r64["torques"], rm["torques"]
         rho64 = r64["full"][0]

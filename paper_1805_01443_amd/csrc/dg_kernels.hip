@@ -23,6 +23,11 @@ namespace dgk {
 
 enum { CL_ISO = 0, CL_LOC = 1, CL_ADI = 2 };
 
+// The same tables in constant memory, for loops whose index is a run-time
+// (wave-uniform) value: entries come in through the scalar cache.
+__constant__ BasisTab c_basis[kMaxOrder + 1] = {make_basis(0), make_basis(1), make_basis(2),
+                                                make_basis(3), make_basis(4), make_basis(5)};
+
 template <int CL>
 struct NVar {
     static constexpr int value = CL == CL_ADI ? 4 : 3;
@@ -157,44 +162,51 @@ __device__ __forceinline__ void edge_term(const Geo& g, const double* __restrict
     const unsigned eoff = (unsigned)e * 8u;
     const unsigned noff = ((unsigned)jn * (unsigned)g.nx + (unsigned)in) * 8u;
     const unsigned pstride = (unsigned)E * 8u;
-    // the neighbour sees the shared edge on its opposite side; a fixed box
-    // edge takes the element's own initial trace on the same side
-    const bool same_side = fixed;
 
-    // collapse the normal degree at the edge: ci (own), co (exterior)
+    // collapse the normal degree at the edge: ci (own), co (exterior).  Waves
+    // without a fixed box edge take the lean path; the others select per lane
+    // between the neighbour (opposite side) and the own initial state (same side).
     double ci[NV][N], co[NV][N];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             ci[v][k] = 0.0;
             co[v][k] = 0.0;
         }
+    if (!wave_fixed) {
 #pragma unroll
-        for (int a = 0; a < N; ++a)
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int b = 0; b < N; ++b) {
-                const int m = v * NN + a * N + b;
-                double uo = ld64(ru, noff, (unsigned)m * pstride);
-                if (wave_fixed) {
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const int m = v * NN + a * N + b;
+                    const double uo = ld64(ru, noff, (unsigned)m * pstride);
+                    const double ui = sU[m * kWave];
+                    const int c = AX == 0 ? a : b, o = AX == 0 ? b : a;
+                    const double so = SGN < 0 ? B.pm[c] : B.pp[c];
+                    const double sx = SGN < 0 ? B.pp[c] : B.pm[c];
+                    ci[v][o] += so * ui;
+                    co[v][o] += sx * uo;
+                }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const int m = v * NN + a * N + b;
+                    const double un = ld64(ru, noff, (unsigned)m * pstride);
                     const double u0v = ld64(ru0, eoff, (unsigned)m * pstride);
-                    uo = fixed ? u0v : uo;
+                    const double ui = sU[m * kWave];
+                    const int c = AX == 0 ? a : b, o = AX == 0 ? b : a;
+                    const double so = SGN < 0 ? B.pm[c] : B.pp[c];
+                    const double sx = SGN < 0 ? B.pp[c] : B.pm[c];
+                    ci[v][o] += so * ui;
+                    co[v][o] += fixed ? so * u0v : sx * un;
                 }
-                const double ui = sU[m * kWave];
-                // own side value of the collapsed basis function, and the
-                // exterior element's (opposite side unless a fixed box edge)
-                if constexpr (AX == 0) {
-                    const double so = SGN < 0 ? B.pm[a] : B.pp[a];
-                    const double sx = SGN < 0 ? B.pp[a] : B.pm[a];
-                    ci[v][b] += so * ui;
-                    co[v][b] += (same_side ? so : sx) * uo;
-                } else {
-                    const double so = SGN < 0 ? B.pm[b] : B.pp[b];
-                    const double sx = SGN < 0 ? B.pp[b] : B.pm[b];
-                    ci[v][a] += so * ui;
-                    co[v][a] += (same_side ? so : sx) * uo;
-                }
-            }
     }
     double gl[NV][N];
 #pragma unroll
@@ -203,19 +215,15 @@ __device__ __forceinline__ void edge_term(const Geo& g, const double* __restrict
         for (int m = 0; m < N; ++m) gl[v][m] = 0.0;
 #pragma unroll 1
     for (int k = 0; k < N; ++k) {
-        // tables at edge point k, selected at run time so they live only here
+        // tables at edge point k (run-time index: scalar loads)
+        const BasisTab& CB = c_basis[N];
         double phk[N], wpk[N];
-        double xik = 0.0;
+        const double xik = CB.xi[k];
 #pragma unroll
-        for (int kk = 0; kk < N; ++kk)
-            if (kk == k) {
-                xik = B.xi[kk];
-#pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    phk[m] = B.phi[m][kk];
-                    wpk[m] = B.wphi[m][kk];
-                }
-            }
+        for (int m = 0; m < N; ++m) {
+            phk[m] = CB.phi[m][k];
+            wpk[m] = CB.wphi[m][k];
+        }
         double Ui[NV], Uo[NV], h[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -330,18 +338,15 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restr
 #pragma unroll 1
     for (int q = 0; q < N; ++q) {
         asm volatile("" ::: "memory");
-        double xiq = 0.0, wpq[N], wdpq[N], phq[N];
+        const BasisTab& CB = c_basis[N];
+        const double xiq = CB.xi[q];
+        double wpq[N], wdpq[N], phq[N];
 #pragma unroll
-        for (int qq = 0; qq < N; ++qq)
-            if (qq == q) {
-                xiq = B.xi[qq];
-#pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    wpq[a] = B.wphi[a][qq];
-                    wdpq[a] = B.wdphi[a][qq];
-                    phq[a] = B.phi[a][qq];
-                }
-            }
+        for (int a = 0; a < N; ++a) {
+            wpq[a] = CB.wphi[a][q];
+            wdpq[a] = CB.wdphi[a][q];
+            phq[a] = CB.phi[a][q];
+        }
         const double x = xc + 0.5 * g.dx * xiq;
         double c[NV][N];
 #pragma unroll
@@ -492,36 +497,45 @@ __device__ __forceinline__ void edge_term_dev(const Geo& g, const float* __restr
     const unsigned pstride = (unsigned)E * 8u;
     float ci[3][N], co[3][N];
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
+    for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             ci[v][k] = 0.0f;
             co[v][k] = 0.0f;
         }
+    if (!wave_fixed) {
 #pragma unroll
-        for (int a = 0; a < N; ++a)
+        for (int v = 0; v < 3; ++v)
 #pragma unroll
-            for (int b = 0; b < N; ++b) {
-                const int m = v * NN + a * N + b;
-                double uod = ld64(rdu, noff, (unsigned)m * pstride);
-                if (wave_fixed) {
-                    const double u0v = ld64(rdu0, eoff, (unsigned)m * pstride);
-                    uod = fixed ? u0v : uod;
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const int m = v * NN + a * N + b;
+                    const float uo = (float)ld64(rdu, noff, (unsigned)m * pstride);
+                    const float ui = sD[m * kWave];
+                    const int c = AX == 0 ? a : b, o = AX == 0 ? b : a;
+                    const float so = (float)(SGN < 0 ? B.pm[c] : B.pp[c]);
+                    const float sx = (float)(SGN < 0 ? B.pp[c] : B.pm[c]);
+                    ci[v][o] += so * ui;
+                    co[v][o] += sx * uo;
                 }
-                const float uo = (float)uod;
-                const float ui = sD[m * kWave];
-                if constexpr (AX == 0) {
-                    const float so = (float)(SGN < 0 ? B.pm[a] : B.pp[a]);
-                    const float sx = (float)(SGN < 0 ? B.pp[a] : B.pm[a]);
-                    ci[v][b] += so * ui;
-                    co[v][b] += (fixed ? so : sx) * uo;
-                } else {
-                    const float so = (float)(SGN < 0 ? B.pm[b] : B.pp[b]);
-                    const float sx = (float)(SGN < 0 ? B.pp[b] : B.pm[b]);
-                    ci[v][a] += so * ui;
-                    co[v][a] += (fixed ? so : sx) * uo;
+    } else {
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const int m = v * NN + a * N + b;
+                    const float un = (float)ld64(rdu, noff, (unsigned)m * pstride);
+                    const float u0v = (float)ld64(rdu0, eoff, (unsigned)m * pstride);
+                    const float ui = sD[m * kWave];
+                    const int c = AX == 0 ? a : b, o = AX == 0 ? b : a;
+                    const float so = (float)(SGN < 0 ? B.pm[c] : B.pp[c]);
+                    const float sx = (float)(SGN < 0 ? B.pp[c] : B.pm[c]);
+                    ci[v][o] += so * ui;
+                    co[v][o] += fixed ? so * u0v : sx * un;
                 }
-            }
     }
     float gl[3][N];
 #pragma unroll
@@ -530,19 +544,15 @@ __device__ __forceinline__ void edge_term_dev(const Geo& g, const float* __restr
         for (int m = 0; m < N; ++m) gl[v][m] = 0.0f;
 #pragma unroll 1
     for (int k = 0; k < N; ++k) {
-        // tables at edge point k, selected at run time so they live only here
+        // tables at edge point k (run-time index: scalar loads)
+        const BasisTab& CB = c_basis[N];
         float phk[N], wpk[N];
-        double xik = 0.0;
+        const double xik = CB.xi[k];
 #pragma unroll
-        for (int kk = 0; kk < N; ++kk)
-            if (kk == k) {
-                xik = B.xi[kk];
-#pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    phk[m] = (float)B.phi[m][kk];
-                    wpk[m] = (float)B.wphi[m][kk];
-                }
-            }
+        for (int m = 0; m < N; ++m) {
+            phk[m] = (float)CB.phi[m][k];
+            wpk[m] = (float)CB.wphi[m][k];
+        }
         float di[3], dd[3];
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
@@ -655,19 +665,15 @@ __global__ void __launch_bounds__(64) k_stage_dev(const Geo g, const double* __r
 #pragma unroll 1
     for (int q = 0; q < N; ++q) {
         asm volatile("" ::: "memory");
-        double xiq = 0.0;
+        const BasisTab& CB = c_basis[N];
+        const double xiq = CB.xi[q];
         float wpq[N], wdpq[N], phq[N];
 #pragma unroll
-        for (int qq = 0; qq < N; ++qq)
-            if (qq == q) {
-                xiq = B.xi[qq];
-#pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    wpq[a] = (float)B.wphi[a][qq];
-                    wdpq[a] = (float)B.wdphi[a][qq];
-                    phq[a] = (float)B.phi[a][qq];
-                }
-            }
+        for (int a = 0; a < N; ++a) {
+            wpq[a] = (float)CB.wphi[a][q];
+            wdpq[a] = (float)CB.wdphi[a][q];
+            phq[a] = (float)CB.phi[a][q];
+        }
         const double x = xc + 0.5 * g.dx * xiq;
         float c[3][N];
 #pragma unroll
