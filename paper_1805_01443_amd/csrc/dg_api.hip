@@ -133,6 +133,9 @@ void make_geo(const dg_config* c, Geo* g) {
     g->bc = c->bc;
     g->star = c->star;
     g->cs2 = c->cs * c->cs;
+    g->cs = c->cs;
+    g->rc2 = c->r_core * c->r_core;
+    g->irc = c->r_core > 0 ? 1.0 / c->r_core : 0.0;
     g->h2gm = c->h * c->h * c->gm;
     g->gamma = c->gamma;
     g->gm = c->gm;

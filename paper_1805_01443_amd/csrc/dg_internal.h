@@ -21,6 +21,8 @@ struct Geo {
     double idx, idy;   // 1/dx, 1/dy
     int closure, bc, star;
     double cs2;        // isothermal c_s^2
+    double cs;         // isothermal c_s
+    double rc2, irc;   // r_core^2, 1 / r_core
     double h2gm;       // h^2 GM (locally isothermal)
     double gamma;
     double gm, r_core, rc3inv;  // GM / r_core^3

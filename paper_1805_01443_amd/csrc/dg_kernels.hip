@@ -85,6 +85,28 @@ __device__ __forceinline__ void pressure(const Geo& g, const double* U, double i
     }
 }
 
+// Reciprocal and inverse square root for the stage kernel: the hardware
+// estimate refined by two Newton steps (a few ulp at most; operands are normal
+// numbers), about half the instructions of the IEEE-rounded sequences.
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+__device__ __forceinline__ double rsq64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// locally isothermal c_s^2 at a point with 1/r = ir (r^2 = r2)
+__device__ __forceinline__ double cs2_loc(const Geo& g, double r2, double ir) {
+    return g.h2gm * (r2 > g.rc2 ? ir : g.irc);
+}
+
 // gradient of the stellar (harmonic core inside r_core, point mass outside)
 // plus softened planet potential
 __device__ __forceinline__ void grad_phi(const Geo& g, double x, double y, double xp, double yp,
@@ -112,10 +134,26 @@ template <int CL, int AX, int SGN>
 __device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const double* Uo, double x,
                                         double y, double* h) {
     constexpr int NV = NVar<CL>::value;
-    const double ii = 1.0 / Ui[0], io = 1.0 / Uo[0];
+    const double ii = rcp64(Ui[0]), io = rcp64(Uo[0]);
     double pi, ci, po, co;
-    pressure<CL>(g, Ui, ii, x, y, pi, ci);
-    pressure<CL>(g, Uo, io, x, y, po, co);
+    if constexpr (CL == CL_ISO) {
+        pi = g.cs2 * Ui[0];
+        po = g.cs2 * Uo[0];
+        ci = co = g.cs;
+    } else if constexpr (CL == CL_LOC) {
+        const double r2 = x * x + y * y;
+        const double cs2 = cs2_loc(g, r2, rsq64(r2));
+        pi = cs2 * Ui[0];
+        po = cs2 * Uo[0];
+        ci = co = cs2 * rsq64(cs2);
+    } else {
+        const double gm1 = g.gamma - 1.0;
+        pi = gm1 * (Ui[3] - 0.5 * (Ui[1] * Ui[1] + Ui[2] * Ui[2]) * ii);
+        po = gm1 * (Uo[3] - 0.5 * (Uo[1] * Uo[1] + Uo[2] * Uo[2]) * io);
+        const double ti = g.gamma * pi * ii, to = g.gamma * po * io;
+        ci = ti * rsq64(ti);
+        co = to * rsq64(to);
+    }
     const double vni = SGN * Ui[1 + AX] * ii;
     const double vno = SGN * Uo[1 + AX] * io;
     double Fi[NV], Fo[NV];
@@ -327,11 +365,16 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restr
             }
             R[0][a * N + b] += g.rdx2 * sx + g.rdy2 * sy;
         }
+    if (a0 != 0.0) {
 #pragma unroll
-    for (int m = 0; m < NN; ++m) {
-        const unsigned po = (unsigned)m * pstride;
-        const double base = a1 * sU[m * kWave] + a2 * R[0][m];
-        st64(rout, eoff, po, a0 != 0.0 ? a0 * ld64(run, eoff, po) + base : base);
+        for (int m = 0; m < NN; ++m) {
+            const unsigned po = (unsigned)m * pstride;
+            st64(rout, eoff, po, a0 * ld64(run, eoff, po) + (a1 * sU[m * kWave] + a2 * R[0][m]));
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < NN; ++m)
+            st64(rout, eoff, (unsigned)m * pstride, a1 * sU[m * kWave] + a2 * R[0][m]);
     }
 
     // momentum (and energy): volume integrals one Gauss column xi_q at a time
@@ -377,12 +420,31 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restr
                 W[v] = s;
             }
             const double y = yc + 0.5 * g.dy * B.xi[r];
-            const double inv = 1.0 / W[0];
-            double p, cs;
-            pressure<CL>(g, W, inv, x, y, p, cs);
+            const double inv = rcp64(W[0]);
+            // one 1/r for the locally isothermal pressure and the stellar pull
+            const double r2 = x * x + y * y;
+            const double ir = (CL == CL_LOC || g.star) ? rsq64(r2) : 0.0;
+            double p;
+            if constexpr (CL == CL_ISO)
+                p = g.cs2 * W[0];
+            else if constexpr (CL == CL_LOC)
+                p = cs2_loc(g, r2, ir) * W[0];
+            else
+                p = (g.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) * inv);
             const double vx = W[1] * inv, vy = W[2] * inv;
-            double gx, gy;
-            grad_phi(g, x, y, xp, yp, gx, gy);
+            double gx = 0.0, gy = 0.0;
+            if (g.star) {
+                const double k = r2 < g.rc2 ? g.rc3inv : g.gm * ir * ir * ir;
+                gx = k * x;
+                gy = k * y;
+            }
+            if (g.q > 0.0) {
+                const double dx = x - xp, dy = y - yp;
+                const double id = rsq64(dx * dx + dy * dy + g.eps2);
+                const double k = g.q * id * id * id;
+                gx += k * dx;
+                gy += k * dy;
+            }
             double fx[NV], sy[NV], fy[NV];
             fx[1] = W[1] * vx + p;
             fy[1] = W[1] * vy;
@@ -415,14 +477,21 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restr
     }
 
     // RK stage combination (Shu-Osher form of SSP(3,3)) or plain L(u)
+    if (a0 != 0.0) {
 #pragma unroll
-    for (int v = 1; v < NV; ++v)
+        for (int v = 1; v < NV; ++v)
 #pragma unroll
-        for (int m = 0; m < NN; ++m) {
-            const unsigned po = (unsigned)(v * NN + m) * pstride;
-            const double base = a1 * sU[(v * NN + m) * kWave] + a2 * R[v][m];
-            st64(rout, eoff, po, a0 != 0.0 ? a0 * ld64(run, eoff, po) + base : base);
-        }
+            for (int m = 0; m < NN; ++m) {
+                const unsigned po = (unsigned)(v * NN + m) * pstride;
+                st64(rout, eoff, po, a0 * ld64(run, eoff, po) + (a1 * sU[(v * NN + m) * kWave] + a2 * R[v][m]));
+            }
+    } else {
+#pragma unroll
+        for (int v = 1; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NN; ++m)
+                st64(rout, eoff, (unsigned)(v * NN + m) * pstride, a1 * sU[(v * NN + m) * kWave] + a2 * R[v][m]);
+    }
 }
 
 // ------------------------------------------------------------------ deviation form
@@ -659,7 +728,10 @@ __global__ void __launch_bounds__(64) k_stage_dev(const Geo g, const double* __r
         const unsigned po = (unsigned)m * pstride;
         const double L = (double)ld32(rleq, eoff4, (unsigned)m * pstride4) + (double)R[0][m];
         const double base = a1 * ld64(rdu, eoff, po) + a2 * L;
-        st64(rout, eoff, po, a0 != 0.0 ? a0 * ld64(rdun, eoff, po) + base : base);
+        if (a0 != 0.0)
+            st64(rout, eoff, po, a0 * ld64(rdun, eoff, po) + base);
+        else
+            st64(rout, eoff, po, base);
     }
 
 #pragma unroll 1
@@ -747,7 +819,10 @@ __global__ void __launch_bounds__(64) k_stage_dev(const Geo g, const double* __r
             const unsigned po = (unsigned)(v * NN + m) * pstride;
             const double L = (double)ld32(rleq, eoff4, (unsigned)(v * NN + m) * pstride4) + (double)R[v][m];
             const double base = a1 * ld64(rdu, eoff, po) + a2 * L;
-            st64(rout, eoff, po, a0 != 0.0 ? a0 * ld64(rdun, eoff, po) + base : base);
+            if (a0 != 0.0)
+                st64(rout, eoff, po, a0 * ld64(rdun, eoff, po) + base);
+            else
+                st64(rout, eoff, po, base);
         }
 }
 
@@ -1110,6 +1185,10 @@ hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim, dou
 
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0, double* out,
                         const StageCoeffs* sc, hipStream_t s) {
+    // arrays that a launch does not read still get a valid base (buffer
+    // resources are never built on a null pointer)
+    if (!un) un = u;
+    if (!u0) u0 = u;
     DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_stage<NT, CT>), dim3(g.tiles_total), dim3(64), 0,
                                                                   s, g, u, un, u0, out, sc)));
     return hipGetLastError();
@@ -1144,6 +1223,8 @@ hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const d
 
 hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double* dun, const double* du0,
                             const float* leq, double* out, const StageCoeffs* sc, hipStream_t s) {
+    if (!dun) dun = du;
+    if (!du0) du0 = du;
     DG_DISPATCH_N(n, hipLaunchKernelGGL((k_stage_dev<NT>), dim3(g.tiles_total), dim3(64), 0, s, g, du, dun, du0, leq,
                                         out, sc));
     return hipGetLastError();

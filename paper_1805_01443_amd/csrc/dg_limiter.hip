@@ -177,6 +177,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const unsigned short* __res
     for (long long tile = (long long)blockIdx.x * 4 + wave; tile < ntile; tile += (long long)gridDim.x * 4) {
         const long long sidx = tile * 16 + i;  // this lane's sample (column)
         const bool valid = sidx < n;
+        const long long sl = valid ? sidx : n - 1;  // loads stay in bounds on a ragged last tile
         // layer 1
         f32x4 c1[2];
 #pragma unroll
@@ -185,7 +186,10 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const unsigned short* __res
         for (int s = 0; s < 4; ++s) {
             bf16x4 b;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) b[k] = valid ? (short)x[sidx * kIn + 16 * s + 4 * gq + k] : (short)0;
+            for (int k = 0; k < 4; ++k) {
+                const short xv = (short)x[sl * kIn + 16 * s + 4 * gq + k];
+                b[k] = valid ? xv : (short)0;
+            }
 #pragma unroll
             for (int t = 0; t < 2; ++t) c1[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[t][s], b, c1[t], 0, 0, 0);
         }
