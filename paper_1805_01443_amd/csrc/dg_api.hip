@@ -241,9 +241,7 @@ hipError_t limit(dg_handle* h, double* u, bool last) {
                                     nullptr, h->s);
     const float th = (float)h->cfg.mlp_theta;
     const float zthr = std::log(th / (1.0f - th));  // sigmoid(z) > theta  <=>  z > logit(theta)
-    e = dgk::launch_features(h->n, h->nvar, h->g, u, h->scale_dev, h->feat, h->s);
-    if (e == hipSuccess)
-        e = dgk::launch_mlp_forward(h->feat, h->E, h->mlp, nullptr, nullptr, nullptr, h->flags, zthr, h->s);
+    e = dgk::launch_mlp_flags(h->g, u, h->scale_dev, h->mlp, h->flags, zthr, h->s);
     if (e == hipSuccess && cap && h->cap_mlp)
         e = hipMemcpyAsync(h->cap_mlp, h->flags, (size_t)h->E, hipMemcpyDeviceToDevice, h->s);
     if (e == hipSuccess)
@@ -335,7 +333,6 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     DG_ALLOC(h->scale_dev, sizeof(double) * 4);
     DG_ALLOC(h->flags, (size_t)h->E);
     DG_ALLOC(h->mlp, sizeof(float) * 3 * (size_t)dgk::mlp_nparam());
-    if (cfg->limiter == DG_LIMITER_LEARNED) DG_ALLOC(h->feat, sizeof(unsigned short) * 64 * (size_t)h->E);
     if (h->dev) {
         DG_ALLOC(h->eq, state_bytes);
         DG_ALLOC(h->du0, state_bytes);

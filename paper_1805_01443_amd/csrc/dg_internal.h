@@ -81,6 +81,8 @@ hipError_t launch_features(int n, int nvar, const Geo& g, const double* u, const
                            hipStream_t s);
 hipError_t launch_mlp_forward(const unsigned short* x, long long n, const float* par, float* z, float* h1, float* h2,
                               unsigned char* flags, float zthr, hipStream_t s);
+hipError_t launch_mlp_flags(const Geo& g, const double* u, const double* scale, const float* par,
+                            unsigned char* flags, float zthr, hipStream_t s);
 int mlp_delta_blocks(long long n);
 int mlp_nparam();
 hipError_t launch_mlp_backward(const unsigned short* x, const float* y, long long n, float pos_weight,

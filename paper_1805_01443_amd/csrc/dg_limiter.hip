@@ -243,6 +243,93 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const unsigned short* __res
     }
 }
 
+// Learned-indicator flags straight from the state (order 4, four variables:
+// 64 features): the same MLP as k_mlp_forward, but each lane builds its B
+// fragments from the modes it loads (K step s = variable s, rows 4g..4g+3 =
+// modes), so no feature array is written or read.  flag[e] = z > zthr.
+__global__ void __launch_bounds__(256) k_mlp_flags(const Geo g, const double* __restrict__ u,
+                                                   const double* __restrict__ scale, const float* __restrict__ par,
+                                                   unsigned char* __restrict__ flag_out, float zthr) {
+    constexpr int NN = 16;
+    __shared__ unsigned short sW1[kH * kIn], sW2[kH * kH];
+    for (int k = threadIdx.x; k < kH * kIn; k += 256) sW1[k] = f2bf(par[kW1 + k]);
+    for (int k = threadIdx.x; k < kH * kH; k += 256) sW2[k] = f2bf(par[kW2 + k]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, gq = lane >> 4;
+    bf16x4 a1[2][4], a2[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a1[t][s][k] = (short)sW1[(16 * t + i) * kIn + 16 * s + 4 * gq + k];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a2[t][s][k] = (short)sW2[(16 * t + i) * kH + 16 * s + 4 * gq + k];
+    }
+    float b1v[2][4], b2v[2][4], w3v[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int row = 16 * t + 4 * gq + k;
+            b1v[t][k] = par[kB1 + row];
+            b2v[t][k] = par[kB2 + row];
+            w3v[t][k] = bf2f(f2bf(par[kW3 + row]));
+        }
+    const float b3 = par[kB3];
+    const long long E = g.E;
+    const long long ntile = (E + 15) / 16;
+    for (long long tile = (long long)blockIdx.x * 4 + wave; tile < ntile; tile += (long long)gridDim.x * 4) {
+        const long long e = tile * 16 + i;
+        const bool valid = e < E;
+        const long long el = valid ? e : E - 1;  // in-bounds loads on a ragged last tile
+        f32x4 c1[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) c1[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const double d = fabs(u[(long long)s * NN * E + el]) + scale[s];
+            bf16x4 b;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const short fv = (short)f2bf((float)(u[(long long)(s * NN + 4 * gq + k) * E + el] / d));
+                b[k] = valid ? fv : (short)0;
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t) c1[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[t][s], b, c1[t], 0, 0, 0);
+        }
+        bf16x4 hb[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float zz = c1[t][k] + b1v[t][k];
+                hb[t][k] = (short)f2bf(zz > 0.f ? zz : 0.f);
+            }
+        f32x4 c2[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) c2[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) c2[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[t][s], hb[s], c2[t], 0, 0, 0);
+        float part = 0.f;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float zz = c2[t][k] + b2v[t][k];
+                part += w3v[t][k] * bf2f(f2bf(zz > 0.f ? zz : 0.f));
+            }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (valid && gq == 0) flag_out[e] = (part + b3) > zthr ? 1 : 0;
+    }
+}
+
 // Backward pass of the BCE-with-logits loss (mean over n, positives weighted
 // by pos_weight) through the forward values saved by k_mlp_forward (bf16
 // rounding treated as identity), FP32.  k_mlp_delta: one thread per sample,
@@ -373,6 +460,16 @@ hipError_t launch_mlp_forward(const unsigned short* x, long long n, const float*
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(256), 0, s, x, n, par, z, h1, h2, flags, zthr);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_flags(const Geo& g, const double* u, const double* scale, const float* par,
+                            unsigned char* flags, float zthr, hipStream_t s) {
+    const long long ntile = (g.E + 15) / 16;
+    long long blocks = (ntile + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_mlp_flags, dim3((unsigned)blocks), dim3(256), 0, s, g, u, scale, par, flags, zthr);
     return hipGetLastError();
 }
 

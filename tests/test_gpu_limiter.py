@@ -177,3 +177,32 @@ def test_mlp_training_reduces_loss_on_a_separable_problem():
     print("[mlp train] loss", hist, flush=True)
     assert hist[-1] < 0.5 * hist[0]
     h.close()
+
+
+def test_fused_learned_flags_match_features_then_forward():
+    """The learned limiter's fused kernel (features built in the MFMA fragments)
+    flags exactly the elements whose logits from dg_mlp_forward on the captured
+    features exceed logit(theta)."""
+    T = torch()
+    theta = 0.3
+    cfg, oc, h, u, uo = ring_setup(nx=40, limiter=dg.LIMITER_LEARNED)
+    h.close()
+    cfg = cfg.replace(mlp_theta=theta)
+    h, u = dg.dg_init(cfg, W.prim_for(cfg, "disc_ring", x=O.nodes(oc)[0], y=O.nodes(oc)[1]))
+    dg.dg_mlp_params(h, set_params=_params(3))
+    E = cfg.n_elem
+    feat = T.zeros((E, 64), dtype=T.int16, device="cuda")
+    mf = T.zeros(E, dtype=T.uint8, device="cuda")
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dg.dg_rk_step(h, u, t_dev, 1e-3, None)
+    dg.dg_capture(h, feat=feat, mlp_flags=mf)
+    dg.dg_rk_step(h, u, t_dev, 1e-3, None)
+    z = T.zeros(E, dtype=T.float32, device="cuda")
+    dg.dg_mlp_forward(h, feat, E, z)
+    dg.dg_sync(h)
+    zthr = np.log(np.float32(theta) / (np.float32(1.0) - np.float32(theta)))
+    ref = (z.cpu().numpy() > np.float32(zthr)).astype(np.uint8)
+    got = mf.cpu().numpy()
+    assert 0 < ref.sum() < E, "pick parameters that flag some but not all elements"
+    assert np.array_equal(got, ref)
+    h.close()
