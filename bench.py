@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
+    ap.add_argument("--no-limited", action="store_true", help="skip the modal vs learned limiter comparison")
+    ap.add_argument("--ring-nx", type=int, default=1024)
+    ap.add_argument("--ring-steps", type=int, default=200)
     ap.add_argument("--seed", type=int, default=None,
                     help="seeded disc: Sigma0 and 1e-4 density noise from the seed, q = 3e-5")
     ap.add_argument("--sweep", action="store_true",
@@ -161,6 +164,55 @@ def run_disc(cfg, prim, steps, warmup, profile):
     return res
 
 
+def run_limited(a):
+    """The ring workload (order 4, adiabatic, 1024^2 by default) with the plain
+    modal-decay indicator and with the learned indicator, both followed by
+    minmod: step rate of each and the density difference after the timed steps."""
+    import torch
+
+    from paper_1805_01443_amd import configs as W
+    from paper_1805_01443_amd import dg, learned
+    lp = learned.load_params()
+    if lp is None:
+        params, theta, s0, src = learned.init_params(0), 0.5, learned.default_s0(4), "untrained (He init)"
+    else:
+        params, theta, s0, src = lp["params"], lp["theta"], lp["s0"], "trained, " + learned.PARAMS_FILE.split(os.sep)[-1]
+    out, rho = {}, {}
+    for name, lim in (("modal", dg.LIMITER_MODAL_DECAY), ("learned", dg.LIMITER_LEARNED)):
+        cfg = learned.ring_config(a.ring_nx, limiter=lim, theta=theta, s0=s0)
+        prim = W.prim_for(cfg, "disc_ring", seed=0)
+        h, u = dg.dg_init(cfg, prim)
+        if lim == dg.LIMITER_LEARNED:
+            dg.dg_mlp_params(h, set_params=params)
+        t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for _ in range(a.warmup):
+            dg.dg_rk_step(h, u, t_dev, 0.0, None)
+        dg.dg_sync(h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.ring_steps):
+            dg.dg_rk_step(h, u, t_dev, 0.0, None)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dg.dg_sync(h)
+        fl = torch.zeros(cfg.n_elem, dtype=torch.uint8, device="cuda")
+        dg.dg_troubled(h, u, apply=False, flags=fl)
+        dofs = cfg.n_elem * cfg.order ** 2
+        out[name] = {"value": dofs * 3 * a.ring_steps / el, "unit": "DOF-stage/s",
+                     "ms_per_step": el * 1e3 / a.ring_steps, "sensor_flagged_at_end": int(fl.sum().item())}
+        rho[name] = u[0].clone()
+        h.close()
+    out["learned_speedup_vs_modal"] = out["modal"]["ms_per_step"] / out["learned"]["ms_per_step"]
+    out["density_rel_L2_diff"] = float(((rho["learned"] - rho["modal"]) ** 2).sum().sqrt()
+                                       / (rho["modal"] ** 2).sum().sqrt())
+    out["workload"] = f"ring{a.ring_nx}_p3_adiabatic_fp64_seed0"
+    out["steps"] = a.ring_steps
+    out["network"] = src
+    out["theta"] = theta
+    out["s0"] = s0
+    return out
+
+
 def disc_workload(a, order):
     from paper_1805_01443_amd import configs as W
     if a.seed is None:
@@ -259,6 +311,8 @@ def main():
                       "note": "FP32 deviation arithmetic about the projected equilibrium; FP64 state, "
                               "stage combination, damping, dt and torque"}}
     del r64
+    if not a.no_limited:
+        out.setdefault("forms", {})["limited"] = run_limited(a)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, prim)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import time
 
 import numpy as np
@@ -36,6 +37,27 @@ def default_s0(order: int) -> float:
 def ring_config(nx, order=4, limiter=dg.LIMITER_MODAL_DECAY, theta=0.5, s0=None):
     return W.disc_ring(nx=nx, order=order).replace(
         limiter=limiter, limiter_s0=default_s0(order) if s0 is None else s0, mlp_theta=theta)
+
+
+PARAMS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mlp_ring_p3.json")
+
+
+def load_params(path=PARAMS_FILE):
+    """Trained parameters, flag threshold and sensor threshold from a JSON file
+    written by ``main`` (``--params-out``); None if there is none."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    p = np.asarray(d["params"], dtype=np.float32)
+    if p.size != dg.MLP_NPARAM:
+        raise ValueError(f"{path}: {p.size} parameters, expected {dg.MLP_NPARAM}")
+    return {"params": p, "theta": float(d["theta"]), "s0": float(d["s0"]), "meta": d.get("meta", {})}
+
+
+def save_params(path, params, theta, s0, meta):
+    with open(path, "w") as f:
+        json.dump({"params": [float(v) for v in params], "theta": theta, "s0": s0, "meta": meta}, f)
 
 
 def init_params(seed=0):
@@ -238,7 +260,9 @@ def main(argv=None):
     with open(a.out, "w") as f:
         json.dump(res, f, indent=1)
     if a.params_out:
-        np.save(a.params_out, params)
+        save_params(a.params_out, params, theta, default_s0(4),
+                    {k: res[k] for k in ("nx", "steps", "every", "train_seeds", "val_seed", "test_seed",
+                                         "train_samples", "train_positives", "epochs", "val_miss")})
 
 
 if __name__ == "__main__":
