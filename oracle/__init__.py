@@ -38,7 +38,7 @@ class _Cfg(C.Structure):
         ("bc", C.c_int), ("star", C.c_int), ("gm", C.c_double), ("r_core", C.c_double),
         ("q", C.c_double), ("eps", C.c_double), ("rp", C.c_double), ("phi0", C.c_double),
         ("damping", C.c_int), ("rd_in", C.c_double), ("rd_out", C.c_double),
-        ("cfl", C.c_double),
+        ("cfl", C.c_double), ("rk", C.c_int),
     ]
 
 
@@ -66,6 +66,8 @@ def lib():
         _lib.or_rk_butcher.argtypes = [C.c_int, P, P, P, _RHS_FN, C.c_void_p, C.c_long, P,
                                        C.c_double, C.c_double]
         _lib.or_ssprk3_tableau.argtypes = [P, P, P]
+        _lib.or_rk_tableau.argtypes = [C.c_int, P, P, P]
+        _lib.or_rk_tableau.restype = C.c_int
         _lib.or_step.argtypes = [cp, P, C.c_double, C.c_double, P]
         _lib.or_step.restype = C.c_double
         _lib.or_damp.argtypes = [cp, P, P, C.c_double]
@@ -90,7 +92,7 @@ def lib():
 
 _DEFAULTS = dict(n=3, nvar=3, nx=8, ny=8, x0=0.0, x1=1.0, y0=0.0, y1=1.0, closure=0, cs=1.0,
                  h=0.05, gamma=1.4, bc=0, star=0, gm=1.0, r_core=0.4, q=0.0, eps=0.03,
-                 rp=1.0, phi0=0.0, damping=0, rd_in=0.4, rd_out=2.3, cfl=0.2)
+                 rp=1.0, phi0=0.0, damping=0, rd_in=0.4, rd_out=2.3, cfl=0.2, rk=0)
 
 
 def cfg(fields=None, **kw):
@@ -183,6 +185,18 @@ def ssprk3_tableau():
     cc = np.zeros(3)
     lib().or_ssprk3_tableau(_p(A), _p(b), _p(cc))
     return A.reshape(3, 3), b, cc
+
+
+def rk_tableau(kind):
+    """(A [s, s], b [s], c [s]) of an Appendix A table (0 SSP(3,3), 1 SSP(2,2),
+    2 SSP(5,4), 3 Cash-Karp)."""
+    A = np.zeros(36)
+    b = np.zeros(6)
+    cc = np.zeros(6)
+    s = lib().or_rk_tableau(int(kind), _p(A), _p(b), _p(cc))
+    if s < 0:
+        raise ValueError(f"unknown RK table {kind}")
+    return A.reshape(6, 6)[:s, :s].copy(), b[:s].copy(), cc[:s].copy()
 
 
 def rk_butcher(A, b, cc, f, u, t, dt_):

@@ -448,14 +448,89 @@ static void dg_rhs_cb(void *ctx, double t, const double *u, double *k)
     or_rhs(d->c, t, u, d->u0, k);
 }
 
+/* The other tables of Appendix A.  SSP(2,2) is printed with a_21 = c_2 = 1/2
+ * and b = (1/2, 1/2), which is first order only (b.c = 1/4); the two-stage
+ * SSP scheme of order two is Heun's, a_21 = c_2 = 1.  The five-stage table
+ * (captioned RK(4,5): fourth order, five stages) and the Cash-Karp table are
+ * taken as printed; Cash-Karp advances with its fifth-order weights. */
+int or_rk_tableau(int kind, double *A, double *b, double *cc)
+{
+    for (int i = 0; i < 36; ++i) A[i] = 0.0;
+    for (int i = 0; i < 6; ++i) b[i] = cc[i] = 0.0;
+    if (kind == 0) {
+        double A3[9];
+        or_ssprk3_tableau(A3, b, cc);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) A[i * 6 + j] = A3[i * 3 + j];
+        return 3;
+    }
+    if (kind == 1) {
+        A[1 * 6 + 0] = 1.0;
+        b[0] = 0.5;
+        b[1] = 0.5;
+        cc[1] = 1.0;
+        return 2;
+    }
+    if (kind == 2) {
+        static const double a[5][4] = {
+            {0.0, 0.0, 0.0, 0.0},
+            {0.39175222700392, 0.0, 0.0, 0.0},
+            {0.21766909633821, 0.36841059262959, 0.0, 0.0},
+            {0.08269208670950, 0.13995850206999, 0.25189177424738, 0.0},
+            {0.06796628370320, 0.11503469844438, 0.20703489864929, 0.54497475021237}};
+        static const double bb[5] = {0.14681187618661, 0.24848290924556, 0.10425883036650,
+                                     0.27443890091960, 0.22600748319395};
+        static const double c5[5] = {0.0, 0.39175222700392, 0.58607968896779, 0.47454236302687,
+                                     0.93501063100924};
+        for (int i = 0; i < 5; ++i) {
+            for (int j = 0; j < 4; ++j) A[i * 6 + j] = a[i][j];
+            b[i] = bb[i];
+            cc[i] = c5[i];
+        }
+        return 5;
+    }
+    if (kind == 3) {
+        A[1 * 6 + 0] = 1.0 / 5.0;
+        A[2 * 6 + 0] = 3.0 / 40.0;
+        A[2 * 6 + 1] = 9.0 / 40.0;
+        A[3 * 6 + 0] = 3.0 / 10.0;
+        A[3 * 6 + 1] = -9.0 / 10.0;
+        A[3 * 6 + 2] = 6.0 / 5.0;
+        A[4 * 6 + 0] = -11.0 / 54.0;
+        A[4 * 6 + 1] = 5.0 / 2.0;
+        A[4 * 6 + 2] = -70.0 / 27.0;
+        A[4 * 6 + 3] = 35.0 / 27.0;
+        A[5 * 6 + 0] = 1631.0 / 55296.0;
+        A[5 * 6 + 1] = 175.0 / 512.0;
+        A[5 * 6 + 2] = 575.0 / 13824.0;
+        A[5 * 6 + 3] = 44275.0 / 110592.0;
+        A[5 * 6 + 4] = 253.0 / 4096.0;
+        b[0] = 37.0 / 378.0;
+        b[2] = 250.0 / 621.0;
+        b[3] = 125.0 / 594.0;
+        b[5] = 512.0 / 1771.0;
+        cc[1] = 1.0 / 5.0;
+        cc[2] = 3.0 / 10.0;
+        cc[3] = 3.0 / 5.0;
+        cc[4] = 1.0;
+        cc[5] = 7.0 / 8.0;
+        return 6;
+    }
+    return -1;
+}
+
 double or_step(const or_cfg *c, double *u, double t, double dt_fixed, const double *u0)
 {
-    double A[9], b[3], cc[3];
-    or_ssprk3_tableau(A, b, cc);
+    double A6[36], b6[6], c6[6];
+    int s = or_rk_tableau(c->rk, A6, b6, c6);
+    if (s < 0) return -1.0;
+    double A[36];
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) A[i * s + j] = A6[i * 6 + j];
     double dt = dt_fixed > 0.0 ? dt_fixed : or_dt(c, u);
     dg_ctx d = {c, u0};
     long N = (long)c->nvar * c->n * c->n * c->nx * c->ny;
-    or_rk_butcher(3, A, b, cc, dg_rhs_cb, &d, N, u, t, dt);
+    or_rk_butcher(s, A, b6, c6, dg_rhs_cb, &d, N, u, t, dt);
     if (c->damping) or_damp(c, u, u0, dt);
     return dt;
 }

@@ -43,6 +43,7 @@ typedef struct {
     int damping;      /* 1: wave-killing zones */
     double rd_in, rd_out;
     double cfl;
+    int rk;           /* Appendix A table: 0 SSP(3,3), 1 SSP(2,2), 2 SSP(5,4), 3 Cash-Karp */
 } or_cfg;
 
 /* Sec. 2.2, eq. (3): Gauss-Legendre nodes (ascending) and weights on [-1,1]. */
@@ -69,7 +70,13 @@ void or_rk_butcher(int s, const double *A, const double *b, const double *cc,
                    or_rhs_fn f, void *ctx, long N, double *u, double t, double dt);
 /* SSP(3,3) tableau with c = (0, 1, 1/2) */
 void or_ssprk3_tableau(double *A9, double *b3, double *c3);
-/* one DG step: dt (CFL if dt_fixed <= 0), SSP-RK3 stages, damping; returns dt */
+/* Appendix A tables, A row-major s x s in a 6 x 6 array: kind 0 SSP(3,3)
+ * (c_3 = 1/2), 1 SSP(2,2) read as Heun (a_21 = c_2 = 1), 2 the five-stage
+ * fourth-order SSP table as printed, 3 Cash-Karp with its fifth-order
+ * weights.  Returns the number of stages s, or -1 for an unknown kind. */
+int or_rk_tableau(int kind, double *A36, double *b6, double *c6);
+/* one DG step: dt (CFL if dt_fixed <= 0), the RK stages of c->rk, damping;
+ * returns dt (-1 for an unknown c->rk) */
 double or_step(const or_cfg *c, double *u, double t, double dt_fixed, const double *u0);
 
 /* Sec. 5.1: wave-killing damping of rho, v (and T) towards the initial state */
