@@ -44,6 +44,11 @@ enum { DG_CLOSURE_ISOTHERMAL = 0, DG_CLOSURE_LOCALLY_ISOTHERMAL = 1, DG_CLOSURE_
 enum { DG_BC_PERIODIC = 0, DG_BC_FIXED_INITIAL = 1 };
 enum { DG_PRECISION_FP64 = 0, DG_PRECISION_MIXED = 1 };
 enum { DG_LIMITER_NONE = 0, DG_LIMITER_MODAL_DECAY = 1, DG_LIMITER_LEARNED = 2 };
+/* Runge-Kutta tables of Appendix A: SSP(3,3) with c_3 = 1/2 (the default),
+ * SSP(2,2) as Heun (a_21 = c_2 = 1), the five-stage fourth-order SSP table
+ * and the six-stage Cash-Karp table with its fifth-order weights, both as
+ * printed. */
+enum { DG_RK_SSP33 = 0, DG_RK_SSP22 = 1, DG_RK_SSP54 = 2, DG_RK_CASHKARP = 3 };
 
 /* Problem statement.  Units: G = M_* = r_p = 1 as in Sec. 5.1. */
 typedef struct dg_config {
@@ -68,6 +73,7 @@ typedef struct dg_config {
     int limiter;          /* DG_LIMITER_* */
     double limiter_s0;    /* modal-decay threshold on log10 of the top-mode energy share */
     double mlp_theta;     /* learned indicator: flag when sigmoid output > theta */
+    int rk;               /* DG_RK_* (0 = SSP(3,3)) */
 } dg_config;
 
 typedef struct dg_handle dg_handle;
@@ -105,13 +111,16 @@ int dg_full_state(dg_handle *h, const double *dev_dev, double *full_dev);
  * state layout, distinct.  Asynchronous on the handle's stream. */
 int dg_rhs(dg_handle *h, double t, const double *u_dev, double *rhs_dev);
 
-/* One SSP-RK3 step (Algorithm 1 with the SSP(3,3) tableau, c = (0, 1, 1/2))
- * of the state u_dev, in place.  t_dev is a device double holding t^n; it is
- * advanced to t^n + dt on the device.  dt = dt_fixed if dt_fixed > 0, else the
- * CFL step of Sec. 2.3 from the element means of u^n, reduced on the device.
- * dt_used_dev (device double, may be NULL) receives dt.  After the three
- * stages the limiter (if configured) has been applied per stage and the
- * damping once.  No host synchronisation. */
+/* One Runge-Kutta step (Algorithm 1) of the state u_dev, in place, with the
+ * table cfg->rk (default SSP(3,3), c = (0, 1, 1/2), run in Shu-Osher form;
+ * the other tables in Butcher form: stage derivatives k_i = L(y_i, t^n + c_i
+ * dt) kept in handle-owned buffers, y_i = u^n + dt sum_j a_ij k_j).  t_dev is
+ * a device double holding t^n; it is advanced to t^n + dt on the device.
+ * dt = dt_fixed if dt_fixed > 0, else the CFL step of Sec. 2.3 from the
+ * element means of u^n, reduced on the device.  dt_used_dev (device double,
+ * may be NULL) receives dt.  The limiter (if configured; SSP(3,3) only, else
+ * dg_init returns DG_EUNSUPPORTED) is applied to every stage state after its
+ * update, the damping once after the last stage.  No host synchronisation. */
 int dg_rk_step(dg_handle *h, double *u_dev, double *t_dev, double dt_fixed, double *dt_used_dev);
 
 /* z-torque of the disc on the planet, eq. (5) (G = 1, per unit planet mass),

@@ -29,8 +29,10 @@ struct dg_handle {
     double* eq = nullptr;   // deviation form: projected equilibrium u_eq (FP64)
     double* du0 = nullptr;  // deviation form: initial deviation (fixed exterior state)
     float* leq = nullptr;   // deviation form: L(u_eq) without the planet, FP32
-    double* ws1 = nullptr;  // SSP stage states u^(1), u^(2)
+    double* ws1 = nullptr;  // SSP stage states u^(1), u^(2); Butcher stage state y_i
     double* ws2 = nullptr;
+    dgk::RKTable tab{};     // Butcher tables (DG_RK_SSP54, DG_RK_CASHKARP)
+    double* kbuf = nullptr; // their stage derivatives k_1 .. k_s
     StageCoeffs* sc_rhs = nullptr;
     StepBlock* sb = nullptr;
     int* damp_list = nullptr;
@@ -103,6 +105,9 @@ int validate(const dg_config* c, std::string* why) {
         return (*why = "the deviation form is built for the locally isothermal disc with stellar gravity and sigma0 > 0",
                 DG_EUNSUPPORTED);
     if (c->limiter < DG_LIMITER_NONE || c->limiter > DG_LIMITER_LEARNED) return (*why = "unknown limiter", DG_EINVAL);
+    if (c->rk < DG_RK_SSP33 || c->rk > DG_RK_CASHKARP) return (*why = "unknown Runge-Kutta table", DG_EINVAL);
+    if (c->rk != DG_RK_SSP33 && c->limiter != DG_LIMITER_NONE)
+        return (*why = "limiters are built for the SSP(3,3) table", DG_EUNSUPPORTED);
     if (c->limiter != DG_LIMITER_NONE && c->precision != DG_PRECISION_FP64)
         return (*why = "limiters are built for the FP64 form", DG_EUNSUPPORTED);
     if (c->limiter == DG_LIMITER_LEARNED && !(c->order == 4 && c->nvar == 4))
@@ -249,6 +254,44 @@ hipError_t limit(dg_handle* h, double* u, bool last) {
     return e;
 }
 
+// Butcher tables of Appendix A run in Butcher form: the five-stage
+// fourth-order SSP table and Cash-Karp (fifth-order weights), as printed
+void butcher_table(int rk, dgk::RKTable* t) {
+    *t = dgk::RKTable{};
+    constexpr int M = dgk::kMaxStages;
+    if (rk == DG_RK_SSP54) {
+        const double a[5][4] = {{0, 0, 0, 0},
+                                {0.39175222700392, 0, 0, 0},
+                                {0.21766909633821, 0.36841059262959, 0, 0},
+                                {0.08269208670950, 0.13995850206999, 0.25189177424738, 0},
+                                {0.06796628370320, 0.11503469844438, 0.20703489864929, 0.54497475021237}};
+        const double b[5] = {0.14681187618661, 0.24848290924556, 0.10425883036650, 0.27443890091960,
+                             0.22600748319395};
+        const double c[5] = {0, 0.39175222700392, 0.58607968896779, 0.47454236302687, 0.93501063100924};
+        t->s = 5;
+        for (int i = 0; i < 5; ++i) {
+            for (int j = 0; j < 4; ++j) t->A[i * M + j] = a[i][j];
+            t->b[i] = b[i];
+            t->c[i] = c[i];
+        }
+    } else if (rk == DG_RK_CASHKARP) {
+        const double a[6][5] = {{0, 0, 0, 0, 0},
+                                {1.0 / 5, 0, 0, 0, 0},
+                                {3.0 / 40, 9.0 / 40, 0, 0, 0},
+                                {3.0 / 10, -9.0 / 10, 6.0 / 5, 0, 0},
+                                {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27, 0},
+                                {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592, 253.0 / 4096}};
+        const double b[6] = {37.0 / 378, 0, 250.0 / 621, 125.0 / 594, 0, 512.0 / 1771};
+        const double c[6] = {0, 1.0 / 5, 3.0 / 10, 3.0 / 5, 1, 7.0 / 8};
+        t->s = 6;
+        for (int i = 0; i < 6; ++i) {
+            for (int j = 0; j < 5; ++j) t->A[i * M + j] = a[i][j];
+            t->b[i] = b[i];
+            t->c[i] = c[i];
+        }
+    }
+}
+
 void release(dg_handle* h) {
     if (!h) return;
     drop_events(h);
@@ -267,6 +310,8 @@ void release(dg_handle* h) {
     (void)hipFree(h->feat);
     (void)hipFree(h->mlp);
     (void)hipFree(h->tr_ws);
+    (void)hipFree(h->kbuf);
+    h->kbuf = nullptr;
     h->u0 = h->ws1 = h->ws2 = h->eq = h->du0 = nullptr;
     h->leq = nullptr;
 }
@@ -333,6 +378,8 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     DG_ALLOC(h->scale_dev, sizeof(double) * 4);
     DG_ALLOC(h->flags, (size_t)h->E);
     DG_ALLOC(h->mlp, sizeof(float) * 3 * (size_t)dgk::mlp_nparam());
+    butcher_table(cfg->rk, &h->tab);
+    if (h->tab.s > 0) DG_ALLOC(h->kbuf, state_bytes * (size_t)h->tab.s);
     if (h->dev) {
         DG_ALLOC(h->eq, state_bytes);
         DG_ALLOC(h->du0, state_bytes);
@@ -409,7 +456,37 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     if (!(dt_fixed == dt_fixed)) return fail(h, DG_EINVAL, "dt_fixed is NaN");
     StepBlock* sb = h->sb;
     DG_HIP(h, dgk::launch_dt(h->n, h->g, u_dev, h->eq, sb, h->s), "CFL reduction");
-    DG_HIP(h, dgk::launch_step_begin(h->g, sb, t_dev, dt_fixed, dt_used_dev, h->s), "step begin");
+    if (h->tab.s > 0) {
+        // Butcher form: k_i = L(y_i), y_1 = u^n, y_i = u^n + dt sum_{j<i} a_ij k_j,
+        // u^{n+1} = u^n + dt sum_j b_j k_j (no limiter with these tables)
+        const int S = h->tab.s;
+        const long long N = (long long)h->nvar * h->n * h->n * h->E;
+        const double* k[dgk::kMaxStages];
+        for (int i = 0; i < S; ++i) k[i] = h->kbuf + (size_t)i * (size_t)N;
+        DG_HIP(h, dgk::launch_step_begin_table(h->g, sb, h->tab, t_dev, dt_fixed, dt_used_dev, h->s), "step begin");
+        for (int i = 0; i < S; ++i) {
+            const double* y = i == 0 ? u_dev : h->ws1;
+            DG_HIP(h, stage(h, y, nullptr, h->kbuf + (size_t)i * (size_t)N, &sb->st[i]), "stage");
+            if (i + 1 < S) {
+                DG_HIP(h, dgk::launch_rk_combine(u_dev, k, i + 1, &sb->comb[i + 1][0], h->ws1, N, h->s), "stage state");
+            }
+        }
+        DG_HIP(h, dgk::launch_rk_combine(u_dev, k, S, &sb->comb[0][0], u_dev, N, h->s), "update");
+        if (h->cfg.damping)
+            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
+                   "damping");
+        return DG_OK;
+    }
+    if (h->cfg.rk == DG_RK_SSP22) {
+        DG_HIP(h, dgk::launch_step_begin(h->g, sb, t_dev, dt_fixed, dt_used_dev, 2, h->s), "step begin");
+        DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
+        DG_HIP(h, stage(h, h->ws1, u_dev, u_dev, &sb->st[1]), "stage 2");
+        if (h->cfg.damping)
+            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
+                   "damping");
+        return DG_OK;
+    }
+    DG_HIP(h, dgk::launch_step_begin(h->g, sb, t_dev, dt_fixed, dt_used_dev, 3, h->s), "step begin");
     DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
     DG_HIP(h, limit(h, h->ws1, false), "limiter");
     DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1]), "stage 2");

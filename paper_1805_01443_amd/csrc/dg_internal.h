@@ -44,9 +44,24 @@ struct StageCoeffs {
     double pad;
 };
 
-// Device-resident per-step block written by the step-begin kernel.
+constexpr int kMaxStages = 6;
+
+// Butcher table (row-major A, s <= kMaxStages), passed by value
+struct RKTable {
+    int s;
+    int pad;
+    double A[kMaxStages * kMaxStages];
+    double b[kMaxStages];
+    double c[kMaxStages];
+};
+
+// Device-resident per-step block written by the step-begin kernels.
+// SSP(3,3) uses st[0..2] as Shu-Osher stage coefficients; a Butcher table
+// uses st[i] for k_i = L(y_i) (a0 = a1 = 0, a2 = 1), comb[i][j] = dt a_ij for
+// the stage states and comb[0][j] = dt b_j for the update.
 struct StepBlock {
-    StageCoeffs st[3];
+    StageCoeffs st[kMaxStages];
+    double comb[kMaxStages][kMaxStages];
     unsigned long long dtmin_bits;  // CFL reduction slot (order-preserving bits)
     unsigned int flags;             // bit 0: non-finite / non-positive mean seen
     unsigned int pad;
@@ -60,8 +75,14 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
 hipError_t launch_dt(int n, const Geo& g, const double* u, const double* eq, StepBlock* sb, hipStream_t s);
+hipError_t launch_step_begin_table(const Geo& g, StepBlock* sb, const RKTable& tab, double* t_dev,
+                                  double dt_fixed, double* dt_used, hipStream_t s);
+// out = base + sum_{j < nk} coef[j] k[j] (coef: device array); out may alias base
+hipError_t launch_rk_combine(const double* base, const double* const* k, int nk, const double* coef,
+                             double* out, long long n, hipStream_t s);
+// nst = 3: SSP(3,3), nst = 2: SSP(2,2), Shu-Osher coefficients in sb->st
 hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double dt_fixed,
-                             double* dt_used_dev, hipStream_t s);
+                             double* dt_used_dev, int nst, hipStream_t s);
 hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const double* eq, const int* list,
                        int nlist, const StageCoeffs* sc, hipStream_t s);
 hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,

@@ -897,15 +897,18 @@ __global__ void k_set_coeffs(StageCoeffs* sc, const Geo g, double t, double a0, 
     *sc = c;
 }
 
-__global__ void k_step_begin(const Geo g, StepBlock* sb, double* t_dev, double dt_fixed, double* dt_used) {
+// Shu-Osher convex forms: SSP(3,3) (nst = 3, c = (0, 1, 1/2)) and SSP(2,2)
+// as Heun (nst = 2, c = (0, 1)): u^(i+1) = a0 u^n + a1 (u^(i) + dt L(u^(i)))
+__global__ void k_step_begin(const Geo g, StepBlock* sb, double* t_dev, double dt_fixed, double* dt_used, int nst) {
     const double t = *t_dev;
     const double dt = dt_fixed > 0.0 ? dt_fixed : __longlong_as_double((long long)sb->dtmin_bits);
     sb->dtmin_bits = 0x7FF0000000000000ull;  // +inf: ready for the next reduction
+    const bool two = nst == 2;
     const double cst[3] = {0.0, 1.0, 0.5};
-    const double a0[3] = {0.0, 0.75, 1.0 / 3.0};
-    const double a1[3] = {1.0, 0.25, 2.0 / 3.0};
-    const double a2[3] = {1.0, 0.25, 2.0 / 3.0};
-    for (int s = 0; s < 3; ++s) {
+    const double a0[3] = {0.0, two ? 0.5 : 0.75, 1.0 / 3.0};
+    const double a1[3] = {1.0, two ? 0.5 : 0.25, 2.0 / 3.0};
+    const double a2[3] = {1.0, two ? 0.5 : 0.25, 2.0 / 3.0};
+    for (int s = 0; s < nst; ++s) {
         StageCoeffs c;
         c.t = t + cst[s] * dt;
         planet_at(g, c.t, c.xp, c.yp);
@@ -918,6 +921,46 @@ __global__ void k_step_begin(const Geo g, StepBlock* sb, double* t_dev, double d
     }
     *t_dev = t + dt;
     if (dt_used) *dt_used = dt;
+}
+
+// Butcher-form step: stage times and planet positions, k_i = L(y_i)
+// coefficients, and the dt-scaled combination rows, from the device dt
+__global__ void k_step_begin_table(const Geo g, StepBlock* sb, const RKTable tab, double* t_dev, double dt_fixed,
+                                   double* dt_used) {
+    const double t = *t_dev;
+    const double dt = dt_fixed > 0.0 ? dt_fixed : __longlong_as_double((long long)sb->dtmin_bits);
+    sb->dtmin_bits = 0x7FF0000000000000ull;
+    for (int i = 0; i < tab.s; ++i) {
+        StageCoeffs c;
+        c.t = t + tab.c[i] * dt;
+        planet_at(g, c.t, c.xp, c.yp);
+        c.a0 = 0.0;
+        c.a1 = 0.0;
+        c.a2 = 1.0;
+        c.dt = dt;
+        c.pad = 0.0;
+        sb->st[i] = c;
+        for (int j = 0; j < kMaxStages; ++j) {
+            sb->comb[i][j] = i == 0 ? (j < tab.s ? dt * tab.b[j] : 0.0)
+                                    : (j < i ? dt * tab.A[i * kMaxStages + j] : 0.0);
+        }
+    }
+    *t_dev = t + dt;
+    if (dt_used) *dt_used = dt;
+}
+
+struct KPtrs {
+    const double* k[kMaxStages];
+};
+
+// out = base + sum_j coef[j] k_j, element-wise (out may alias base)
+__global__ void __launch_bounds__(256) k_rk_combine(const double* base, const KPtrs kp, int nk,
+                                                    const double* __restrict__ coef, double* out, long long n) {
+    const long long x = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (x >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < nk; ++j) acc = fma(coef[j], kp.k[j][x], acc);
+    out[x] = base[x] + acc;
 }
 
 // CFL step of Sec. 2.3 per element from its means; global minimum by an
@@ -1206,9 +1249,32 @@ hipError_t launch_dt(int n, const Geo& g, const double* u, const double* eq, Ste
     return hipGetLastError();
 }
 
+hipError_t launch_step_begin_table(const Geo& g, StepBlock* sb, const RKTable& tab, double* t_dev,
+                                  double dt_fixed, double* dt_used, hipStream_t s) {
+    if (tab.s < 1 || tab.s > kMaxStages) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_begin_table, dim3(1), dim3(1), 0, s, g, sb, tab, t_dev, dt_fixed, dt_used);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk_combine(const double* base, const double* const* k, int nk, const double* coef,
+                             double* out, long long n, hipStream_t s) {
+    if (nk < 1 || nk > kMaxStages) return hipErrorInvalidValue;
+    if (n <= 0) return hipSuccess;
+    KPtrs kp{};
+    for (int j = 0; j < nk; ++j) {
+        if (!k[j]) return hipErrorInvalidValue;
+        kp.k[j] = k[j];
+    }
+    for (int j = nk; j < kMaxStages; ++j) kp.k[j] = k[0];
+    const long long blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_rk_combine, dim3((unsigned)blocks), dim3(256), 0, s, base, kp, nk, coef, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double dt_fixed, double* dt_used,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, g, sb, t_dev, dt_fixed, dt_used);
+                             int nst, hipStream_t s) {
+    if (nst != 2 && nst != 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, g, sb, t_dev, dt_fixed, dt_used, nst);
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ CLOSURE_ISOTHERMAL, CLOSURE_LOCALLY_ISOTHERMAL, CLOSURE_ADIABATIC = 0, 1, 2
 BC_PERIODIC, BC_FIXED_INITIAL = 0, 1
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 LIMITER_NONE, LIMITER_MODAL_DECAY, LIMITER_LEARNED = 0, 1, 2
+RK_SSP33, RK_SSP22, RK_SSP54, RK_CASHKARP = 0, 1, 2, 3
 
 
 class DGError(RuntimeError):
@@ -38,7 +39,7 @@ class dg_config(C.Structure):
         ("q", C.c_double), ("eps", C.c_double), ("rp", C.c_double), ("phi0", C.c_double),
         ("damping", C.c_int), ("rd_in", C.c_double), ("rd_out", C.c_double),
         ("cfl", C.c_double), ("precision", C.c_int), ("sigma0", C.c_double), ("limiter", C.c_int),
-        ("limiter_s0", C.c_double), ("mlp_theta", C.c_double),
+        ("limiter_s0", C.c_double), ("mlp_theta", C.c_double), ("rk", C.c_int),
     ]
 
 
@@ -74,6 +75,7 @@ class Config:
     limiter: int = LIMITER_NONE
     limiter_s0: float = 0.0
     mlp_theta: float = 0.5
+    rk: int = RK_SSP33
 
     @property
     def n(self):

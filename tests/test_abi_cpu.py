@@ -61,6 +61,8 @@ def dataclass_fields(cfg):
     (dict(cfl=0.0), dg.DG_EINVAL),
     (dict(closure=9), dg.DG_EINVAL),
     (dict(q=-1.0), dg.DG_EINVAL),
+    (dict(rk=7), dg.DG_EINVAL),
+    (dict(rk=dg.RK_CASHKARP, limiter=dg.LIMITER_MODAL_DECAY), dg.DG_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_configs_without_a_device(bad, code):
     cfg = W.wave(nx=8).replace(**bad)

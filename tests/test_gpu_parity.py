@@ -120,6 +120,37 @@ def test_rk_steps_parity(name, cfg, kind, nsteps):
     h.close()
 
 
+@pytest.mark.parametrize("rk", [dg.RK_SSP22, dg.RK_SSP54, dg.RK_CASHKARP], ids=["ssp22", "ssp54", "cashkarp"])
+@pytest.mark.parametrize("name,cfg,kind,nsteps", [
+    ("wave_p3", W.wave(nx=33, order=4).replace(ny=7), "wave", 3),
+    ("disc_p4_damped", W.disc(nx=26, order=5, q=1e-3), "disc", 2),
+])
+def test_other_tables_steps_parity(rk, name, cfg, kind, nsteps):
+    """Appendix A tables other than SSP(3,3): SSP(2,2) in Shu-Osher form, the
+    five-stage SSP table and Cash-Karp in Butcher form, against the oracle's
+    Butcher steps with the same table."""
+    T = torch()
+    cfg = cfg.replace(rk=rk)
+    print(f"[steps rk={rk}] {name} order={cfg.order} nx={cfg.nx} ny={cfg.ny} steps={nsteps}", flush=True)
+    h, u, uo = setup(cfg, kind)
+    u0o = uo.copy()
+    oc = ocfg(cfg)
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    t = 0.0
+    for s in range(nsteps):
+        dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
+        dg.dg_sync(h)
+        uo, dto = O.step(oc, uo, t, 0.0, u0=u0o)
+        assert abs(dt_dev.item() - dto) <= 1e-14 * dto
+        t += dto
+        assert abs(t_dev.item() - t) <= 1e-14 * max(t, 1.0)
+        err = relerr(u.cpu().numpy(), uo)
+        print(f"  step {s}: rel err {err}", flush=True)
+        assert max(err) <= TOL
+    h.close()
+
+
 def test_torque_parity_and_determinism():
     T = torch()
     cfg = W.disc(nx=48, order=5, q=1e-5)
