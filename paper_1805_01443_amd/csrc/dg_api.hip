@@ -35,6 +35,9 @@ struct dg_handle {
     double* kbuf = nullptr; // their stage derivatives k_1 .. k_s
     StageCoeffs* sc_rhs = nullptr;
     StepBlock* sb = nullptr;
+    double* dt_part = nullptr;        // per-block CFL minima
+    unsigned int* bad_part = nullptr; // per-block flags
+    int dt_blocks = 0;
     int* damp_list = nullptr;
     int ndamp = 0;
     double* tq_part = nullptr;
@@ -300,6 +303,10 @@ void release(dg_handle* h) {
     (void)hipFree(h->ws2);
     (void)hipFree(h->sc_rhs);
     (void)hipFree(h->sb);
+    (void)hipFree(h->dt_part);
+    (void)hipFree(h->bad_part);
+    h->dt_part = nullptr;
+    h->bad_part = nullptr;
     (void)hipFree(h->damp_list);
     (void)hipFree(h->tq_part);
     (void)hipFree(h->eq);
@@ -372,6 +379,9 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     DG_ALLOC(h->ws2, state_bytes);
     DG_ALLOC(h->sc_rhs, sizeof(StageCoeffs));
     DG_ALLOC(h->sb, sizeof(StepBlock));
+    h->dt_blocks = dgk::dt_blocks(h->g);
+    DG_ALLOC(h->dt_part, sizeof(double) * (size_t)h->dt_blocks);
+    DG_ALLOC(h->bad_part, sizeof(unsigned int) * (size_t)h->dt_blocks);
     h->tq_blocks = dgk::torque_blocks(h->g);
     DG_ALLOC(h->tq_part, sizeof(double) * (size_t)h->tq_blocks);
     DG_ALLOC(prim_dev, state_bytes);
@@ -414,7 +424,6 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
 #undef DG_ALLOC
 
     StepBlock sb0{};
-    sb0.dtmin_bits = 0x7FF0000000000000ull;
     e = hipMemcpyAsync(h->sb, &sb0, sizeof sb0, hipMemcpyHostToDevice, h->s);
     if (e == hipSuccess) e = hipMemcpyAsync(prim_dev, prim_nodes_host, state_bytes, hipMemcpyHostToDevice, h->s);
     if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, u0_dev, h->s);
@@ -455,7 +464,7 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     if (!u_dev || !t_dev) return fail(h, DG_EINVAL, "u_dev and t_dev are required");
     if (!(dt_fixed == dt_fixed)) return fail(h, DG_EINVAL, "dt_fixed is NaN");
     StepBlock* sb = h->sb;
-    DG_HIP(h, dgk::launch_dt(h->n, h->g, u_dev, h->eq, sb, h->s), "CFL reduction");
+    DG_HIP(h, dgk::launch_dt(h->n, h->g, u_dev, h->eq, h->dt_part, h->bad_part, h->s), "CFL reduction");
     if (h->tab.s > 0) {
         // Butcher form: k_i = L(y_i), y_1 = u^n, y_i = u^n + dt sum_{j<i} a_ij k_j,
         // u^{n+1} = u^n + dt sum_j b_j k_j (no limiter with these tables)
@@ -463,7 +472,8 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
         const long long N = (long long)h->nvar * h->n * h->n * h->E;
         const double* k[dgk::kMaxStages];
         for (int i = 0; i < S; ++i) k[i] = h->kbuf + (size_t)i * (size_t)N;
-        DG_HIP(h, dgk::launch_step_begin_table(h->g, sb, h->tab, t_dev, dt_fixed, dt_used_dev, h->s), "step begin");
+        DG_HIP(h, dgk::launch_step_begin_table(h->g, sb, h->tab, h->dt_part, h->bad_part, h->dt_blocks, t_dev,
+                                                         dt_fixed, dt_used_dev, h->s), "step begin");
         for (int i = 0; i < S; ++i) {
             const double* y = i == 0 ? u_dev : h->ws1;
             DG_HIP(h, stage(h, y, nullptr, h->kbuf + (size_t)i * (size_t)N, &sb->st[i]), "stage");
@@ -478,7 +488,8 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
         return DG_OK;
     }
     if (h->cfg.rk == DG_RK_SSP22) {
-        DG_HIP(h, dgk::launch_step_begin(h->g, sb, t_dev, dt_fixed, dt_used_dev, 2, h->s), "step begin");
+        DG_HIP(h, dgk::launch_step_begin(h->g, sb, h->dt_part, h->bad_part, h->dt_blocks, t_dev, dt_fixed,
+                                                   dt_used_dev, 2, h->s), "step begin");
         DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
         DG_HIP(h, stage(h, h->ws1, u_dev, u_dev, &sb->st[1]), "stage 2");
         if (h->cfg.damping)
@@ -486,7 +497,8 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
                    "damping");
         return DG_OK;
     }
-    DG_HIP(h, dgk::launch_step_begin(h->g, sb, t_dev, dt_fixed, dt_used_dev, 3, h->s), "step begin");
+    DG_HIP(h, dgk::launch_step_begin(h->g, sb, h->dt_part, h->bad_part, h->dt_blocks, t_dev, dt_fixed,
+                                               dt_used_dev, 3, h->s), "step begin");
     DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
     DG_HIP(h, limit(h, h->ws1, false), "limiter");
     DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1]), "stage 2");

@@ -62,7 +62,6 @@ struct RKTable {
 struct StepBlock {
     StageCoeffs st[kMaxStages];
     double comb[kMaxStages][kMaxStages];
-    unsigned long long dtmin_bits;  // CFL reduction slot (order-preserving bits)
     unsigned int flags;             // bit 0: non-finite / non-positive mean seen
     unsigned int pad;
 };
@@ -74,15 +73,22 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
                         double* out, const StageCoeffs* sc, hipStream_t s);
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
-hipError_t launch_dt(int n, const Geo& g, const double* u, const double* eq, StepBlock* sb, hipStream_t s);
-hipError_t launch_step_begin_table(const Geo& g, StepBlock* sb, const RKTable& tab, double* t_dev,
-                                  double dt_fixed, double* dt_used, hipStream_t s);
+// CFL step per element; per-block minimum into dt_part[block] and a per-block
+// flag (non-finite or non-positive mean) into bad_part[block]
+hipError_t launch_dt(int n, const Geo& g, const double* u, const double* eq, double* dt_part,
+                     unsigned int* bad_part, hipStream_t s);
+int dt_blocks(const Geo& g);
+// The step-begin kernels reduce the CFL partials (dt = dt_fixed if > 0, else
+// their minimum), OR the flags into sb->flags and write the stage data.
+hipError_t launch_step_begin_table(const Geo& g, StepBlock* sb, const RKTable& tab, const double* dt_part,
+                                  const unsigned int* bad_part, int nblk, double* t_dev, double dt_fixed,
+                                  double* dt_used, hipStream_t s);
 // out = base + sum_{j < nk} coef[j] k[j] (coef: device array); out may alias base
 hipError_t launch_rk_combine(const double* base, const double* const* k, int nk, const double* coef,
                              double* out, long long n, hipStream_t s);
 // nst = 3: SSP(3,3), nst = 2: SSP(2,2), Shu-Osher coefficients in sb->st
-hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double dt_fixed,
-                             double* dt_used_dev, int nst, hipStream_t s);
+hipError_t launch_step_begin(const Geo& g, StepBlock* sb, const double* dt_part, const unsigned int* bad_part,
+                             int nblk, double* t_dev, double dt_fixed, double* dt_used_dev, int nst, hipStream_t s);
 hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const double* eq, const int* list,
                        int nlist, const StageCoeffs* sc, hipStream_t s);
 hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,

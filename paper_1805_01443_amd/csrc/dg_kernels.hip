@@ -897,12 +897,43 @@ __global__ void k_set_coeffs(StageCoeffs* sc, const Geo g, double t, double a0, 
     *sc = c;
 }
 
+// Minimum of the per-block CFL steps and OR of the per-block flags, over one
+// block of 256 threads; the result is valid in thread 0.  The flags are
+// merged into sb->flags (read and cleared by the host).
+__device__ double reduce_dt_partials(const double* __restrict__ dt_part, const unsigned int* __restrict__ bad_part,
+                                     int nblk, StepBlock* sb) {
+    __shared__ double sm[256];
+    __shared__ unsigned int sf[256];
+    double m = INFINITY;
+    unsigned int f = 0;
+    for (int k = threadIdx.x; k < nblk; k += 256) {
+        m = fmin(m, dt_part[k]);
+        f |= bad_part[k];
+    }
+    sm[threadIdx.x] = m;
+    sf[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + w]);
+            sf[threadIdx.x] |= sf[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && sf[0]) sb->flags |= 1u;
+    return sm[0];
+}
+
 // Shu-Osher convex forms: SSP(3,3) (nst = 3, c = (0, 1, 1/2)) and SSP(2,2)
-// as Heun (nst = 2, c = (0, 1)): u^(i+1) = a0 u^n + a1 (u^(i) + dt L(u^(i)))
-__global__ void k_step_begin(const Geo g, StepBlock* sb, double* t_dev, double dt_fixed, double* dt_used, int nst) {
+// as Heun (nst = 2, c = (0, 1)): u^(i+1) = a0 u^n + a1 (u^(i) + dt L(u^(i))).
+// One block of 256 threads.
+__global__ void __launch_bounds__(256) k_step_begin(const Geo g, StepBlock* sb, const double* __restrict__ dt_part,
+                                                    const unsigned int* __restrict__ bad_part, int nblk,
+                                                    double* t_dev, double dt_fixed, double* dt_used, int nst) {
+    const double dtmin = reduce_dt_partials(dt_part, bad_part, nblk, sb);
+    if (threadIdx.x != 0) return;
     const double t = *t_dev;
-    const double dt = dt_fixed > 0.0 ? dt_fixed : __longlong_as_double((long long)sb->dtmin_bits);
-    sb->dtmin_bits = 0x7FF0000000000000ull;  // +inf: ready for the next reduction
+    const double dt = dt_fixed > 0.0 ? dt_fixed : dtmin;
     const bool two = nst == 2;
     const double cst[3] = {0.0, 1.0, 0.5};
     const double a0[3] = {0.0, two ? 0.5 : 0.75, 1.0 / 3.0};
@@ -925,11 +956,14 @@ __global__ void k_step_begin(const Geo g, StepBlock* sb, double* t_dev, double d
 
 // Butcher-form step: stage times and planet positions, k_i = L(y_i)
 // coefficients, and the dt-scaled combination rows, from the device dt
-__global__ void k_step_begin_table(const Geo g, StepBlock* sb, const RKTable tab, double* t_dev, double dt_fixed,
-                                   double* dt_used) {
+__global__ void __launch_bounds__(256) k_step_begin_table(const Geo g, StepBlock* sb, const RKTable tab,
+                                                          const double* __restrict__ dt_part,
+                                                          const unsigned int* __restrict__ bad_part, int nblk,
+                                                          double* t_dev, double dt_fixed, double* dt_used) {
+    const double dtmin = reduce_dt_partials(dt_part, bad_part, nblk, sb);
+    if (threadIdx.x != 0) return;
     const double t = *t_dev;
-    const double dt = dt_fixed > 0.0 ? dt_fixed : __longlong_as_double((long long)sb->dtmin_bits);
-    sb->dtmin_bits = 0x7FF0000000000000ull;
+    const double dt = dt_fixed > 0.0 ? dt_fixed : dtmin;
     for (int i = 0; i < tab.s; ++i) {
         StageCoeffs c;
         c.t = t + tab.c[i] * dt;
@@ -963,11 +997,13 @@ __global__ void __launch_bounds__(256) k_rk_combine(const double* base, const KP
     out[x] = base[x] + acc;
 }
 
-// CFL step of Sec. 2.3 per element from its means; global minimum by an
-// atomic min on the (order-preserving) bit pattern of the positive double.
+// CFL step of Sec. 2.3 per element from its means; the block minimum and
+// the block's flag go to per-block slots, reduced by the step-begin kernel
+// (no atomics: a fixed reduction order and no cross-kernel atomic traffic).
 template <int CL>
 __global__ void __launch_bounds__(256) k_dt(const Geo g, int nn, const double* __restrict__ u,
-                                            const double* __restrict__ eq, StepBlock* sb) {
+                                            const double* __restrict__ eq, double* __restrict__ dt_part,
+                                            unsigned int* __restrict__ bad_part) {
     __shared__ double red[4];
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     double dte = INFINITY;
@@ -995,13 +1031,13 @@ __global__ void __launch_bounds__(256) k_dt(const Geo g, int nn, const double* _
         if (bad) dte = INFINITY;
     }
     for (int off = 32; off > 0; off >>= 1) dte = fmin(dte, __shfl_xor(dte, off));
-    if (bad) atomicOr(&sb->flags, 1u);
+    const int anybad = __syncthreads_or(bad ? 1 : 0);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) red[w] = dte;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const double m = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
-        if (m < INFINITY) atomicMin(&sb->dtmin_bits, (unsigned long long)__double_as_longlong(m));
+        dt_part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+        bad_part[blockIdx.x] = anybad ? 1u : 0u;
     }
 }
 
@@ -1243,16 +1279,22 @@ hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0,
     return hipGetLastError();
 }
 
-hipError_t launch_dt(int n, const Geo& g, const double* u, const double* eq, StepBlock* sb, hipStream_t s) {
-    const int blocks = (int)((g.E + 255) / 256);
-    DG_DISPATCH_CL(g.closure, hipLaunchKernelGGL((k_dt<CT>), dim3(blocks), dim3(256), 0, s, g, n * n, u, eq, sb));
+int dt_blocks(const Geo& g) { return (int)((g.E + 255) / 256); }
+
+hipError_t launch_dt(int n, const Geo& g, const double* u, const double* eq, double* dt_part, unsigned int* bad_part,
+                     hipStream_t s) {
+    const int blocks = dt_blocks(g);
+    DG_DISPATCH_CL(g.closure, hipLaunchKernelGGL((k_dt<CT>), dim3(blocks), dim3(256), 0, s, g, n * n, u, eq, dt_part,
+                                                 bad_part));
     return hipGetLastError();
 }
 
-hipError_t launch_step_begin_table(const Geo& g, StepBlock* sb, const RKTable& tab, double* t_dev,
-                                  double dt_fixed, double* dt_used, hipStream_t s) {
-    if (tab.s < 1 || tab.s > kMaxStages) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_begin_table, dim3(1), dim3(1), 0, s, g, sb, tab, t_dev, dt_fixed, dt_used);
+hipError_t launch_step_begin_table(const Geo& g, StepBlock* sb, const RKTable& tab, const double* dt_part,
+                                  const unsigned int* bad_part, int nblk, double* t_dev, double dt_fixed,
+                                  double* dt_used, hipStream_t s) {
+    if (tab.s < 1 || tab.s > kMaxStages || nblk < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_begin_table, dim3(1), dim3(256), 0, s, g, sb, tab, dt_part, bad_part, nblk, t_dev,
+                       dt_fixed, dt_used);
     return hipGetLastError();
 }
 
@@ -1271,10 +1313,11 @@ hipError_t launch_rk_combine(const double* base, const double* const* k, int nk,
     return hipGetLastError();
 }
 
-hipError_t launch_step_begin(const Geo& g, StepBlock* sb, double* t_dev, double dt_fixed, double* dt_used,
-                             int nst, hipStream_t s) {
-    if (nst != 2 && nst != 3) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, g, sb, t_dev, dt_fixed, dt_used, nst);
+hipError_t launch_step_begin(const Geo& g, StepBlock* sb, const double* dt_part, const unsigned int* bad_part,
+                             int nblk, double* t_dev, double dt_fixed, double* dt_used, int nst, hipStream_t s) {
+    if ((nst != 2 && nst != 3) || nblk < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, g, sb, dt_part, bad_part, nblk, t_dev, dt_fixed,
+                       dt_used, nst);
     return hipGetLastError();
 }
 
