@@ -429,8 +429,34 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, u0_dev, h->s);
     if (e == hipSuccess) e = hipMemcpyAsync(h->u0, u0_dev, state_bytes, hipMemcpyDeviceToDevice, h->s);
     if (e == hipSuccess) e = hipStreamSynchronize(h->s);
+    if (e != hipSuccess) {
+        (void)hipFree(prim_dev);
+        return bail(hip_fail(h, e, "dg_init projection"));
+    }
+    if (h->dev) {
+        // Deviation form: project the equilibrium (same projection kernel as
+        // the state), evaluate L(u_eq) once with the FP64 stage kernel (no
+        // planet, exterior state = u_eq) and keep it in FP32; the caller's
+        // u0_dev and the fixed exterior state become deviations u0 - u_eq.
+        std::vector<double> peq;
+        equilibrium_prim(cfg, &peq);
+        const long long N = (long long)h->nvar * h->n * h->n * h->E;
+        Geo g0 = h->g;
+        g0.q = 0.0;
+        e = hipMemcpyAsync(prim_dev, peq.data(), state_bytes, hipMemcpyHostToDevice, h->s);
+        if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, h->eq, h->s);
+        if (e == hipSuccess) e = dgk::launch_set_coeffs(h->sc_rhs, g0, 0.0, 0.0, 0.0, 1.0, h->s);
+        if (e == hipSuccess) e = dgk::launch_stage(h->n, g0, h->eq, nullptr, h->eq, h->ws1, h->sc_rhs, h->s);
+        if (e == hipSuccess) e = dgk::launch_to_f32(h->ws1, h->leq, N, h->s);
+        if (e == hipSuccess) e = dgk::launch_add_state(u0_dev, h->eq, u0_dev, -1.0, N, h->s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->du0, u0_dev, state_bytes, hipMemcpyDeviceToDevice, h->s);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->s);  // peq lives until here
+        if (e != hipSuccess) {
+            (void)hipFree(prim_dev);
+            return bail(hip_fail(h, e, "dg_init equilibrium"));
+        }
+    }
     (void)hipFree(prim_dev);
-    if (e != hipSuccess) return bail(hip_fail(h, e, "dg_init projection"));
     // feature scales: RMS of the initial element means of each variable
     {
         std::vector<double> means((size_t)h->E);

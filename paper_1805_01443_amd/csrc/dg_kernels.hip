@@ -827,7 +827,7 @@ __global__ void __launch_bounds__(64) k_stage_dev(const Geo g, const double* __r
 }
 
 // out = a + sign * b, elementwise over a state array (out may alias b)
-__global__ void k_add_state(const double* __restrict__ a, const double* b, double* out, double sign, long long n) {
+__global__ void k_add_state(const double* a, const double* b, double* out, double sign, long long n) {
     const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
     if (k < n) out[k] = a[k] + sign * b[k];
 }

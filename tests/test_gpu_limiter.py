@@ -29,12 +29,18 @@ def ocfg(cfg):
     return O.cfg(dataclasses.asdict(cfg))
 
 
-def ring_setup(nx=48, order=4, s0=-2.4, limiter=dg.LIMITER_MODAL_DECAY):
+def ring_setup(nx=48, order=4, s0=-2.4, limiter=dg.LIMITER_MODAL_DECAY, jump=False):
+    """The ring workload; with jump=True the density and energy are doubled
+    inside r = 1.6 (a discontinuity that the sensor flags)."""
     T = torch()
     cfg = W.disc_ring(nx=nx, order=order).replace(limiter=limiter, limiter_s0=s0)
     oc = ocfg(cfg)
     x, y = O.nodes(oc)
     prim = W.prim_for(cfg, "disc_ring", x=x, y=y)
+    if jump:
+        r = np.sqrt(x ** 2 + y ** 2).reshape(cfg.n_elem, order * order)
+        prim[0] *= np.where(r < 1.6, 2.0, 1.0)
+        prim[3] *= np.where(r < 1.6, 2.0, 1.0)
     h, u = dg.dg_init(cfg, prim)
     T.cuda.synchronize()
     return cfg, oc, h, u, O.project(oc, prim)
@@ -42,11 +48,8 @@ def ring_setup(nx=48, order=4, s0=-2.4, limiter=dg.LIMITER_MODAL_DECAY):
 
 def test_indicator_flags_labels_and_limited_state():
     T = torch()
-    cfg, oc, h, u, uo = ring_setup()
-    # a state with sharp features: a few RK steps of the ring without limiting
+    cfg, oc, h, u, uo = ring_setup(jump=True)
     u0 = uo.copy()
-    for k in range(3):
-        uo, _ = O.step(oc, uo, 0.01 * k, 2e-3, u0=u0)
     ug = T.tensor(uo, device="cuda")
     E = cfg.n_elem
     fl = T.zeros(E, dtype=T.uint8, device="cuda")
@@ -57,6 +60,7 @@ def test_indicator_flags_labels_and_limited_state():
     s = O.indicator(oc, uo)
     assert np.max(np.abs(sn.cpu().numpy() - s.astype(np.float32))) <= 1e-6 * np.max(np.abs(s))
     fo = s > cfg.limiter_s0
+    print(f"[indicator] {int(fo.sum())} of {E} flagged", flush=True)
     assert 0 < fo.sum() < E
     assert np.array_equal(fl.cpu().numpy().astype(bool), fo)
     ul, cho = O.minmod(oc, uo, u0, fo)
@@ -94,7 +98,9 @@ def test_features_bitwise():
     sc = dg.dg_mlp_feature_scales(h)
     means = uo[:, 0, :]
     assert np.allclose(sc, np.sqrt(np.mean(means ** 2, axis=1)), rtol=1e-14, atol=0)
-    fo = O.mlp_features(oc, uo, sc)
+    # the same state on both sides (modes that vanish by symmetry carry
+    # different round-off in the two projections)
+    fo = O.mlp_features(oc, u.cpu().numpy(), sc)
     fo16 = np.array([O.bf16(v) for v in fo.ravel()]).reshape(fo.shape)
     got = (f.cpu().numpy().astype(np.int32) & 0xFFFF).astype(np.uint32) << 16
     got = got.view(np.float32).astype(np.float64)
@@ -184,7 +190,11 @@ def test_fused_learned_flags_match_features_then_forward():
     flags exactly the elements whose logits from dg_mlp_forward on the captured
     features exceed logit(theta)."""
     T = torch()
-    theta = 0.3
+    # these random parameters give logits of about 0.11 .. 0.26 on the ring
+    # state: theta = sigmoid(0.18) splits the elements.  One step only: with
+    # half of the elements limited at random, component-wise minmod of this
+    # high-Mach disc can make the pressure negative at nodes, in the oracle too.
+    theta = 1.0 / (1.0 + np.exp(-0.18))
     cfg, oc, h, u, uo = ring_setup(nx=40, limiter=dg.LIMITER_LEARNED)
     h.close()
     cfg = cfg.replace(mlp_theta=theta)
@@ -194,13 +204,13 @@ def test_fused_learned_flags_match_features_then_forward():
     feat = T.zeros((E, 64), dtype=T.int16, device="cuda")
     mf = T.zeros(E, dtype=T.uint8, device="cuda")
     t_dev = T.zeros(1, dtype=T.float64, device="cuda")
-    dg.dg_rk_step(h, u, t_dev, 1e-3, None)
     dg.dg_capture(h, feat=feat, mlp_flags=mf)
     dg.dg_rk_step(h, u, t_dev, 1e-3, None)
     z = T.zeros(E, dtype=T.float32, device="cuda")
     dg.dg_mlp_forward(h, feat, E, z)
     dg.dg_sync(h)
-    zthr = np.log(np.float32(theta) / (np.float32(1.0) - np.float32(theta)))
+    th = np.float32(theta)
+    zthr = np.float32(np.log(th / (np.float32(1.0) - th)))
     ref = (z.cpu().numpy() > np.float32(zthr)).astype(np.uint8)
     got = mf.cpu().numpy()
     print(f"[fused flags] {int(ref.sum())} of {E} flagged", flush=True)
