@@ -52,8 +52,10 @@ def parse():
 
 
 def calibrate_copy():
-    """A plain 2 GiB device-to-device copy, five times: the PMC byte counters of
-    this kernel, divided by 2 GiB, give the counter-to-HBM-bytes factors."""
+    """A plain streaming kernel over 2 GiB, five times: b = a * 1 reads 2 GiB and
+    writes 2 GiB with ordinary vector loads and stores (torch's elementwise
+    kernel; the runtime's blit copy uses another load path).  Its PMC byte
+    counters, divided by 2 GiB, give the counter-to-HBM-bytes factors."""
     import torch
     n = 1 << 28  # doubles: 2 GiB
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -61,7 +63,7 @@ def calibrate_copy():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(5):
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8,
