@@ -494,6 +494,354 @@ __global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restr
     }
 }
 
+// ------------------------------------------------------------------ stage kernel, N lanes per element
+// Lane-dependent entry t[k] of a compile-time table (k < N): a select chain on
+// immediates.
+template <int N>
+__device__ __forceinline__ double pick(const double (&t)[kMaxOrder], int k) {
+    double r = t[0];
+#pragma unroll
+    for (int m = 1; m < N; ++m) r = k == m ? t[m] : r;
+    return r;
+}
+
+// Collapse of the exterior state across one edge for lane k: the neighbour's
+// row k (ROW: modes (k, b), summed over b) or column k (modes (a, k), summed
+// over a) with the basis values of the neighbour's far side NB_SIDE, or, at a
+// fixed box edge, the element's own initial row/column with the near side.
+// vnb / vown: the lane's byte offset of mode (k, 0) resp. (0, k) of the
+// neighbour / of the element itself.
+template <int N, int NV, bool ROW, int NB_SIDE>
+__device__ __forceinline__ void ext_collapse(rsrc_t ru, rsrc_t ru0, unsigned pstride, unsigned vnb, unsigned vown,
+                                             bool fixed, bool wave_fixed, double (&T)[NV]) {
+    constexpr BasisTab B = make_basis(N);
+    constexpr int NN = N * N;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) T[v] = 0.0;
+    if (!wave_fixed) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const unsigned so = (unsigned)(v * NN + (ROW ? m : m * N)) * pstride;
+                T[v] += (NB_SIDE > 0 ? B.pp[m] : B.pm[m]) * ld64(ru, vnb, so);
+            }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const unsigned so = (unsigned)(v * NN + (ROW ? m : m * N)) * pstride;
+                const double un = ld64(ru, vnb, so);
+                const double u0v = ld64(ru0, vown, so);
+                T[v] += fixed ? (NB_SIDE > 0 ? B.pm[m] : B.pp[m]) * u0v : (NB_SIDE > 0 ? B.pp[m] : B.pm[m]) * un;
+            }
+    }
+}
+
+// out = a0 u^n + a1 u + a2 L(u, t), with the N lanes of an element sharing
+// its tensor-product contractions.  Lane (s, k): element slot s = lane / N of
+// the wave (EW = 64 / N consecutive elements of one row), index k = lane % N.
+// Transposes between the lanes of an element go through LDS:
+//   phase 1, k = mode row a: own row u[v][a][.] -> C[v][a][r] = sum_b u[v][a][b]
+//            phi_b(eta_r); y collapses of the own row (both sides) and of the y
+//            neighbours' rows, x collapses of the x neighbours' columns;
+//   phase 2, k = Gauss row r: node values at (xi_q, eta_r) for every q, the
+//            physical flux and source, partial projections
+//            X[r][a] = sum_q w_q (2/dx phi_a'(q) f_x + phi_a(q) s),
+//            Y[r][a] = sum_q w_q phi_a(q) (2/dy) f_y; traces at point k of the
+//            four edges and their Rusanov fluxes;
+//   phase 3, k = mode row a: R[a][b] = sum_r w_r (phi_b(r) X[r][a] + phi_b'(r)
+//            Y[r][a]) minus the edge lifts; stage combination of row a.
+// Every integral is the same Gauss sum as in eq. (3); the density volume term
+// is taken by quadrature (exact for its polynomial integrand).
+template <int N, int CL>
+__global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int tiles_total,
+                                                const double* __restrict__ u, const double* un,
+                                                const double* __restrict__ u0, double* out,
+                                                const StageCoeffs* __restrict__ scp) {
+    constexpr int NV = NVar<CL>::value;
+    constexpr int NN = N * N;
+    constexpr int EW = 64 / N;
+    constexpr BasisTab B = make_basis(N);
+    constexpr int P1 = NV * NN + 6 * NV * N;      // C, six collapse vectors
+    constexpr int P2 = 2 * NV * NN + 4 * NV * N;  // X, Y, four edge fluxes
+    constexpr int SLOT = P1 > P2 ? P1 : P2;
+    __shared__ double lds[(EW + 1) * SLOT];       // slot EW: lanes beyond EW * N
+
+    const int lane = threadIdx.x;
+    const int sl = lane / N, k = lane - sl * N;
+    const int tile = remap_tile(blockIdx.x, tiles_total);
+    const int j = tile / tiles_x;
+    const int i0 = (tile - j * tiles_x) * EW;
+    const bool active = sl < EW && i0 + sl < g.nx;
+    const int i = active ? i0 + sl : i0;  // idle lanes shadow a valid element and store nothing
+    double* S = lds + sl * SLOT;
+
+    const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
+    const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), rout = make_rsrc(out), run = make_rsrc(un);
+    const unsigned pstride = (unsigned)g.E * 8u;
+    const unsigned e = (unsigned)j * (unsigned)g.nx + (unsigned)i;
+    const unsigned vrow = (unsigned)(k * N) * pstride + e * 8u;  // mode (k, 0) of this element
+    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+
+    // ---- phase 1: k = mode row
+    double Ua[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int b = 0; b < N; ++b) Ua[v][b] = ld64(ru, vrow, (unsigned)(v * NN + b) * pstride);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double c = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) c += Ua[v][b] * B.phi[b][r];
+            S[(v * N + k) * N + r] = c;
+        }
+        double tm = 0.0, tp = 0.0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            tm += B.pm[b] * Ua[v][b];
+            tp += B.pp[b] * Ua[v][b];
+        }
+        S[NV * NN + (0 * NV + v) * N + k] = tm;
+        S[NV * NN + (1 * NV + v) * N + k] = tp;
+    }
+    {
+        int il = i - 1, ir = i + 1, jb = j - 1, jt = j + 1;
+        const bool ol = il < 0, orr = ir >= g.nx, ob = jb < 0, ot = jt >= g.ny;
+        il += ol ? g.nx : 0;
+        ir -= orr ? g.nx : 0;
+        jb += ob ? g.ny : 0;
+        jt -= ot ? g.ny : 0;
+        const bool fx = g.bc == 1, fl = fx && ol, fr = fx && orr, fb = fx && ob, ft = fx && ot;
+        const bool wfx = __any(fl || fr), wfy = __any(fb || ft);
+        const unsigned vcol = (unsigned)k * pstride + e * 8u;  // mode (0, k)
+        const unsigned kr = (unsigned)(k * N) * pstride, kc = (unsigned)k * pstride;
+        double T[NV];
+        ext_collapse<N, NV, true, +1>(ru, ru0, pstride, kr + ((unsigned)jb * g.nx + i) * 8u, vrow, fb, wfy, T);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[NV * NN + (2 * NV + v) * N + k] = T[v];
+        ext_collapse<N, NV, true, -1>(ru, ru0, pstride, kr + ((unsigned)jt * g.nx + i) * 8u, vrow, ft, wfy, T);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[NV * NN + (3 * NV + v) * N + k] = T[v];
+        ext_collapse<N, NV, false, +1>(ru, ru0, pstride, kc + ((unsigned)j * g.nx + il) * 8u, vcol, fl, wfx, T);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[NV * NN + (4 * NV + v) * N + k] = T[v];
+        ext_collapse<N, NV, false, -1>(ru, ru0, pstride, kc + ((unsigned)j * g.nx + ir) * 8u, vcol, fr, wfx, T);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[NV * NN + (5 * NV + v) * N + k] = T[v];
+    }
+    __syncthreads();
+
+    // ---- phase 2: k = Gauss row r
+    const double xik = pick<N>(B.xi, k);
+    double phk[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) phk[m] = pick<N>(B.phi[m], k);  // phi_m(xi_k)
+    const double yk = yc + 0.5 * g.dy * xik;
+    double Cc[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) Cc[v][a] = S[(v * N + a) * N + k];
+    double X[NV][N], Y[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            X[v][a] = 0.0;
+            Y[v][a] = 0.0;
+        }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double W[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) s += B.phi[a][q] * Cc[v][a];
+            W[v] = s;
+        }
+        const double x = xc + 0.5 * g.dx * B.xi[q];
+        const double y = yk;
+        const double inv = rcp64(W[0]);
+        const double r2 = x * x + y * y;
+        const double ir = (CL == CL_LOC || g.star) ? rsq64(r2) : 0.0;
+        double p;
+        if constexpr (CL == CL_ISO)
+            p = g.cs2 * W[0];
+        else if constexpr (CL == CL_LOC)
+            p = cs2_loc(g, r2, ir) * W[0];
+        else
+            p = (g.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) * inv);
+        const double vx = W[1] * inv, vy = W[2] * inv;
+        double gx = 0.0, gy = 0.0;
+        if (g.star) {
+            const double kk = r2 < g.rc2 ? g.rc3inv : g.gm * ir * ir * ir;
+            gx = kk * x;
+            gy = kk * y;
+        }
+        if (g.q > 0.0) {
+            const double dx = x - xp, dy = y - yp;
+            const double id = rsq64(dx * dx + dy * dy + g.eps2);
+            const double kk = g.q * id * id * id;
+            gx += kk * dx;
+            gy += kk * dy;
+        }
+        double fx[NV], fy[NV], sy[NV];
+        fx[0] = W[1];
+        fy[0] = W[2];
+        sy[0] = 0.0;
+        fx[1] = W[1] * vx + p;
+        fy[1] = W[1] * vy;
+        fx[2] = W[2] * vx;
+        fy[2] = W[2] * vy + p;
+        sy[1] = -W[0] * gx;
+        sy[2] = -W[0] * gy;
+        if constexpr (NV == 4) {
+            fx[3] = (W[3] + p) * vx;
+            fy[3] = (W[3] + p) * vy;
+            sy[3] = -(W[1] * gx + W[2] * gy);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double fxx = g.rdx2 * fx[v], fyy = g.rdy2 * fy[v];
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                X[v][a] += B.wdphi[a][q] * fxx + B.wphi[a][q] * sy[v];
+                Y[v][a] += B.wphi[a][q] * fyy;
+            }
+        }
+    }
+    // edge traces at point k and their fluxes (outward normals)
+    double hf[4][NV];
+    {
+        const double* Cl = S + NV * NN;
+        double Ui[NV], Uo[NV];
+        // west / east: own traces from C, exterior from the x collapses
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double si = 0.0, so = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += B.pm[a] * Cc[v][a];
+                so += phk[a] * Cl[(4 * NV + v) * N + a];
+            }
+            Ui[v] = si;
+            Uo[v] = so;
+        }
+        rusanov<CL, 0, -1>(g, Ui, Uo, xc - 0.5 * g.dx, yk, hf[0]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double si = 0.0, so = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += B.pp[a] * Cc[v][a];
+                so += phk[a] * Cl[(5 * NV + v) * N + a];
+            }
+            Ui[v] = si;
+            Uo[v] = so;
+        }
+        rusanov<CL, 0, 1>(g, Ui, Uo, xc + 0.5 * g.dx, yk, hf[1]);
+        const double xk = xc + 0.5 * g.dx * xik;
+        // south / north: own and exterior traces from the y collapses
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double si = 0.0, so = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += phk[a] * Cl[(0 * NV + v) * N + a];
+                so += phk[a] * Cl[(2 * NV + v) * N + a];
+            }
+            Ui[v] = si;
+            Uo[v] = so;
+        }
+        rusanov<CL, 1, -1>(g, Ui, Uo, xk, yc - 0.5 * g.dy, hf[2]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double si = 0.0, so = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += phk[a] * Cl[(1 * NV + v) * N + a];
+                so += phk[a] * Cl[(3 * NV + v) * N + a];
+            }
+            Ui[v] = si;
+            Uo[v] = so;
+        }
+        rusanov<CL, 1, 1>(g, Ui, Uo, xk, yc + 0.5 * g.dy, hf[3]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            S[((0 * NV + v) * N + k) * N + a] = X[v][a];
+            S[((1 * NV + v) * N + k) * N + a] = Y[v][a];
+        }
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[2 * NV * NN + (f * NV + v) * N + k] = hf[f][v];
+    __syncthreads();
+
+    // ---- phase 3: k = mode row a
+    double wrow[N];  // w_q phi_k(xi_q)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double r = B.wphi[0][q];
+#pragma unroll
+        for (int m = 1; m < N; ++m) r = k == m ? B.wphi[m][q] : r;
+        wrow[q] = r;
+    }
+    const double pmk = pick<N>(B.pm, k), ppk = pick<N>(B.pp, k);
+    const double* H = S + 2 * NV * NN;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double glb = 0.0, glt = 0.0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            glb += wrow[q] * H[(2 * NV + v) * N + q];
+            glt += wrow[q] * H[(3 * NV + v) * N + q];
+        }
+        double hw[N], he[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            hw[r] = H[(0 * NV + v) * N + r];
+            he[r] = H[(1 * NV + v) * N + r];
+        }
+        double R[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            double acc = 0.0, glw = 0.0, gle = 0.0;
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                acc += B.wphi[b][r] * S[((0 * NV + v) * N + r) * N + k] + B.wdphi[b][r] * S[((1 * NV + v) * N + r) * N + k];
+                glw += B.wphi[b][r] * hw[r];
+                gle += B.wphi[b][r] * he[r];
+            }
+            acc -= g.idx * (pmk * glw + ppk * gle);
+            acc -= g.idy * (B.pm[b] * glb + B.pp[b] * glt);
+            R[b] = acc;
+        }
+        if (active) {
+            if (a0 != 0.0) {
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const unsigned po = (unsigned)(v * NN + b) * pstride;
+                    st64(rout, vrow, po, a0 * ld64(run, vrow, po) + (a1 * Ua[v][b] + a2 * R[b]));
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+                    st64(rout, vrow, (unsigned)(v * NN + b) * pstride, a1 * Ua[v][b] + a2 * R[b]);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ deviation form
 // u = u_eq + du about the disc's rotational equilibrium (locally isothermal,
 // stellar harmonic core inside r_core).  The FP64 state du is converted to
@@ -1268,8 +1616,12 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
     // resources are never built on a null pointer)
     if (!un) un = u;
     if (!u0) u0 = u;
-    DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_stage<NT, CT>), dim3(g.tiles_total), dim3(64), 0,
-                                                                  s, g, u, un, u0, out, sc)));
+    DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, {
+        constexpr int EW = 64 / NT;
+        const int tx = (g.nx + EW - 1) / EW;
+        const int tt = tx * g.ny;
+        hipLaunchKernelGGL((k_stage_c<NT, CT>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, sc);
+    }));
     return hipGetLastError();
 }
 
