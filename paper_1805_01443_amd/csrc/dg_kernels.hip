@@ -1520,6 +1520,136 @@ __global__ void __launch_bounds__(64) k_damp(const Geo g, double* __restrict__ u
         }
 }
 
+// Damping with N lanes per element (same split as k_stage_c): lane k first
+// holds mode row k of u and of u0 and contracts them in y, then Gauss row k
+// (node values, nodal increments, x projection), then mode row k again
+// (y projection and the update).  EW = 64 / N listed elements per wave.
+template <int N, int CL>
+__global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const double* __restrict__ u0,
+                                               const double* __restrict__ eq, const int* __restrict__ list, int nlist,
+                                               const StageCoeffs* __restrict__ scp) {
+    constexpr BasisTab B = make_basis(N);
+    constexpr int NV = NVar<CL>::value;
+    constexpr int NN = N * N;
+    constexpr int EW = 64 / N;
+    constexpr int SLOT = 2 * NV * NN;
+    __shared__ double lds[(EW + 1) * SLOT];
+    const int lane = threadIdx.x;
+    const int sl = lane / N, k = lane - sl * N;
+    const int li = blockIdx.x * EW + sl;
+    const bool active = sl < EW && li < nlist;
+    const int e = list[active ? li : blockIdx.x * EW];  // idle lanes shadow a listed element
+    double* S = lds + sl * SLOT;
+    const double dt = scp->dt;
+    const int i = e % g.nx, j = e / g.nx;
+    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+    const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), req = make_rsrc(eq ? eq : u0);
+    const unsigned pstride = (unsigned)g.E * 8u;
+    const unsigned vrow = (unsigned)(k * N) * pstride + (unsigned)e * 8u;
+
+    // mode row k: y contraction of u (full state) and u0
+    double Ud[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double A[N], A0[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            const unsigned so = (unsigned)(v * NN + b) * pstride;
+            Ud[v][b] = ld64(ru, vrow, so);
+            A[b] = eq ? ld64(req, vrow, so) + Ud[v][b] : Ud[v][b];
+            A0[b] = ld64(ru0, vrow, so);
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double c = 0.0, c0 = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                c += A[b] * B.phi[b][r];
+                c0 += A0[b] * B.phi[b][r];
+            }
+            S[(v * N + k) * N + r] = c;
+            S[NV * NN + (v * N + k) * N + r] = c0;
+        }
+    }
+    __syncthreads();
+
+    // Gauss row k: nodal increments, projected in x
+    const double yk = yc + 0.5 * g.dy * pick<N>(B.xi, k);
+    double Cc[NV][N], C0[NV][N], P[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            Cc[v][a] = S[(v * N + a) * N + k];
+            C0[v][a] = S[NV * NN + (v * N + a) * N + k];
+            P[v][a] = 0.0;
+        }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double W[NV], W0[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s = 0.0, s0 = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                s += B.phi[a][q] * Cc[v][a];
+                s0 += B.phi[a][q] * C0[v][a];
+            }
+            W[v] = s;
+            W0[v] = s0;
+        }
+        const double x = xc + 0.5 * g.dx * B.xi[q];
+        double td;
+        const double R = ramp(g, sqrt(x * x + yk * yk), td);
+        double D[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) D[v] = 0.0;
+        if (R > 0.0) {
+            const double w = dt * R / (td + dt * R);
+            const double rho = W[0], vx = W[1] / rho, vy = W[2] / rho;
+            const double rho0 = W0[0], vx0 = W0[1] / rho0, vy0 = W0[2] / rho0;
+            const double drho = w * (rho0 - rho);
+            const double dvx = w * (vx0 - vx), dvy = w * (vy0 - vy);
+            const double vx1 = vx + dvx, vy1 = vy + dvy;
+            D[0] = drho;
+            D[1] = rho * dvx + drho * vx1;
+            D[2] = rho * dvy + drho * vy1;
+            if constexpr (NV == 4) {
+                const double gm1 = g.gamma - 1.0;
+                const double T1 = gm1 * (W[3] - 0.5 * rho * (vx * vx + vy * vy)) / rho;
+                const double T0 = gm1 * (W0[3] - 0.5 * rho0 * (vx0 * vx0 + vy0 * vy0)) / rho0;
+                const double dT = w * (T0 - T1);
+                const double dp = rho * dT + drho * (T1 + dT);
+                const double dke = 0.5 * (drho * (vx1 * vx1 + vy1 * vy1) + rho * (dvx * (vx1 + vx) + dvy * (vy1 + vy)));
+                D[3] = dp / gm1 + dke;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int a = 0; a < N; ++a) P[v][a] += B.wphi[a][q] * D[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) S[(v * N + k) * N + a] = P[v][a];
+    __syncthreads();
+
+    // mode row k: y projection and update
+    if (active) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < N; ++r) s += B.wphi[b][r] * S[(v * N + r) * N + k];
+                st64(ru, vrow, (unsigned)(v * NN + b) * pstride, Ud[v][b] + s);
+            }
+    }
+}
+
 // ------------------------------------------------------------------ torque
 constexpr int kTorqueBlock = 256;
 
@@ -1676,9 +1806,11 @@ hipError_t launch_step_begin(const Geo& g, StepBlock* sb, const double* dt_part,
 hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const double* eq, const int* list,
                        int nlist, const StageCoeffs* sc, hipStream_t s) {
     if (nlist <= 0) return hipSuccess;
-    const int blocks = (nlist + 63) / 64;
-    DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_damp<NT, CT>), dim3(blocks), dim3(64), 0, s, g,
-                                                                  u, u0, eq, list, nlist, sc)));
+    DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, {
+        constexpr int EW = 64 / NT;
+        const int blocks = (nlist + EW - 1) / EW;
+        hipLaunchKernelGGL((k_damp_c<NT, CT>), dim3(blocks), dim3(64), 0, s, g, u, u0, eq, list, nlist, sc);
+    }));
     return hipGetLastError();
 }
 
