@@ -1174,6 +1174,321 @@ __global__ void __launch_bounds__(64) k_stage_dev(const Geo g, const double* __r
         }
 }
 
+// Exterior collapse for the deviation form (FP64 deviation loaded, FP32
+// arithmetic), otherwise as ext_collapse.
+template <int N, bool ROW, int NB_SIDE>
+__device__ __forceinline__ void ext_collapse_f(rsrc_t ru, rsrc_t ru0, unsigned pstride, unsigned vnb, unsigned vown,
+                                               bool fixed, bool wave_fixed, float (&T)[3]) {
+    constexpr BasisTab B = make_basis(N);
+    constexpr int NN = N * N;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) T[v] = 0.0f;
+    if (!wave_fixed) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const unsigned so = (unsigned)(v * NN + (ROW ? m : m * N)) * pstride;
+                T[v] += (float)(NB_SIDE > 0 ? B.pp[m] : B.pm[m]) * (float)ld64(ru, vnb, so);
+            }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const unsigned so = (unsigned)(v * NN + (ROW ? m : m * N)) * pstride;
+                const float un = (float)ld64(ru, vnb, so);
+                const float u0v = (float)ld64(ru0, vown, so);
+                T[v] += fixed ? (float)(NB_SIDE > 0 ? B.pm[m] : B.pp[m]) * u0v
+                              : (float)(NB_SIDE > 0 ? B.pp[m] : B.pm[m]) * un;
+            }
+    }
+}
+
+// Rusanov flux of the deviation through an axis-aligned edge (outward normal
+// SGN e_AX) at a point with equilibrium q: the locally isothermal sound speed
+// is shared by both sides.
+template <int AX, int SGN>
+__device__ __forceinline__ void rusanov_dev(const EqPoint& q, const float* di, const float* dd, float* h) {
+    const float ii = 1.0f / (q.rho + di[0]), io = 1.0f / (q.rho + dd[0]);
+    float fi[3], fo[3];
+    dflux<AX>(q, di, ii, fi);
+    dflux<AX>(q, dd, io, fo);
+    const float alpha = fmaxf(fabsf(vnorm<AX, SGN>(q, di, ii)), fabsf(vnorm<AX, SGN>(q, dd, io))) + sqrtf(q.c2);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) h[v] = 0.5f * SGN * (fi[v] + fo[v]) - 0.5f * alpha * (dd[v] - di[v]);
+}
+
+// Deviation-form stage with N lanes per element: the phases of k_stage_c in
+// FP32 on the deviation (fluxes about the analytic equilibrium, stellar pull
+// on the density deviation, planet on the full density), then
+// out = a0 du^n + a1 du + a2 (L_eq + dL) in FP64.
+template <int N>
+__global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, int tiles_total,
+                                                    const double* __restrict__ du, const double* dun,
+                                                    const double* __restrict__ du0, const float* __restrict__ leq,
+                                                    double* out, const StageCoeffs* __restrict__ scp) {
+    constexpr int NV = 3;
+    constexpr int NN = N * N;
+    constexpr int EW = 64 / N;
+    constexpr BasisTab B = make_basis(N);
+    constexpr int P1 = NV * NN + 6 * NV * N;
+    constexpr int P2 = 2 * NV * NN + 4 * NV * N;
+    constexpr int SLOT = P1 > P2 ? P1 : P2;
+    __shared__ float lds[(EW + 1) * SLOT];
+
+    const int lane = threadIdx.x;
+    const int sl = lane / N, k = lane - sl * N;
+    const int tile = remap_tile(blockIdx.x, tiles_total);
+    const int j = tile / tiles_x;
+    const int i0 = (tile - j * tiles_x) * EW;
+    const bool active = sl < EW && i0 + sl < g.nx;
+    const int i = active ? i0 + sl : i0;
+    float* S = lds + sl * SLOT;
+
+    const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
+    const rsrc_t rdu = make_rsrc(du), rdu0 = make_rsrc(du0), rout = make_rsrc(out), rdun = make_rsrc(dun),
+                 rleq = make_rsrc(leq);
+    const unsigned pstride = (unsigned)g.E * 8u, pstride4 = (unsigned)g.E * 4u;
+    const unsigned e = (unsigned)j * (unsigned)g.nx + (unsigned)i;
+    const unsigned vrow = (unsigned)(k * N) * pstride + e * 8u;
+    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+
+    // ---- phase 1: k = mode row
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        float Ua[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) Ua[b] = (float)ld64(rdu, vrow, (unsigned)(v * NN + b) * pstride);
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            float c = 0.0f;
+#pragma unroll
+            for (int b = 0; b < N; ++b) c += Ua[b] * (float)B.phi[b][r];
+            S[(v * N + k) * N + r] = c;
+        }
+        float tm = 0.0f, tp = 0.0f;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            tm += (float)B.pm[b] * Ua[b];
+            tp += (float)B.pp[b] * Ua[b];
+        }
+        S[NV * NN + (0 * NV + v) * N + k] = tm;
+        S[NV * NN + (1 * NV + v) * N + k] = tp;
+    }
+    {
+        int il = i - 1, ir = i + 1, jb = j - 1, jt = j + 1;
+        const bool ol = il < 0, orr = ir >= g.nx, ob = jb < 0, ot = jt >= g.ny;
+        il += ol ? g.nx : 0;
+        ir -= orr ? g.nx : 0;
+        jb += ob ? g.ny : 0;
+        jt -= ot ? g.ny : 0;
+        const bool fx = g.bc == 1, fl = fx && ol, fr = fx && orr, fb = fx && ob, ft = fx && ot;
+        const bool wfx = __any(fl || fr), wfy = __any(fb || ft);
+        const unsigned vcol = (unsigned)k * pstride + e * 8u;
+        const unsigned kr = (unsigned)(k * N) * pstride, kc = (unsigned)k * pstride;
+        float T[NV];
+        ext_collapse_f<N, true, +1>(rdu, rdu0, pstride, kr + ((unsigned)jb * g.nx + i) * 8u, vrow, fb, wfy, T);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[NV * NN + (2 * NV + v) * N + k] = T[v];
+        ext_collapse_f<N, true, -1>(rdu, rdu0, pstride, kr + ((unsigned)jt * g.nx + i) * 8u, vrow, ft, wfy, T);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[NV * NN + (3 * NV + v) * N + k] = T[v];
+        ext_collapse_f<N, false, +1>(rdu, rdu0, pstride, kc + ((unsigned)j * g.nx + il) * 8u, vcol, fl, wfx, T);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[NV * NN + (4 * NV + v) * N + k] = T[v];
+        ext_collapse_f<N, false, -1>(rdu, rdu0, pstride, kc + ((unsigned)j * g.nx + ir) * 8u, vcol, fr, wfx, T);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[NV * NN + (5 * NV + v) * N + k] = T[v];
+    }
+    __syncthreads();
+
+    // ---- phase 2: k = Gauss row r
+    const double xik = pick<N>(B.xi, k);
+    float phk[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) phk[m] = (float)pick<N>(B.phi[m], k);
+    const double yk = yc + 0.5 * g.dy * xik;
+    float Cc[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) Cc[v][a] = S[(v * N + a) * N + k];
+    float X[NV][N], Y[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            X[v][a] = 0.0f;
+            Y[v][a] = 0.0f;
+        }
+    const float rdx2 = (float)g.rdx2, rdy2 = (float)g.rdy2;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        float d[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            float s = 0.0f;
+#pragma unroll
+            for (int a = 0; a < N; ++a) s += (float)B.phi[a][q] * Cc[v][a];
+            d[v] = s;
+        }
+        const double x = xc + 0.5 * g.dx * B.xi[q];
+        const EqPoint qe = eq_at(g, x, yk);
+        const float inv1 = 1.0f / (qe.rho + d[0]);
+        float fx[NV], fy[NV], sy[NV];
+        dflux<0>(qe, d, inv1, fx);
+        dflux<1>(qe, d, inv1, fy);
+        const float xf = (float)x, yf = (float)yk;
+        const float r2 = xf * xf + yf * yf, rr = sqrtf(r2);
+        const float ks = rr < (float)g.r_core ? (float)g.rc3inv : (float)g.gm / (r2 * rr);
+        float gsx = -d[0] * ks * xf, gsy = -d[0] * ks * yf;
+        if (g.q > 0.0) {
+            const float dx = (float)(x - xp), dy = (float)(yk - yp);
+            const float d2 = dx * dx + dy * dy + (float)g.eps2;
+            const float kp = (float)g.q * rsqrtf(d2) / d2;
+            const float rho = qe.rho + d[0];
+            gsx -= rho * kp * dx;
+            gsy -= rho * kp * dy;
+        }
+        sy[0] = 0.0f;
+        sy[1] = gsx;
+        sy[2] = gsy;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const float fxx = rdx2 * fx[v], fyy = rdy2 * fy[v];
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                X[v][a] += (float)B.wdphi[a][q] * fxx + (float)B.wphi[a][q] * sy[v];
+                Y[v][a] += (float)B.wphi[a][q] * fyy;
+            }
+        }
+    }
+    float hf[4][NV];
+    {
+        const float* Cl = S + NV * NN;
+        float di[NV], dd[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            float si = 0.0f, so = 0.0f;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += (float)B.pm[a] * Cc[v][a];
+                so += phk[a] * Cl[(4 * NV + v) * N + a];
+            }
+            di[v] = si;
+            dd[v] = so;
+        }
+        rusanov_dev<0, -1>(eq_at(g, xc - 0.5 * g.dx, yk), di, dd, hf[0]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            float si = 0.0f, so = 0.0f;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += (float)B.pp[a] * Cc[v][a];
+                so += phk[a] * Cl[(5 * NV + v) * N + a];
+            }
+            di[v] = si;
+            dd[v] = so;
+        }
+        rusanov_dev<0, 1>(eq_at(g, xc + 0.5 * g.dx, yk), di, dd, hf[1]);
+        const double xk = xc + 0.5 * g.dx * xik;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            float si = 0.0f, so = 0.0f;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += phk[a] * Cl[(0 * NV + v) * N + a];
+                so += phk[a] * Cl[(2 * NV + v) * N + a];
+            }
+            di[v] = si;
+            dd[v] = so;
+        }
+        rusanov_dev<1, -1>(eq_at(g, xk, yc - 0.5 * g.dy), di, dd, hf[2]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            float si = 0.0f, so = 0.0f;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += phk[a] * Cl[(1 * NV + v) * N + a];
+                so += phk[a] * Cl[(3 * NV + v) * N + a];
+            }
+            di[v] = si;
+            dd[v] = so;
+        }
+        rusanov_dev<1, 1>(eq_at(g, xk, yc + 0.5 * g.dy), di, dd, hf[3]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            S[((0 * NV + v) * N + k) * N + a] = X[v][a];
+            S[((1 * NV + v) * N + k) * N + a] = Y[v][a];
+        }
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[2 * NV * NN + (f * NV + v) * N + k] = hf[f][v];
+    __syncthreads();
+
+    // ---- phase 3: k = mode row a
+    float wrow[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double r = B.wphi[0][q];
+#pragma unroll
+        for (int m = 1; m < N; ++m) r = k == m ? B.wphi[m][q] : r;
+        wrow[q] = (float)r;
+    }
+    const float pmk = (float)pick<N>(B.pm, k), ppk = (float)pick<N>(B.pp, k);
+    const float idx = (float)g.idx, idy = (float)g.idy;
+    const float* H = S + 2 * NV * NN;
+    const unsigned vrow4 = (unsigned)(k * N) * pstride4 + e * 4u;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        float glb = 0.0f, glt = 0.0f;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            glb += wrow[q] * H[(2 * NV + v) * N + q];
+            glt += wrow[q] * H[(3 * NV + v) * N + q];
+        }
+        float hw[N], he[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            hw[r] = H[(0 * NV + v) * N + r];
+            he[r] = H[(1 * NV + v) * N + r];
+        }
+        float R[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            float acc = 0.0f, glw = 0.0f, gle = 0.0f;
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                acc += (float)B.wphi[b][r] * S[((0 * NV + v) * N + r) * N + k] +
+                       (float)B.wdphi[b][r] * S[((1 * NV + v) * N + r) * N + k];
+                glw += (float)B.wphi[b][r] * hw[r];
+                gle += (float)B.wphi[b][r] * he[r];
+            }
+            acc -= idx * (pmk * glw + ppk * gle);
+            acc -= idy * ((float)B.pm[b] * glb + (float)B.pp[b] * glt);
+            R[b] = acc;
+        }
+        if (active) {
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                const unsigned po = (unsigned)(v * NN + b) * pstride;
+                const double L = (double)ld32(rleq, vrow4, (unsigned)(v * NN + b) * pstride4) + (double)R[b];
+                const double base = a1 * ld64(rdu, vrow, po) + a2 * L;
+                if (a0 != 0.0)
+                    st64(rout, vrow, po, a0 * ld64(rdun, vrow, po) + base);
+                else
+                    st64(rout, vrow, po, base);
+            }
+        }
+    }
+}
+
 // out = a + sign * b, elementwise over a state array (out may alias b)
 __global__ void k_add_state(const double* a, const double* b, double* out, double sign, long long n) {
     const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -1818,8 +2133,12 @@ hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double*
                             const float* leq, double* out, const StageCoeffs* sc, hipStream_t s) {
     if (!dun) dun = du;
     if (!du0) du0 = du;
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_stage_dev<NT>), dim3(g.tiles_total), dim3(64), 0, s, g, du, dun, du0, leq,
-                                        out, sc));
+    DG_DISPATCH_N(n, {
+        constexpr int EW = 64 / NT;
+        const int tx = (g.nx + EW - 1) / EW;
+        const int tt = tx * g.ny;
+        hipLaunchKernelGGL((k_stage_dev_c<NT>), dim3(tt), dim3(64), 0, s, g, tx, tt, du, dun, du0, leq, out, sc);
+    });
     return hipGetLastError();
 }
 
