@@ -292,7 +292,7 @@ def main():
                    "final_torque": float(r64["torques"][-1].item()), "t_end": r64["t_end"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "k_stage (fused RK stage)", "avg_launch_us": avg_launch_s * 1e6,
+                     "kernel": "k_stage_c (fused RK stage, N lanes per element)", "avg_launch_us": avg_launch_s * 1e6,
                      "alg_bytes_per_launch": alg_bytes_per_launch},
         "fp64_model": fp64_model(cfg, avg_launch_s),
     }
