@@ -127,8 +127,6 @@ void make_geo(const dg_config* c, Geo* g) {
     g->nx = c->nx;
     g->ny = c->ny;
     g->E = (long long)c->nx * c->ny;
-    g->tiles_x = (c->nx + dgk::kWave - 1) / dgk::kWave;
-    g->tiles_total = g->tiles_x * c->ny;
     g->x0 = c->x0;
     g->y0 = c->y0;
     g->dx = (c->x1 - c->x0) / c->nx;

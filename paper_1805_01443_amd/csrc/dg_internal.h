@@ -8,14 +8,11 @@
 namespace dgk {
 
 constexpr int kMaxN = 5;  // orders 2..5 (P1..P4)
-constexpr int kWave = 64;
 
 // Mesh, closure and gravity parameters.
 struct Geo {
     int nx, ny;
     long long E;
-    int tiles_x;       // 64-element row tiles per row
-    int tiles_total;   // tiles_x * ny
     double x0, y0, dx, dy;
     double rdx2, rdy2; // 2/dx, 2/dy
     double idx, idy;   // 1/dx, 1/dy

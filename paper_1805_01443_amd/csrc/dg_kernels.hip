@@ -23,11 +23,6 @@ namespace dgk {
 
 enum { CL_ISO = 0, CL_LOC = 1, CL_ADI = 2 };
 
-// The same tables in constant memory, for loops whose index is a run-time
-// (wave-uniform) value: entries come in through the scalar cache.
-__constant__ BasisTab c_basis[kMaxOrder + 1] = {make_basis(0), make_basis(1), make_basis(2),
-                                                make_basis(3), make_basis(4), make_basis(5)};
-
 template <int CL>
 struct NVar {
     static constexpr int value = CL == CL_ADI ? 4 : 3;
@@ -171,327 +166,6 @@ __device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const do
     const double alpha = si > so ? si : so;
 #pragma unroll
     for (int v = 0; v < NV; ++v) h[v] = 0.5 * (Fi[v] + Fo[v]) - 0.5 * alpha * (Uo[v] - Ui[v]);
-}
-
-// Edge F (0 west, 1 east, 2 south, 3 north) of element (i, j): own trace from
-// the lane's LDS column, exterior trace from the neighbour's modes in global
-// memory (or the initial state at a fixed box edge), Rusanov flux at the n
-// edge Gauss points, lifted into R.
-template <int N, int CL, int F>
-__device__ __forceinline__ void edge_term(const Geo& g, const double* __restrict__ sU,
-                                          double (&R)[NVar<CL>::value][N * N], rsrc_t ru, rsrc_t ru0, int i, int j,
-                                          long long e, double xc, double yc) {
-    constexpr int NV = NVar<CL>::value;
-    constexpr int NN = N * N;
-    constexpr int AX = F < 2 ? 0 : 1;
-    constexpr int SGN = (F == 0 || F == 2) ? -1 : 1;
-    constexpr BasisTab B = make_basis(N);
-    const long long E = g.E;
-
-    int in = i + (F == 1) - (F == 0);
-    int jn = j + (F == 3) - (F == 2);
-    const bool outside = in < 0 || in >= g.nx || jn < 0 || jn >= g.ny;
-    if (in < 0) in += g.nx;
-    if (in >= g.nx) in -= g.nx;
-    if (jn < 0) jn += g.ny;
-    if (jn >= g.ny) jn -= g.ny;
-    const bool fixed = outside && g.bc == 1;
-    const bool wave_fixed = __any(fixed);  // only box-edge waves read the initial state
-    const unsigned eoff = (unsigned)e * 8u;
-    const unsigned noff = ((unsigned)jn * (unsigned)g.nx + (unsigned)in) * 8u;
-    const unsigned pstride = (unsigned)E * 8u;
-
-    // collapse the normal degree at the edge: ci (own), co (exterior).  Waves
-    // without a fixed box edge take the lean path; the others select per lane
-    // between the neighbour (opposite side) and the own initial state (same side).
-    double ci[NV][N], co[NV][N];
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            ci[v][k] = 0.0;
-            co[v][k] = 0.0;
-        }
-    if (!wave_fixed) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    const int m = v * NN + a * N + b;
-                    const double uo = ld64(ru, noff, (unsigned)m * pstride);
-                    const double ui = sU[m * kWave];
-                    const int c = AX == 0 ? a : b, o = AX == 0 ? b : a;
-                    const double so = SGN < 0 ? B.pm[c] : B.pp[c];
-                    const double sx = SGN < 0 ? B.pp[c] : B.pm[c];
-                    ci[v][o] += so * ui;
-                    co[v][o] += sx * uo;
-                }
-    } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    const int m = v * NN + a * N + b;
-                    const double un = ld64(ru, noff, (unsigned)m * pstride);
-                    const double u0v = ld64(ru0, eoff, (unsigned)m * pstride);
-                    const double ui = sU[m * kWave];
-                    const int c = AX == 0 ? a : b, o = AX == 0 ? b : a;
-                    const double so = SGN < 0 ? B.pm[c] : B.pp[c];
-                    const double sx = SGN < 0 ? B.pp[c] : B.pm[c];
-                    ci[v][o] += so * ui;
-                    co[v][o] += fixed ? so * u0v : sx * un;
-                }
-    }
-    double gl[NV][N];
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int m = 0; m < N; ++m) gl[v][m] = 0.0;
-#pragma unroll 1
-    for (int k = 0; k < N; ++k) {
-        // tables at edge point k (run-time index: scalar loads)
-        const BasisTab& CB = c_basis[N];
-        double phk[N], wpk[N];
-        const double xik = CB.xi[k];
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            phk[m] = CB.phi[m][k];
-            wpk[m] = CB.wphi[m][k];
-        }
-        double Ui[NV], Uo[NV], h[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double si = 0.0, so = 0.0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                si += ci[v][m] * phk[m];
-                so += co[v][m] * phk[m];
-            }
-            Ui[v] = si;
-            Uo[v] = so;
-        }
-        const double x = AX == 0 ? xc + SGN * 0.5 * g.dx : xc + 0.5 * g.dx * xik;
-        const double y = AX == 0 ? yc + 0.5 * g.dy * xik : yc + SGN * 0.5 * g.dy;
-        rusanov<CL, AX, SGN>(g, Ui, Uo, x, y, h);
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int m = 0; m < N; ++m) gl[v][m] += wpk[m] * h[v];
-    }
-    const double s = AX == 0 ? g.idx : g.idy;
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int a = 0; a < N; ++a)
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                if constexpr (AX == 0) {
-                    const double so = SGN < 0 ? B.pm[a] : B.pp[a];
-                    R[v][a * N + b] -= (s * so) * gl[v][b];
-                } else {
-                    const double so = SGN < 0 ? B.pm[b] : B.pp[b];
-                    R[v][a * N + b] -= (s * so) * gl[v][a];
-                }
-            }
-}
-
-// out = a0 u^n + a1 u + a2 L(u, t) for every element (a0 = 0: u^n not read).
-// `un` and `out` may alias (the last SSP stage updates u^n in place; each
-// thread reads and writes only its own element there).
-//
-// One thread per element.  The element's modes are staged in the lane's own
-// column of LDS (no lane reads another lane's column, so no barrier), which
-// keeps the residual R in registers without spilling.  The density residual
-// is the exact modal form of its volume integral, (2/dx) D mx + (2/dy) my D^T
-// with D the Legendre derivative matrix, and is written out first.
-template <int N, int CL>
-__global__ void __launch_bounds__(64) k_stage(const Geo g, const double* __restrict__ u, const double* un,
-                                              const double* __restrict__ u0, double* out,
-                                              const StageCoeffs* __restrict__ scp) {
-    constexpr int NV = NVar<CL>::value;
-    constexpr int NN = N * N;
-    constexpr BasisTab B = make_basis(N);
-    __shared__ double sAll[NV * NN * kWave];
-    const int tile = remap_tile(blockIdx.x, g.tiles_total);
-    const int j = tile / g.tiles_x;
-    const int i = (tile - j * g.tiles_x) * kWave + threadIdx.x;
-    if (i >= g.nx) return;
-    const long long E = g.E;
-    const long long e = (long long)j * g.nx + i;
-    const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
-    double* sU = sAll + threadIdx.x;  // this lane's column: sU[m * kWave]
-    const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), rout = make_rsrc(out), run = make_rsrc(un);
-    const unsigned eoff = (unsigned)e * 8u, pstride = (unsigned)E * 8u;
-
-#pragma unroll
-    for (int m = 0; m < NV * NN; ++m) sU[m * kWave] = ld64(ru, eoff, (unsigned)m * pstride);
-
-    double R[NV][NN];
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int m = 0; m < NN; ++m) R[v][m] = 0.0;
-    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
-
-    // edge integrals, one edge per iteration of a runtime loop so that the
-    // four edges' neighbour loads and temporaries are never live together
-#pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
-        asm volatile("" ::: "memory");
-        if (f == 0)
-            edge_term<N, CL, 0>(g, sU, R, ru, ru0, i, j, e, xc, yc);
-        else if (f == 1)
-            edge_term<N, CL, 1>(g, sU, R, ru, ru0, i, j, e, xc, yc);
-        else if (f == 2)
-            edge_term<N, CL, 2>(g, sU, R, ru, ru0, i, j, e, xc, yc);
-        else
-            edge_term<N, CL, 3>(g, sU, R, ru, ru0, i, j, e, xc, yc);
-    }
-
-    // density: volume term in modal form, then the stage update
-#pragma unroll
-    for (int a = 0; a < N; ++a)
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-            double sx = 0.0, sy = 0.0;
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                if (B.D[a][c] != 0.0) sx += B.D[a][c] * sU[(1 * NN + c * N + b) * kWave];
-                if (B.D[b][c] != 0.0) sy += B.D[b][c] * sU[(2 * NN + a * N + c) * kWave];
-            }
-            R[0][a * N + b] += g.rdx2 * sx + g.rdy2 * sy;
-        }
-    if (a0 != 0.0) {
-#pragma unroll
-        for (int m = 0; m < NN; ++m) {
-            const unsigned po = (unsigned)m * pstride;
-            st64(rout, eoff, po, a0 * ld64(run, eoff, po) + (a1 * sU[m * kWave] + a2 * R[0][m]));
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < NN; ++m)
-            st64(rout, eoff, (unsigned)m * pstride, a1 * sU[m * kWave] + a2 * R[0][m]);
-    }
-
-    // momentum (and energy): volume integrals one Gauss column xi_q at a time
-#pragma unroll 1
-    for (int q = 0; q < N; ++q) {
-        asm volatile("" ::: "memory");
-        const BasisTab& CB = c_basis[N];
-        const double xiq = CB.xi[q];
-        double wpq[N], wdpq[N], phq[N];
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            wpq[a] = CB.wphi[a][q];
-            wdpq[a] = CB.wdphi[a][q];
-            phq[a] = CB.phi[a][q];
-        }
-        const double x = xc + 0.5 * g.dx * xiq;
-        double c[NV][N];
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                double s = 0.0;
-#pragma unroll
-                for (int a = 0; a < N; ++a) s += phq[a] * sU[(v * NN + a * N + b) * kWave];
-                c[v][b] = s;
-            }
-        double Ax[NV][N], By[NV][N];
-#pragma unroll
-        for (int v = 1; v < NV; ++v)
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                Ax[v][b] = 0.0;
-                By[v][b] = 0.0;
-            }
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double W[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                double s = 0.0;
-#pragma unroll
-                for (int b = 0; b < N; ++b) s += c[v][b] * B.phi[b][r];
-                W[v] = s;
-            }
-            const double y = yc + 0.5 * g.dy * B.xi[r];
-            const double inv = rcp64(W[0]);
-            // one 1/r for the locally isothermal pressure and the stellar pull
-            const double r2 = x * x + y * y;
-            const double ir = (CL == CL_LOC || g.star) ? rsq64(r2) : 0.0;
-            double p;
-            if constexpr (CL == CL_ISO)
-                p = g.cs2 * W[0];
-            else if constexpr (CL == CL_LOC)
-                p = cs2_loc(g, r2, ir) * W[0];
-            else
-                p = (g.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) * inv);
-            const double vx = W[1] * inv, vy = W[2] * inv;
-            double gx = 0.0, gy = 0.0;
-            if (g.star) {
-                const double k = r2 < g.rc2 ? g.rc3inv : g.gm * ir * ir * ir;
-                gx = k * x;
-                gy = k * y;
-            }
-            if (g.q > 0.0) {
-                const double dx = x - xp, dy = y - yp;
-                const double id = rsq64(dx * dx + dy * dy + g.eps2);
-                const double k = g.q * id * id * id;
-                gx += k * dx;
-                gy += k * dy;
-            }
-            double fx[NV], sy[NV], fy[NV];
-            fx[1] = W[1] * vx + p;
-            fy[1] = W[1] * vy;
-            fx[2] = W[2] * vx;
-            fy[2] = W[2] * vy + p;
-            sy[1] = -W[0] * gx;
-            sy[2] = -W[0] * gy;
-            if constexpr (NV == 4) {
-                fx[3] = (W[3] + p) * vx;
-                fy[3] = (W[3] + p) * vy;
-                sy[3] = -(W[1] * gx + W[2] * gy);
-            }
-#pragma unroll
-            for (int v = 1; v < NV; ++v) {
-                const double fyy = g.rdy2 * fy[v];
-#pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    Ax[v][b] += B.wphi[b][r] * fx[v];
-                    By[v][b] += B.wdphi[b][r] * fyy + B.wphi[b][r] * sy[v];
-                }
-            }
-        }
-#pragma unroll
-        for (int v = 1; v < NV; ++v)
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-                for (int b = 0; b < N; ++b)
-                    R[v][a * N + b] += (g.rdx2 * wdpq[a]) * Ax[v][b] + wpq[a] * By[v][b];
-    }
-
-    // RK stage combination (Shu-Osher form of SSP(3,3)) or plain L(u)
-    if (a0 != 0.0) {
-#pragma unroll
-        for (int v = 1; v < NV; ++v)
-#pragma unroll
-            for (int m = 0; m < NN; ++m) {
-                const unsigned po = (unsigned)(v * NN + m) * pstride;
-                st64(rout, eoff, po, a0 * ld64(run, eoff, po) + (a1 * sU[(v * NN + m) * kWave] + a2 * R[v][m]));
-            }
-    } else {
-#pragma unroll
-        for (int v = 1; v < NV; ++v)
-#pragma unroll
-            for (int m = 0; m < NN; ++m)
-                st64(rout, eoff, (unsigned)(v * NN + m) * pstride, a1 * sU[(v * NN + m) * kWave] + a2 * R[v][m]);
-    }
 }
 
 // ------------------------------------------------------------------ stage kernel, N lanes per element
@@ -889,289 +563,6 @@ template <int AX, int SGN>
 __device__ __forceinline__ float vnorm(const EqPoint& q, const float* d, float inv1) {
     const float v = AX == 0 ? q.vx + (d[1] - q.vx * d[0]) * inv1 : q.vy + (d[2] - q.vy * d[0]) * inv1;
     return SGN * v;
-}
-
-template <int N, int F>
-__device__ __forceinline__ void edge_term_dev(const Geo& g, const float* __restrict__ sD, float (&R)[3][N * N],
-                                              rsrc_t rdu, rsrc_t rdu0, int i, int j, long long e, double xc,
-                                              double yc) {
-    constexpr int NN = N * N;
-    constexpr int AX = F < 2 ? 0 : 1;
-    constexpr int SGN = (F == 0 || F == 2) ? -1 : 1;
-    constexpr BasisTab B = make_basis(N);
-    const long long E = g.E;
-    int in = i + (F == 1) - (F == 0);
-    int jn = j + (F == 3) - (F == 2);
-    const bool outside = in < 0 || in >= g.nx || jn < 0 || jn >= g.ny;
-    if (in < 0) in += g.nx;
-    if (in >= g.nx) in -= g.nx;
-    if (jn < 0) jn += g.ny;
-    if (jn >= g.ny) jn -= g.ny;
-    const bool fixed = outside && g.bc == 1;
-    const bool wave_fixed = __any(fixed);
-    const unsigned eoff = (unsigned)e * 8u;
-    const unsigned noff = ((unsigned)jn * (unsigned)g.nx + (unsigned)in) * 8u;
-    const unsigned pstride = (unsigned)E * 8u;
-    float ci[3][N], co[3][N];
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            ci[v][k] = 0.0f;
-            co[v][k] = 0.0f;
-        }
-    if (!wave_fixed) {
-#pragma unroll
-        for (int v = 0; v < 3; ++v)
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    const int m = v * NN + a * N + b;
-                    const float uo = (float)ld64(rdu, noff, (unsigned)m * pstride);
-                    const float ui = sD[m * kWave];
-                    const int c = AX == 0 ? a : b, o = AX == 0 ? b : a;
-                    const float so = (float)(SGN < 0 ? B.pm[c] : B.pp[c]);
-                    const float sx = (float)(SGN < 0 ? B.pp[c] : B.pm[c]);
-                    ci[v][o] += so * ui;
-                    co[v][o] += sx * uo;
-                }
-    } else {
-#pragma unroll
-        for (int v = 0; v < 3; ++v)
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    const int m = v * NN + a * N + b;
-                    const float un = (float)ld64(rdu, noff, (unsigned)m * pstride);
-                    const float u0v = (float)ld64(rdu0, eoff, (unsigned)m * pstride);
-                    const float ui = sD[m * kWave];
-                    const int c = AX == 0 ? a : b, o = AX == 0 ? b : a;
-                    const float so = (float)(SGN < 0 ? B.pm[c] : B.pp[c]);
-                    const float sx = (float)(SGN < 0 ? B.pp[c] : B.pm[c]);
-                    ci[v][o] += so * ui;
-                    co[v][o] += fixed ? so * u0v : sx * un;
-                }
-    }
-    float gl[3][N];
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int m = 0; m < N; ++m) gl[v][m] = 0.0f;
-#pragma unroll 1
-    for (int k = 0; k < N; ++k) {
-        // tables at edge point k (run-time index: scalar loads)
-        const BasisTab& CB = c_basis[N];
-        float phk[N], wpk[N];
-        const double xik = CB.xi[k];
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            phk[m] = (float)CB.phi[m][k];
-            wpk[m] = (float)CB.wphi[m][k];
-        }
-        float di[3], dd[3];
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            float si = 0.0f, so = 0.0f;
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                si += ci[v][m] * phk[m];
-                so += co[v][m] * phk[m];
-            }
-            di[v] = si;
-            dd[v] = so;
-        }
-        const double x = AX == 0 ? xc + SGN * 0.5 * g.dx : xc + 0.5 * g.dx * xik;
-        const double y = AX == 0 ? yc + 0.5 * g.dy * xik : yc + SGN * 0.5 * g.dy;
-        const EqPoint q = eq_at(g, x, y);
-        const float ii = 1.0f / (q.rho + di[0]), io = 1.0f / (q.rho + dd[0]);
-        float fi[3], fo[3];
-        dflux<AX>(q, di, ii, fi);
-        dflux<AX>(q, dd, io, fo);
-        const float c = sqrtf(q.c2);
-        const float alpha = fmaxf(fabsf(vnorm<AX, SGN>(q, di, ii)), fabsf(vnorm<AX, SGN>(q, dd, io))) + c;
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            const float h = 0.5f * SGN * (fi[v] + fo[v]) - 0.5f * alpha * (dd[v] - di[v]);
-#pragma unroll
-            for (int m = 0; m < N; ++m) gl[v][m] += wpk[m] * h;
-        }
-    }
-    const float s = (float)(AX == 0 ? g.idx : g.idy);
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int a = 0; a < N; ++a)
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                if constexpr (AX == 0) {
-                    const float so = (float)(SGN < 0 ? B.pm[a] : B.pp[a]);
-                    R[v][a * N + b] -= (s * so) * gl[v][b];
-                } else {
-                    const float so = (float)(SGN < 0 ? B.pm[b] : B.pp[b]);
-                    R[v][a * N + b] -= (s * so) * gl[v][a];
-                }
-            }
-}
-
-// deviation-form stage: out = a0 du^n + a1 du + a2 (L_eq + dL(du, t))
-template <int N>
-__global__ void __launch_bounds__(64) k_stage_dev(const Geo g, const double* __restrict__ du, const double* dun,
-                                                  const double* __restrict__ du0, const float* __restrict__ leq,
-                                                  double* out, const StageCoeffs* __restrict__ scp) {
-    constexpr int NN = N * N;
-    constexpr BasisTab B = make_basis(N);
-    __shared__ float sAll[3 * NN * kWave];
-    const int tile = remap_tile(blockIdx.x, g.tiles_total);
-    const int j = tile / g.tiles_x;
-    const int i = (tile - j * g.tiles_x) * kWave + threadIdx.x;
-    if (i >= g.nx) return;
-    const long long E = g.E;
-    const long long e = (long long)j * g.nx + i;
-    const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
-    float* sD = sAll + threadIdx.x;
-    const rsrc_t rdu = make_rsrc(du), rdu0 = make_rsrc(du0), rdun = make_rsrc(dun), rout = make_rsrc(out),
-                 rleq = make_rsrc(leq);
-    const unsigned eoff = (unsigned)e * 8u, eoff4 = (unsigned)e * 4u, pstride = (unsigned)E * 8u,
-                   pstride4 = (unsigned)E * 4u;
-#pragma unroll
-    for (int m = 0; m < 3 * NN; ++m) sD[m * kWave] = (float)ld64(rdu, eoff, (unsigned)m * pstride);
-    float R[3][NN];
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int m = 0; m < NN; ++m) R[v][m] = 0.0f;
-    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
-
-#pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
-        asm volatile("" ::: "memory");
-        if (f == 0)
-            edge_term_dev<N, 0>(g, sD, R, rdu, rdu0, i, j, e, xc, yc);
-        else if (f == 1)
-            edge_term_dev<N, 1>(g, sD, R, rdu, rdu0, i, j, e, xc, yc);
-        else if (f == 2)
-            edge_term_dev<N, 2>(g, sD, R, rdu, rdu0, i, j, e, xc, yc);
-        else
-            edge_term_dev<N, 3>(g, sD, R, rdu, rdu0, i, j, e, xc, yc);
-    }
-
-    // density: modal volume term (linear in the momentum deviation)
-    const float rdx2 = (float)g.rdx2, rdy2 = (float)g.rdy2;
-#pragma unroll
-    for (int a = 0; a < N; ++a)
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-            float sx = 0.0f, sy = 0.0f;
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                if (B.D[a][c] != 0.0) sx += (float)B.D[a][c] * sD[(1 * NN + c * N + b) * kWave];
-                if (B.D[b][c] != 0.0) sy += (float)B.D[b][c] * sD[(2 * NN + a * N + c) * kWave];
-            }
-            R[0][a * N + b] += rdx2 * sx + rdy2 * sy;
-        }
-#pragma unroll
-    for (int m = 0; m < NN; ++m) {
-        const unsigned po = (unsigned)m * pstride;
-        const double L = (double)ld32(rleq, eoff4, (unsigned)m * pstride4) + (double)R[0][m];
-        const double base = a1 * ld64(rdu, eoff, po) + a2 * L;
-        if (a0 != 0.0)
-            st64(rout, eoff, po, a0 * ld64(rdun, eoff, po) + base);
-        else
-            st64(rout, eoff, po, base);
-    }
-
-#pragma unroll 1
-    for (int q = 0; q < N; ++q) {
-        asm volatile("" ::: "memory");
-        const BasisTab& CB = c_basis[N];
-        const double xiq = CB.xi[q];
-        float wpq[N], wdpq[N], phq[N];
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            wpq[a] = (float)CB.wphi[a][q];
-            wdpq[a] = (float)CB.wdphi[a][q];
-            phq[a] = (float)CB.phi[a][q];
-        }
-        const double x = xc + 0.5 * g.dx * xiq;
-        float c[3][N];
-#pragma unroll
-        for (int v = 0; v < 3; ++v)
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                float s = 0.0f;
-#pragma unroll
-                for (int a = 0; a < N; ++a) s += phq[a] * sD[(v * NN + a * N + b) * kWave];
-                c[v][b] = s;
-            }
-        float Ax[3][N], By[3][N];
-#pragma unroll
-        for (int v = 1; v < 3; ++v)
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                Ax[v][b] = 0.0f;
-                By[v][b] = 0.0f;
-            }
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            float d[3];
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                float s = 0.0f;
-#pragma unroll
-                for (int b = 0; b < N; ++b) s += c[v][b] * (float)B.phi[b][r];
-                d[v] = s;
-            }
-            const double y = yc + 0.5 * g.dy * B.xi[r];
-            const EqPoint qe = eq_at(g, x, y);
-            const float inv1 = 1.0f / (qe.rho + d[0]);
-            float fx[3], fy[3];
-            dflux<0>(qe, d, inv1, fx);
-            dflux<1>(qe, d, inv1, fy);
-            // stellar pull on the density deviation, planet on the full density
-            const float xf = (float)x, yf = (float)y;
-            const float r2 = xf * xf + yf * yf, rr = sqrtf(r2);
-            const float ks = rr < (float)g.r_core ? (float)g.rc3inv : (float)g.gm / (r2 * rr);
-            float sx = -d[0] * ks * xf, sy = -d[0] * ks * yf;
-            if (g.q > 0.0) {
-                const float dx = (float)(x - xp), dy = (float)(y - yp);
-                const float d2 = dx * dx + dy * dy + (float)g.eps2;
-                const float kp = (float)g.q * rsqrtf(d2) / d2;
-                const float rho = qe.rho + d[0];
-                sx -= rho * kp * dx;
-                sy -= rho * kp * dy;
-            }
-            const float fyy1 = rdy2 * fy[1], fyy2 = rdy2 * fy[2];
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                const float wp = (float)B.wphi[b][r], wd = (float)B.wdphi[b][r];
-                Ax[1][b] += wp * fx[1];
-                Ax[2][b] += wp * fx[2];
-                By[1][b] += wd * fyy1 + wp * sx;
-                By[2][b] += wd * fyy2 + wp * sy;
-            }
-        }
-#pragma unroll
-        for (int v = 1; v < 3; ++v)
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-                for (int b = 0; b < N; ++b)
-                    R[v][a * N + b] += (rdx2 * wdpq[a]) * Ax[v][b] + wpq[a] * By[v][b];
-    }
-#pragma unroll
-    for (int v = 1; v < 3; ++v)
-#pragma unroll
-        for (int m = 0; m < NN; ++m) {
-            const unsigned po = (unsigned)(v * NN + m) * pstride;
-            const double L = (double)ld32(rleq, eoff4, (unsigned)(v * NN + m) * pstride4) + (double)R[v][m];
-            const double base = a1 * ld64(rdu, eoff, po) + a2 * L;
-            if (a0 != 0.0)
-                st64(rout, eoff, po, a0 * ld64(rdun, eoff, po) + base);
-            else
-                st64(rout, eoff, po, base);
-        }
 }
 
 // Exterior collapse for the deviation form (FP64 deviation loaded, FP32
@@ -1745,94 +1136,6 @@ __device__ __forceinline__ double ramp(const Geo& g, double r, double& td) {
     }
     td = g.td_in;
     return 0.0;
-}
-
-template <int N, int CL>
-__global__ void __launch_bounds__(64) k_damp(const Geo g, double* __restrict__ u,
-                                             const double* __restrict__ u0, const double* __restrict__ eq,
-                                             const int* __restrict__ list, int nlist,
-                                             const StageCoeffs* __restrict__ scp) {
-    constexpr BasisTab T = make_basis(N);
-    constexpr int NV = NVar<CL>::value;
-    constexpr int NN = N * N;
-    const int idx = blockIdx.x * 64 + threadIdx.x;
-    if (idx >= nlist) return;
-    const long long e = list[idx];
-    const long long E = g.E;
-    const double dt = scp->dt;
-    const int i = (int)(e % g.nx), j = (int)(e / g.nx);
-    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
-    double M[NV][NN], W[NV][NN], W0[NV][NN];
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int m = 0; m < NN; ++m) M[v][m] = u0[(long long)(v * NN + m) * E + e];
-    eval_nodes<N, NV>(M, W0);
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int m = 0; m < NN; ++m) {
-            const long long idx = (long long)(v * NN + m) * E + e;
-            M[v][m] = eq ? eq[idx] + u[idx] : u[idx];  // full state (deviation form: u_eq + du)
-        }
-    eval_nodes<N, NV>(M, W);
-    // nodal increments (written over W)
-#pragma unroll
-    for (int q = 0; q < N; ++q)
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const int k = q * N + r;
-            const double x = xc + 0.5 * g.dx * T.xi[q], y = yc + 0.5 * g.dy * T.xi[r];
-            double td;
-            const double R = ramp(g, sqrt(x * x + y * y), td);
-            if (R <= 0.0) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) W[v][k] = 0.0;
-                continue;
-            }
-            const double w = dt * R / (td + dt * R);
-            const double rho = W[0][k], vx = W[1][k] / rho, vy = W[2][k] / rho;
-            const double rho0 = W0[0][k], vx0 = W0[1][k] / rho0, vy0 = W0[2][k] / rho0;
-            const double drho = w * (rho0 - rho);
-            const double dvx = w * (vx0 - vx), dvy = w * (vy0 - vy);
-            const double vx1 = vx + dvx, vy1 = vy + dvy;
-            double D3 = 0.0;
-            if constexpr (NV == 4) {
-                const double gm1 = g.gamma - 1.0;
-                const double T1 = gm1 * (W[3][k] - 0.5 * rho * (vx * vx + vy * vy)) / rho;
-                const double T0 = gm1 * (W0[3][k] - 0.5 * rho0 * (vx0 * vx0 + vy0 * vy0)) / rho0;
-                const double dT = w * (T0 - T1);
-                const double dp = rho * dT + drho * (T1 + dT);
-                const double dke = 0.5 * (drho * (vx1 * vx1 + vy1 * vy1) + rho * (dvx * (vx1 + vx) + dvy * (vy1 + vy)));
-                D3 = dp / gm1 + dke;
-            }
-            W[0][k] = drho;
-            W[1][k] = rho * dvx + drho * vx1;
-            W[2][k] = rho * dvy + drho * vy1;
-            if constexpr (NV == 4) W[3][k] = D3;
-        }
-    // project the increments and add them to the modes
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            double c[N];
-#pragma unroll
-            for (int r = 0; r < N; ++r) {
-                double s = 0.0;
-#pragma unroll
-                for (int q = 0; q < N; ++q) s += T.wh[q] * T.phi[a][q] * W[v][q * N + r];
-                c[r] = s;
-            }
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                double s = 0.0;
-#pragma unroll
-                for (int r = 0; r < N; ++r) s += T.wh[r] * T.phi[b][r] * c[r];
-                const long long idx = (long long)(v * NN + a * N + b) * E + e;
-                u[idx] = u[idx] + s;
-            }
-        }
 }
 
 // Damping with N lanes per element (same split as k_stage_c): lane k first
