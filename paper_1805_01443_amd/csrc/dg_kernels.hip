@@ -179,40 +179,6 @@ __device__ __forceinline__ double pick(const double (&t)[kMaxOrder], int k) {
     return r;
 }
 
-// Collapse of the exterior state across one edge for lane k: the neighbour's
-// row k (ROW: modes (k, b), summed over b) or column k (modes (a, k), summed
-// over a) with the basis values of the neighbour's far side NB_SIDE, or, at a
-// fixed box edge, the element's own initial row/column with the near side.
-// vnb / vown: the lane's byte offset of mode (k, 0) resp. (0, k) of the
-// neighbour / of the element itself.
-template <int N, int NV, bool ROW, int NB_SIDE>
-__device__ __forceinline__ void ext_collapse(rsrc_t ru, rsrc_t ru0, unsigned pstride, unsigned vnb, unsigned vown,
-                                             bool fixed, bool wave_fixed, double (&T)[NV]) {
-    constexpr BasisTab B = make_basis(N);
-    constexpr int NN = N * N;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) T[v] = 0.0;
-    if (!wave_fixed) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const unsigned so = (unsigned)(v * NN + (ROW ? m : m * N)) * pstride;
-                T[v] += (NB_SIDE > 0 ? B.pp[m] : B.pm[m]) * ld64(ru, vnb, so);
-            }
-    } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const unsigned so = (unsigned)(v * NN + (ROW ? m : m * N)) * pstride;
-                const double un = ld64(ru, vnb, so);
-                const double u0v = ld64(ru0, vown, so);
-                T[v] += fixed ? (NB_SIDE > 0 ? B.pm[m] : B.pp[m]) * u0v : (NB_SIDE > 0 ? B.pp[m] : B.pm[m]) * un;
-            }
-    }
-}
-
 // out = a0 u^n + a1 u + a2 L(u, t), with the N lanes of an element sharing
 // its tensor-product contractions.  Lane (s, k): element slot s = lane / N of
 // the wave (EW = 64 / N consecutive elements of one row), index k = lane % N.
@@ -259,12 +225,52 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     const unsigned vrow = (unsigned)(k * N) * pstride + e * 8u;  // mode (k, 0) of this element
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
 
-    // ---- phase 1: k = mode row
-    double Ua[NV][N];
+    // ---- phase 1: k = mode row.  Every global load of the phase is issued
+    // before the first use: the own row k, the y neighbours' rows k and the x
+    // neighbours' columns k (at a fixed box edge the own initial row/column).
+    int il = i - 1, ir = i + 1, jb = j - 1, jt = j + 1;
+    const bool ol = il < 0, orr = ir >= g.nx, ob = jb < 0, ot = jt >= g.ny;
+    il += ol ? g.nx : 0;
+    ir -= orr ? g.nx : 0;
+    jb += ob ? g.ny : 0;
+    jt -= ot ? g.ny : 0;
+    const bool fxd = g.bc == 1, fl = fxd && ol, fr = fxd && orr, fb = fxd && ob, ft = fxd && ot;
+    const unsigned vcol = (unsigned)k * pstride + e * 8u;  // mode (0, k)
+    const unsigned kr = (unsigned)(k * N) * pstride, kc = (unsigned)k * pstride;
+    const unsigned vb = kr + ((unsigned)jb * g.nx + i) * 8u, vt = kr + ((unsigned)jt * g.nx + i) * 8u;
+    const unsigned vl = kc + ((unsigned)j * g.nx + il) * 8u, vr = kc + ((unsigned)j * g.nx + ir) * 8u;
+    double Ua[NV][N], Xb[NV][N], Xt[NV][N], Xl[NV][N], Xr[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int b = 0; b < N; ++b) Ua[v][b] = ld64(ru, vrow, (unsigned)(v * NN + b) * pstride);
+        for (int m = 0; m < N; ++m) {
+            const unsigned srow = (unsigned)(v * NN + m) * pstride, scol = (unsigned)(v * NN + m * N) * pstride;
+            Ua[v][m] = ld64(ru, vrow, srow);
+            Xb[v][m] = ld64(ru, vb, srow);
+            Xt[v][m] = ld64(ru, vt, srow);
+            Xl[v][m] = ld64(ru, vl, scol);
+            Xr[v][m] = ld64(ru, vr, scol);
+        }
+    if (__any(fb || ft)) {  // wave-uniform: waves on a fixed bottom/top box edge
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const double o = ld64(ru0, vrow, (unsigned)(v * NN + m) * pstride);
+                Xb[v][m] = fb ? o : Xb[v][m];
+                Xt[v][m] = ft ? o : Xt[v][m];
+            }
+    }
+    if (__any(fl || fr)) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const double o = ld64(ru0, vcol, (unsigned)(v * NN + m * N) * pstride);
+                Xl[v][m] = fl ? o : Xl[v][m];
+                Xr[v][m] = fr ? o : Xr[v][m];
+            }
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
@@ -274,39 +280,24 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             for (int b = 0; b < N; ++b) c += Ua[v][b] * B.phi[b][r];
             S[(v * N + k) * N + r] = c;
         }
-        double tm = 0.0, tp = 0.0;
+        // own y collapses; exterior collapses with the neighbour's far side or,
+        // at a fixed box edge, the element's near side
+        double tm = 0.0, tp = 0.0, tb = 0.0, tt = 0.0, sl2 = 0.0, sr = 0.0;
 #pragma unroll
-        for (int b = 0; b < N; ++b) {
-            tm += B.pm[b] * Ua[v][b];
-            tp += B.pp[b] * Ua[v][b];
+        for (int m = 0; m < N; ++m) {
+            tm += B.pm[m] * Ua[v][m];
+            tp += B.pp[m] * Ua[v][m];
+            tb += (fb ? B.pm[m] : B.pp[m]) * Xb[v][m];
+            tt += (ft ? B.pp[m] : B.pm[m]) * Xt[v][m];
+            sl2 += (fl ? B.pm[m] : B.pp[m]) * Xl[v][m];
+            sr += (fr ? B.pp[m] : B.pm[m]) * Xr[v][m];
         }
         S[NV * NN + (0 * NV + v) * N + k] = tm;
         S[NV * NN + (1 * NV + v) * N + k] = tp;
-    }
-    {
-        int il = i - 1, ir = i + 1, jb = j - 1, jt = j + 1;
-        const bool ol = il < 0, orr = ir >= g.nx, ob = jb < 0, ot = jt >= g.ny;
-        il += ol ? g.nx : 0;
-        ir -= orr ? g.nx : 0;
-        jb += ob ? g.ny : 0;
-        jt -= ot ? g.ny : 0;
-        const bool fx = g.bc == 1, fl = fx && ol, fr = fx && orr, fb = fx && ob, ft = fx && ot;
-        const bool wfx = __any(fl || fr), wfy = __any(fb || ft);
-        const unsigned vcol = (unsigned)k * pstride + e * 8u;  // mode (0, k)
-        const unsigned kr = (unsigned)(k * N) * pstride, kc = (unsigned)k * pstride;
-        double T[NV];
-        ext_collapse<N, NV, true, +1>(ru, ru0, pstride, kr + ((unsigned)jb * g.nx + i) * 8u, vrow, fb, wfy, T);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) S[NV * NN + (2 * NV + v) * N + k] = T[v];
-        ext_collapse<N, NV, true, -1>(ru, ru0, pstride, kr + ((unsigned)jt * g.nx + i) * 8u, vrow, ft, wfy, T);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) S[NV * NN + (3 * NV + v) * N + k] = T[v];
-        ext_collapse<N, NV, false, +1>(ru, ru0, pstride, kc + ((unsigned)j * g.nx + il) * 8u, vcol, fl, wfx, T);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) S[NV * NN + (4 * NV + v) * N + k] = T[v];
-        ext_collapse<N, NV, false, -1>(ru, ru0, pstride, kc + ((unsigned)j * g.nx + ir) * 8u, vcol, fr, wfx, T);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) S[NV * NN + (5 * NV + v) * N + k] = T[v];
+        S[NV * NN + (2 * NV + v) * N + k] = tb;
+        S[NV * NN + (3 * NV + v) * N + k] = tt;
+        S[NV * NN + (4 * NV + v) * N + k] = sl2;
+        S[NV * NN + (5 * NV + v) * N + k] = sr;
     }
     __syncthreads();
 
@@ -472,6 +463,20 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     }
     const double pmk = pick<N>(B.pm, k), ppk = pick<N>(B.pp, k);
     const double* H = S + 2 * NV * NN;
+    // the row's u and u^n, issued before any store (out may alias u^n, so a
+    // load after a store could not be moved ahead of it); u comes back from L2
+    double U1[NV][N], Un[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int b = 0; b < N; ++b) U1[v][b] = ld64(ru, vrow, (unsigned)(v * NN + b) * pstride);
+    if (a0 != 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) Un[v][b] = ld64(run, vrow, (unsigned)(v * NN + b) * pstride);
+    }
+    double R[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         double glb = 0.0, glt = 0.0;
@@ -486,7 +491,6 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             hw[r] = H[(0 * NV + v) * N + r];
             he[r] = H[(1 * NV + v) * N + r];
         }
-        double R[N];
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             double acc = 0.0, glw = 0.0, gle = 0.0;
@@ -498,20 +502,22 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             }
             acc -= g.idx * (pmk * glw + ppk * gle);
             acc -= g.idy * (B.pm[b] * glb + B.pp[b] * glt);
-            R[b] = acc;
+            R[v][b] = acc;
         }
-        if (active) {
-            if (a0 != 0.0) {
+    }
+    if (active) {
+        if (a0 != 0.0) {
 #pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    const unsigned po = (unsigned)(v * NN + b) * pstride;
-                    st64(rout, vrow, po, a0 * ld64(run, vrow, po) + (a1 * Ua[v][b] + a2 * R[b]));
-                }
-            } else {
+            for (int v = 0; v < NV; ++v)
 #pragma unroll
                 for (int b = 0; b < N; ++b)
-                    st64(rout, vrow, (unsigned)(v * NN + b) * pstride, a1 * Ua[v][b] + a2 * R[b]);
-            }
+                    st64(rout, vrow, (unsigned)(v * NN + b) * pstride, a0 * Un[v][b] + (a1 * U1[v][b] + a2 * R[v][b]));
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+                    st64(rout, vrow, (unsigned)(v * NN + b) * pstride, a1 * U1[v][b] + a2 * R[v][b]);
         }
     }
 }
@@ -836,6 +842,23 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     const float idx = (float)g.idx, idy = (float)g.idy;
     const float* H = S + 2 * NV * NN;
     const unsigned vrow4 = (unsigned)(k * N) * pstride4 + e * 4u;
+    // L_eq, du and du^n of the row, issued before any store (out may alias du^n)
+    float Le[NV][N];
+    double U1[NV][N], Un[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            Le[v][b] = ld32(rleq, vrow4, (unsigned)(v * NN + b) * pstride4);
+            U1[v][b] = ld64(rdu, vrow, (unsigned)(v * NN + b) * pstride);
+        }
+    if (a0 != 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) Un[v][b] = ld64(rdun, vrow, (unsigned)(v * NN + b) * pstride);
+    }
+    float R[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         float glb = 0.0f, glt = 0.0f;
@@ -850,7 +873,6 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
             hw[r] = H[(0 * NV + v) * N + r];
             he[r] = H[(1 * NV + v) * N + r];
         }
-        float R[N];
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             float acc = 0.0f, glw = 0.0f, gle = 0.0f;
@@ -863,20 +885,19 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
             }
             acc -= idx * (pmk * glw + ppk * gle);
             acc -= idy * ((float)B.pm[b] * glb + (float)B.pp[b] * glt);
-            R[b] = acc;
+            R[v][b] = acc;
         }
-        if (active) {
+    }
+    if (active) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int b = 0; b < N; ++b) {
                 const unsigned po = (unsigned)(v * NN + b) * pstride;
-                const double L = (double)ld32(rleq, vrow4, (unsigned)(v * NN + b) * pstride4) + (double)R[b];
-                const double base = a1 * ld64(rdu, vrow, po) + a2 * L;
-                if (a0 != 0.0)
-                    st64(rout, vrow, po, a0 * ld64(rdun, vrow, po) + base);
-                else
-                    st64(rout, vrow, po, base);
+                const double L = (double)Le[v][b] + (double)R[v][b];
+                const double base = a1 * U1[v][b] + a2 * L;
+                st64(rout, vrow, po, a0 != 0.0 ? a0 * Un[v][b] + base : base);
             }
-        }
     }
 }
 
