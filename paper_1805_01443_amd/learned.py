@@ -69,10 +69,12 @@ def init_params(seed=0):
     return p
 
 
-def collect(seed, nx, steps, every, cap, torch, log=print):
+def collect(seed, nx, steps, every, cap, torch, s0=None, log=print):
     """Run the plain pipeline; returns (features int16 [N, 64], labels float [N],
-    per-capture positive counts)."""
-    cfg = ring_config(nx)
+    per-capture positive counts, steps run).  A run whose state turns
+    non-finite (the plain limiter does not preserve positivity) stops there and
+    keeps the samples captured before."""
+    cfg = ring_config(nx, s0=s0)
     prim = W.prim_for(cfg, "disc_ring", seed=seed)
     h, u = dg.dg_init(cfg, prim)
     E = cfg.n_elem
@@ -82,12 +84,18 @@ def collect(seed, nx, steps, every, cap, torch, log=print):
     g = torch.Generator(device="cuda")
     g.manual_seed(1000 + seed)
     xs, ys, npos = [], [], []
+    done = 0
     for k in range(steps):
         cap_now = (k + 1) % every == 0
         if cap_now:
             dg.dg_capture(h, feat=feat, labels=lab)
         dg.dg_rk_step(h, u, t_dev, 0.0, None)
         if cap_now:
+            try:
+                dg.dg_sync(h)
+            except dg.DGError as err:
+                log(f"[collect] seed {seed}: stopped at step {k + 1} ({err})")
+                break
             pos = torch.nonzero(lab).flatten()
             neg = torch.nonzero(lab == 0).flatten()
             npos.append(int(pos.numel()))
@@ -98,10 +106,15 @@ def collect(seed, nx, steps, every, cap, torch, log=print):
             idx = torch.cat([pos, neg])
             xs.append(feat[idx].clone())
             ys.append(torch.cat([torch.ones(pos.numel(), device="cuda"), torch.zeros(neg.numel(), device="cuda")]))
-    dg.dg_sync(h)
-    log(f"[collect] seed {seed}: t_end {t_dev.item():.4f}, positives per capture {npos[:3]}...{npos[-3:]}")
+        done = k + 1
+    try:
+        dg.dg_sync(h)
+    except dg.DGError:
+        pass
+    log(f"[collect] seed {seed}: {done} steps, t_end {t_dev.item():.4f}, positives per capture "
+        f"{npos[:3]}...{npos[-3:]} (total {sum(npos)})")
     h.close()
-    return torch.cat(xs), torch.cat(ys), npos
+    return torch.cat(xs), torch.cat(ys), npos, done
 
 
 def train(h, X, Y, epochs, batch, lr, seed, torch, log=print):
@@ -135,43 +148,53 @@ def rates(prob, y, theta):
     return miss, fa
 
 
-def evaluate_run(seed, nx, steps, every, params, theta, torch, log=print):
+def evaluate_run(seed, nx, steps, every, params, theta, torch, s0=None, log=print):
     """Plain and learned limiter on the same seeded workload: step times,
     torque series and final density difference, and the learned flags vs the
-    plain labels on the learned run's captured states."""
+    plain labels on the learned run's captured states.  Runs stop at the first
+    non-finite state; the comparison covers the steps both completed."""
     out = {}
     res = {}
     for name, lim in (("plain", dg.LIMITER_MODAL_DECAY), ("learned", dg.LIMITER_LEARNED)):
-        cfg = ring_config(nx, limiter=lim, theta=theta)
+        cfg = ring_config(nx, limiter=lim, theta=theta, s0=s0)
         prim = W.prim_for(cfg, "disc_ring", seed=seed)
         h, u = dg.dg_init(cfg, prim)
         if lim == dg.LIMITER_LEARNED:
             dg.dg_mlp_params(h, set_params=params)
         E = cfg.n_elem
         lab = torch.zeros(E, dtype=torch.uint8, device="cuda")
-        fl = torch.zeros(E, dtype=torch.uint8, device="cuda")
         mf = torch.zeros(E, dtype=torch.uint8, device="cuda")
         t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
         tq = torch.zeros(steps, dtype=torch.float64, device="cuda")
         tp = fp = fn = tn = 0
-        # timed run (no captures), then a second run with captures for the rates
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(steps):
-            dg.dg_rk_step(h, u, t_dev, 0.0, None)
-            dg.dg_torque(h, u, tq[k:k + 1], t_dev=t_dev)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        dg.dg_sync(h)
-        res[name] = {"u": u.clone(), "tq": tq.clone(), "elapsed": el}
+        # timed run in chunks (no captures; a finiteness check between chunks)
+        chunk = max(every, 1)
+        done, el = 0, 0.0
+        while done < steps:
+            n = min(chunk, steps - done)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(done, done + n):
+                dg.dg_rk_step(h, u, t_dev, 0.0, None)
+                dg.dg_torque(h, u, tq[k:k + 1], t_dev=t_dev)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            try:
+                dg.dg_sync(h)
+            except dg.DGError:
+                log(f"[eval] {name}: non-finite state after step {done + n}")
+                break
+            done += n
+        res[name] = {"u": u.clone(), "tq": tq.clone(), "elapsed": el, "steps": done}
         if lim == dg.LIMITER_LEARNED:
             h2, u2 = dg.dg_init(cfg, prim)
             dg.dg_mlp_params(h2, set_params=params)
             t2 = torch.zeros(1, dtype=torch.float64, device="cuda")
-            for k in range(steps):
+            ncap = 0
+            for k in range(done):
                 cap = (k + 1) % every == 0
                 if cap:
-                    dg.dg_capture(h2, flags=fl, labels=lab, mlp_flags=mf)
+                    dg.dg_capture(h2, labels=lab, mlp_flags=mf)
                 dg.dg_rk_step(h2, u2, t2, 0.0, None)
                 if cap:
                     y = lab.bool()
@@ -180,20 +203,24 @@ def evaluate_run(seed, nx, steps, every, params, theta, torch, log=print):
                     fn += int((y & ~m).sum())
                     fp += int((~y & m).sum())
                     tn += int((~y & ~m).sum())
-            dg.dg_sync(h2)
+                    ncap += 1
             h2.close()
-            out["captured_states"] = steps // every
+            out["captured_states"] = ncap
             out["miss_rate"] = fn / max(tp + fn, 1)
             out["false_alarm_rate"] = fp / max(fp + tn, 1)
             out["label_positives"] = tp + fn
+            out["mlp_flags"] = tp + fp
         h.close()
     a, b = res["plain"], res["learned"]
-    rho_p, rho_l = a["u"][0], b["u"][0]
-    out["density_rel_L2_diff"] = float(((rho_l - rho_p) ** 2).sum().sqrt() / (rho_p ** 2).sum().sqrt())
-    out["torque_series_rel_diff"] = float((b["tq"] - a["tq"]).abs().max() / a["tq"].abs().max())
-    out["ms_per_step_plain"] = a["elapsed"] * 1e3 / steps
-    out["ms_per_step_learned"] = b["elapsed"] * 1e3 / steps
-    out["speedup_learned_vs_plain"] = a["elapsed"] / b["elapsed"]
+    n = min(a["steps"], b["steps"])
+    out["steps_completed"] = {"plain": a["steps"], "learned": b["steps"]}
+    if a["steps"] == b["steps"]:
+        rho_p, rho_l = a["u"][0], b["u"][0]
+        out["density_rel_L2_diff"] = float(((rho_l - rho_p) ** 2).sum().sqrt() / (rho_p ** 2).sum().sqrt())
+    out["torque_series_rel_diff"] = float((b["tq"][:n] - a["tq"][:n]).abs().max() / a["tq"][:n].abs().max())
+    out["ms_per_step_plain"] = a["elapsed"] * 1e3 / max(a["steps"], 1)
+    out["ms_per_step_learned"] = b["elapsed"] * 1e3 / max(b["steps"], 1)
+    out["speedup_learned_vs_plain"] = out["ms_per_step_plain"] / out["ms_per_step_learned"]
     return out
 
 
@@ -211,6 +238,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default="learned_result.json")
     ap.add_argument("--params-out", default=None)
+    ap.add_argument("--s0", type=float, default=None, help="modal-decay threshold (default -4 log10(order))")
     a = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
@@ -221,12 +249,12 @@ def main(argv=None):
     t_start = time.time()
     Xs, Ys = [], []
     for s in a.train_seeds:
-        X, Y, _ = collect(s, a.nx, a.steps, a.every, a.cap, torch, log)
+        X, Y, _, _ = collect(s, a.nx, a.steps, a.every, a.cap, torch, a.s0, log)
         Xs.append(X)
         Ys.append(Y)
     X = torch.cat(Xs)
     Y = torch.cat(Ys)
-    Xv, Yv, _ = collect(a.val_seed, a.nx, a.steps, a.every, a.cap, torch, log)
+    Xv, Yv, _, _ = collect(a.val_seed, a.nx, a.steps, a.every, a.cap, torch, a.s0, log)
     log(f"[data] train {X.shape[0]} samples ({int(Y.sum().item())} positive), val {Xv.shape[0]}")
     # a handle is needed to own the network; any configuration with the limiter works
     cfg = ring_config(64)
@@ -249,8 +277,9 @@ def main(argv=None):
     vmiss, vfa = rates(pv, yv, theta)
     log(f"[val] theta {theta:.3f}: miss {vmiss:.4f}, false alarm (balanced sample) {vfa:.4f}")
     h.close()
-    ev = evaluate_run(a.test_seed, a.nx, a.steps, a.every, params, theta, torch, log)
-    res = {"nx": a.nx, "order": 4, "steps": a.steps, "every": a.every, "train_seeds": a.train_seeds,
+    s0 = default_s0(4) if a.s0 is None else a.s0
+    ev = evaluate_run(a.test_seed, a.nx, a.steps, a.every, params, theta, torch, s0, log)
+    res = {"nx": a.nx, "order": 4, "steps": a.steps, "s0": s0, "every": a.every, "train_seeds": a.train_seeds,
            "val_seed": a.val_seed, "test_seed": a.test_seed, "train_samples": int(X.shape[0]),
            "train_positives": int(Y.sum().item()), "pos_weight": pw, "epochs": a.epochs, "batch": a.batch,
            "lr": a.lr, "loss_history": hist, "train_seconds": t_tr, "theta": theta,
@@ -260,7 +289,7 @@ def main(argv=None):
     with open(a.out, "w") as f:
         json.dump(res, f, indent=1)
     if a.params_out:
-        save_params(a.params_out, params, theta, default_s0(4),
+        save_params(a.params_out, params, theta, s0,
                     {k: res[k] for k in ("nx", "steps", "every", "train_seeds", "val_seed", "test_seed",
                                          "train_samples", "train_positives", "epochs", "val_miss")})
 
