@@ -202,7 +202,7 @@ def run_limited(a):
         dofs = cfg.n_elem * cfg.order ** 2
         out[name] = {"value": dofs * 3 * a.ring_steps / el, "unit": "DOF-stage/s",
                      "ms_per_step": el * 1e3 / a.ring_steps, "sensor_flagged_at_end": int(fl.sum().item())}
-        rho[name] = u[0].clone()
+        rho[name] = dg.to_planes(cfg, u)[0].clone()
         h.close()
     out["learned_speedup_vs_modal"] = out["modal"]["ms_per_step"] / out["learned"]["ms_per_step"]
     out["density_rel_L2_diff"] = float(((rho["learned"] - rho["modal"]) ** 2).sum().sqrt()
@@ -301,8 +301,8 @@ def main():
         cm = cfg.replace(precision=dg.PRECISION_MIXED, sigma0=sigma0)
         rm = run_disc(cm, prim, a.steps, a.warmup, profile=True)
         g64, gm = r64["torques"], rm["torques"]
-        rho64 = r64["full"][0]
-        rhom = rm["full"][0]
+        rho64 = dg.to_planes(cfg, r64["full"])[0]
+        rhom = dg.to_planes(cm, rm["full"])[0]
         dens_l2 = float(((rhom - rho64) ** 2).sum().sqrt() / (rho64 ** 2).sum().sqrt())
         tq_err = float((gm - g64).abs().max() / g64.abs().max())
         out["forms"] = {

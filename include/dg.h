@@ -9,10 +9,15 @@
  * (PyTorch) types.
  *
  * Data layout (caller-owned device arrays, FP64):
- *   state  u[(v*n*n + a*n + b)*E + e]   v: variable (rho, rho vx, rho vy[, E]),
- *          (a, b): Legendre degrees in x and y, e = j*nx + i the element.
- *          One nx*ny plane per (variable, mode), i fastest: the paper's
- *          "one matrix per mode" layout (Sec. 3.1), coalesced by element.
+ *   state  element-tiled: the elements of row j are grouped in tiles of
+ *          W = 64 / n consecutive elements (n = order): tile t = j * TX + i / W
+ *          with TX = ceil(nx / W), slot s = i % W; inside a tile the entries
+ *          run [v][b][a][s], so mode (a, b) of variable v (rho, rho vx,
+ *          rho vy[, E]) of element (i, j) is
+ *              u[((t * nvar + v) * n + b) * n * W + a * W + s].
+ *          Slots past the end of a row are padding.  The array holds
+ *          dg_state_size(cfg) doubles.  (The paper keeps one matrix per mode,
+ *          Sec. 3.1; tiles keep what one wavefront reads contiguous.)
  *   basis  phi_ab(xi, eta) = sqrt((2a+1)(2b+1)) P_a(xi) P_b(eta), orthonormal
  *          under (1/|K|) int_K, so mode 00 is the element mean (Sec. 2.2 and
  *          the zeroth-mode statement of Sec. 3.1).
@@ -23,8 +28,7 @@
  * (or of dg_init / dg_get_nodes when the handle is NULL).  Device-side
  * problems (non-finite or non-positive density means) raise a flag that the
  * next dg_sync() reports as DG_ENONFINITE.  A handle belongs to one stream and
- * is not thread-safe; the library keeps no global mutable state apart from
- * per-device scratch set up explicitly by the calls that use it.
+ * is not thread-safe; the library keeps no global mutable state.
  */
 #ifndef DG_MI355X_H
 #define DG_MI355X_H
@@ -77,6 +81,11 @@ typedef struct dg_config {
 } dg_config;
 
 typedef struct dg_handle dg_handle;
+
+/* Number of doubles in one state array of this configuration (padding
+ * included), or a negative DG_E* code for an invalid configuration.  Needs no
+ * device. */
+long long dg_state_size(const dg_config *cfg);
 
 /* Volume Gauss node coordinates, host arrays x_host[e*n*n + node] and y_host
  * likewise (E*n*n doubles each, caller-owned).  Needs no device. */

@@ -81,6 +81,12 @@ int hip_fail(dg_handle* h, hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail((h), e_, (what)); \
     } while (0)
 
+// elements of the tiled layout, padding included
+double state_slots(const dg_config* c) {
+    const int ew = dgk::tile_width(c->order);
+    return (double)((c->nx + ew - 1) / ew) * ew * (double)c->ny;
+}
+
 int validate(const dg_config* c, std::string* why) {
     if (!c) return (*why = "cfg is NULL", DG_EINVAL);
     if (c->order < 2 || c->order > dgk::kMaxN) return (*why = "order must be in 2..5", DG_EUNSUPPORTED);
@@ -117,7 +123,7 @@ int validate(const dg_config* c, std::string* why) {
         return (*why = "the learned indicator takes 16 modes x 4 variables (order 4, nvar 4)", DG_EUNSUPPORTED);
     if (c->limiter == DG_LIMITER_LEARNED && !(c->mlp_theta > 0 && c->mlp_theta < 1))
         return (*why = "mlp_theta must be in (0, 1)", DG_EINVAL);
-    if ((double)c->nvar * c->order * c->order * (double)c->nx * c->ny * 8.0 >= 4294967296.0)
+    if ((double)c->nvar * c->order * c->order * state_slots(c) * 8.0 >= 4294967296.0)
         return (*why = "state arrays are limited to 4 GiB (32-bit buffer offsets)", DG_EUNSUPPORTED);
     return DG_OK;
 }
@@ -127,6 +133,9 @@ void make_geo(const dg_config* c, Geo* g) {
     g->nx = c->nx;
     g->ny = c->ny;
     g->E = (long long)c->nx * c->ny;
+    g->ew = dgk::tile_width(c->order);
+    g->tiles_x = (c->nx + g->ew - 1) / g->ew;
+    g->slots = (long long)g->tiles_x * c->ny * g->ew;
     g->x0 = c->x0;
     g->y0 = c->y0;
     g->dx = (c->x1 - c->x0) / c->nx;
@@ -337,6 +346,16 @@ int dg_get_nodes(const dg_config* cfg, double* x_host, double* y_host) {
     return DG_OK;
 }
 
+long long dg_state_size(const dg_config* cfg) {
+    std::string why;
+    const int rc = validate(cfg, &why);
+    if (rc != DG_OK) {
+        g_err = why;
+        return rc;
+    }
+    return (long long)cfg->nvar * cfg->order * cfg->order * (long long)state_slots(cfg);
+}
+
 int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev, void* hip_stream, dg_handle** out) {
     if (!out) return fail(nullptr, DG_EINVAL, "out is NULL");
     *out = nullptr;
@@ -363,7 +382,8 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     };
     if (hipGetDevice(&h->device) != hipSuccess) return bail(hip_fail(h, hipGetLastError(), "hipGetDevice"));
 
-    const size_t state_bytes = sizeof(double) * (size_t)h->nvar * h->n * h->n * (size_t)h->E;
+    const size_t state_bytes = sizeof(double) * (size_t)h->nvar * h->n * h->n * (size_t)h->g.slots;
+    const size_t prim_bytes = sizeof(double) * (size_t)h->nvar * h->n * h->n * (size_t)h->E;  // [var][e][node]
     double* prim_dev = nullptr;
     hipError_t e;
 #define DG_ALLOC(ptr, bytes)                                                   \
@@ -382,7 +402,7 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     DG_ALLOC(h->bad_part, sizeof(unsigned int) * (size_t)h->dt_blocks);
     h->tq_blocks = dgk::torque_blocks(h->g);
     DG_ALLOC(h->tq_part, sizeof(double) * (size_t)h->tq_blocks);
-    DG_ALLOC(prim_dev, state_bytes);
+    DG_ALLOC(prim_dev, prim_bytes);
     DG_ALLOC(h->scale_dev, sizeof(double) * 4);
     DG_ALLOC(h->flags, (size_t)h->E);
     DG_ALLOC(h->mlp, sizeof(float) * 3 * (size_t)dgk::mlp_nparam());
@@ -394,20 +414,26 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
         DG_ALLOC(h->leq, state_bytes / 2);
     }
 
-    // damped elements: any volume node with a non-zero ramp
+    // damped tiles: tiles with any volume node of non-zero ramp (the kernel
+    // leaves the undamped elements of such a tile unchanged: zero increments)
     if (cfg->damping) {
         std::vector<double> x, y;
         host_nodes(cfg, &x, &y);
         std::vector<int> list;
         const int nn = h->n * h->n;
-        for (long long el = 0; el < h->E; ++el) {
-            bool any = false;  // the ramp is positive exactly for r < rd_in or r > rd_out
-            for (int k = 0; k < nn && !any; ++k) {
-                const double r = std::sqrt(x[el * nn + k] * x[el * nn + k] + y[el * nn + k] * y[el * nn + k]);
-                any = r < cfg->rd_in || r > cfg->rd_out;
+        const int ew = h->g.ew;
+        for (int j = 0; j < cfg->ny; ++j)
+            for (int t = 0; t < h->g.tiles_x; ++t) {
+                bool any = false;  // the ramp is positive exactly for r < rd_in or r > rd_out
+                for (int i = t * ew; i < (t + 1) * ew && i < cfg->nx && !any; ++i) {
+                    const long long el = (long long)j * cfg->nx + i;
+                    for (int k = 0; k < nn && !any; ++k) {
+                        const double r = std::sqrt(x[el * nn + k] * x[el * nn + k] + y[el * nn + k] * y[el * nn + k]);
+                        any = r < cfg->rd_in || r > cfg->rd_out;
+                    }
+                }
+                if (any) list.push_back(j * h->g.tiles_x + t);
             }
-            if (any) list.push_back((int)el);
-        }
         h->ndamp = (int)list.size();
         if (h->ndamp) {
             DG_ALLOC(h->damp_list, sizeof(int) * list.size());
@@ -423,7 +449,15 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
 
     StepBlock sb0{};
     e = hipMemcpyAsync(h->sb, &sb0, sizeof sb0, hipMemcpyHostToDevice, h->s);
-    if (e == hipSuccess) e = hipMemcpyAsync(prim_dev, prim_nodes_host, state_bytes, hipMemcpyHostToDevice, h->s);
+    // padding slots of the tiled layout stay zero in every state array the
+    // library writes (the stage kernels skip them, combinations keep zeros)
+    if (e == hipSuccess) e = hipMemsetAsync(u0_dev, 0, state_bytes, h->s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws1, 0, state_bytes, h->s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws2, 0, state_bytes, h->s);
+    if (e == hipSuccess && h->kbuf) e = hipMemsetAsync(h->kbuf, 0, state_bytes * (size_t)h->tab.s, h->s);
+    if (e == hipSuccess && h->dev) e = hipMemsetAsync(h->eq, 0, state_bytes, h->s);
+    if (e == hipSuccess && h->dev) e = hipMemsetAsync(h->leq, 0, state_bytes / 2, h->s);
+    if (e == hipSuccess) e = hipMemcpyAsync(prim_dev, prim_nodes_host, prim_bytes, hipMemcpyHostToDevice, h->s);
     if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, u0_dev, h->s);
     if (e == hipSuccess) e = hipMemcpyAsync(h->u0, u0_dev, state_bytes, hipMemcpyDeviceToDevice, h->s);
     if (e == hipSuccess) e = hipStreamSynchronize(h->s);
@@ -438,10 +472,10 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
         // u0_dev and the fixed exterior state become deviations u0 - u_eq.
         std::vector<double> peq;
         equilibrium_prim(cfg, &peq);
-        const long long N = (long long)h->nvar * h->n * h->n * h->E;
+        const long long N = (long long)h->nvar * h->n * h->n * h->g.slots;
         Geo g0 = h->g;
         g0.q = 0.0;
-        e = hipMemcpyAsync(prim_dev, peq.data(), state_bytes, hipMemcpyHostToDevice, h->s);
+        e = hipMemcpyAsync(prim_dev, peq.data(), sizeof(double) * peq.size(), hipMemcpyHostToDevice, h->s);
         if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, h->eq, h->s);
         if (e == hipSuccess) e = dgk::launch_set_coeffs(h->sc_rhs, g0, 0.0, 0.0, 0.0, 1.0, h->s);
         if (e == hipSuccess) e = dgk::launch_stage(h->n, g0, h->eq, nullptr, h->eq, h->ws1, h->sc_rhs, h->s);
@@ -457,10 +491,12 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     (void)hipFree(prim_dev);
     // feature scales: RMS of the initial element means of each variable
     {
+        // the means of u0, gathered into [v][e] in the stage workspace
         std::vector<double> means((size_t)h->E);
-        const size_t nn = (size_t)h->n * h->n;
+        e = dgk::launch_means(h->n, h->nvar, h->g, h->u0, h->ws1, h->s);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->s);
         for (int v = 0; v < h->nvar && e == hipSuccess; ++v) {
-            e = hipMemcpy(means.data(), h->u0 + v * nn * h->E, sizeof(double) * h->E, hipMemcpyDeviceToHost);
+            e = hipMemcpy(means.data(), h->ws1 + (size_t)v * h->E, sizeof(double) * h->E, hipMemcpyDeviceToHost);
             double ss = 0.0;
             for (double m : means) ss += m * m;
             h->scale_host[v] = std::sqrt(ss / (double)h->E);
@@ -493,7 +529,7 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
         // Butcher form: k_i = L(y_i), y_1 = u^n, y_i = u^n + dt sum_{j<i} a_ij k_j,
         // u^{n+1} = u^n + dt sum_j b_j k_j (no limiter with these tables)
         const int S = h->tab.s;
-        const long long N = (long long)h->nvar * h->n * h->n * h->E;
+        const long long N = (long long)h->nvar * h->n * h->n * h->g.slots;
         const double* k[dgk::kMaxStages];
         for (int i = 0; i < S; ++i) k[i] = h->kbuf + (size_t)i * (size_t)N;
         DG_HIP(h, dgk::launch_step_begin_table(h->g, sb, h->tab, h->dt_part, h->bad_part, h->dt_blocks, t_dev,
@@ -641,7 +677,7 @@ int dg_mlp_train_step(dg_handle* h, const unsigned short* feat_dev, const float*
 int dg_full_state(dg_handle* h, const double* dev_dev, double* full_dev) {
     if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
     if (!dev_dev || !full_dev) return fail(h, DG_EINVAL, "NULL state");
-    const long long ns = (long long)h->nvar * h->n * h->n * h->E;
+    const long long ns = (long long)h->nvar * h->n * h->n * h->g.slots;
     if (h->dev) {
         DG_HIP(h, dgk::launch_add_state(h->eq, dev_dev, full_dev, 1.0, ns, h->s), "full state");
     } else if (dev_dev != full_dev) {

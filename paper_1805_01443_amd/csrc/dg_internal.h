@@ -9,10 +9,22 @@ namespace dgk {
 
 constexpr int kMaxN = 5;  // orders 2..5 (P1..P4)
 
+// State layout (every state array of a handle): elements are grouped in
+// tiles of EW = 64 / n consecutive elements of one row (n = order), tile
+// t = j * tiles_x + i / EW, slot s = i % EW; inside a tile the entries are
+// ordered [v][b][a][s] for mode (a, b) of variable v.  So the n lanes of one
+// element that hold its mode rows a = 0..n-1 read, for fixed (v, b), one
+// contiguous run of n * EW doubles with the other elements of the tile.
+// Slots past the end of a row are padding (never read as neighbours).
+constexpr int tile_width(int n) { return 64 / n; }
+
 // Mesh, closure and gravity parameters.
 struct Geo {
     int nx, ny;
     long long E;
+    int ew;            // elements per tile
+    int tiles_x;       // tiles per row
+    long long slots;   // tiles_x * ny * ew: elements of the padded layout
     double x0, y0, dx, dy;
     double rdx2, rdy2; // 2/dx, 2/dy
     double idx, idy;   // 1/dx, 1/dy
@@ -31,6 +43,19 @@ struct Geo {
     double cfl_fac;             // C / (2 N_p + 1)
     double sigma0;              // deviation form: equilibrium Sigma0
 };
+
+// Index (in entries) of mode (0, 0) of variable 0 of element (i, j) in the
+// tiled layout, and the offset of mode (a, b) of variable v from it.
+template <int N, int NV>
+__device__ __forceinline__ unsigned tiled_base(const Geo& g, int i, int j) {
+    constexpr int EW = tile_width(N);
+    const int ti = i / EW;
+    return (unsigned)(j * g.tiles_x + ti) * (unsigned)(NV * N * N * EW) + (unsigned)(i - ti * EW);
+}
+template <int N>
+__device__ __forceinline__ constexpr unsigned mode_off(int v, int a, int b) {
+    return (unsigned)(((v * N + b) * N + a) * tile_width(N));
+}
 
 // Per-stage coefficients: out = a0 * u^n + a1 * u + a2 * L(u, t)
 struct StageCoeffs {
@@ -98,6 +123,8 @@ hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
 int torque_blocks(const Geo& g);
 
 // troubled cells and the learned indicator
+// means of every variable into out[v * E + e] (contiguous), from a state array
+hipError_t launch_means(int n, int nvar, const Geo& g, const double* u, double* out, hipStream_t s);
 hipError_t launch_troubled(int n, int nvar, const Geo& g, double* u, const double* u0, double s0, int mode, int apply,
                            const unsigned char* flag_in, unsigned char* flag_out, unsigned char* changed_out,
                            float* sensor_out, hipStream_t s);

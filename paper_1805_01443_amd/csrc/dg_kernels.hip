@@ -220,9 +220,11 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 
     const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
     const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), rout = make_rsrc(out), run = make_rsrc(un);
-    const unsigned pstride = (unsigned)g.E * 8u;
-    const unsigned e = (unsigned)j * (unsigned)g.nx + (unsigned)i;
-    const unsigned vrow = (unsigned)(k * N) * pstride + e * 8u;  // mode (k, 0) of this element
+    // tiled layout: row k of an element is mode (k, b) at + (v * N + b) * RS,
+    // column k is mode (a, k) at + (v * N * N + a) * CS (byte strides)
+    constexpr unsigned RS = N * EW * 8, CS = EW * 8;
+    const unsigned eb = tiled_base<N, NV>(g, i, j);
+    const unsigned vrow = (eb + k * EW) * 8u;  // mode (k, 0) of this element
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
 
     // ---- phase 1: k = mode row.  Every global load of the phase is issued
@@ -235,16 +237,16 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     jb += ob ? g.ny : 0;
     jt -= ot ? g.ny : 0;
     const bool fxd = g.bc == 1, fl = fxd && ol, fr = fxd && orr, fb = fxd && ob, ft = fxd && ot;
-    const unsigned vcol = (unsigned)k * pstride + e * 8u;  // mode (0, k)
-    const unsigned kr = (unsigned)(k * N) * pstride, kc = (unsigned)k * pstride;
-    const unsigned vb = kr + ((unsigned)jb * g.nx + i) * 8u, vt = kr + ((unsigned)jt * g.nx + i) * 8u;
-    const unsigned vl = kc + ((unsigned)j * g.nx + il) * 8u, vr = kc + ((unsigned)j * g.nx + ir) * 8u;
+    const unsigned vcol = (eb + k * N * EW) * 8u;  // mode (0, k)
+    const unsigned vb = (tiled_base<N, NV>(g, i, jb) + k * EW) * 8u, vt = (tiled_base<N, NV>(g, i, jt) + k * EW) * 8u;
+    const unsigned vl = (tiled_base<N, NV>(g, il, j) + k * N * EW) * 8u;
+    const unsigned vr = (tiled_base<N, NV>(g, ir, j) + k * N * EW) * 8u;
     double Ua[NV][N], Xb[NV][N], Xt[NV][N], Xl[NV][N], Xr[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int m = 0; m < N; ++m) {
-            const unsigned srow = (unsigned)(v * NN + m) * pstride, scol = (unsigned)(v * NN + m * N) * pstride;
+            const unsigned srow = (unsigned)(v * N + m) * RS, scol = (unsigned)(v * NN + m) * CS;
             Ua[v][m] = ld64(ru, vrow, srow);
             Xb[v][m] = ld64(ru, vb, srow);
             Xt[v][m] = ld64(ru, vt, srow);
@@ -256,7 +258,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const double o = ld64(ru0, vrow, (unsigned)(v * NN + m) * pstride);
+                const double o = ld64(ru0, vrow, (unsigned)(v * N + m) * RS);
                 Xb[v][m] = fb ? o : Xb[v][m];
                 Xt[v][m] = ft ? o : Xt[v][m];
             }
@@ -266,7 +268,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const double o = ld64(ru0, vcol, (unsigned)(v * NN + m * N) * pstride);
+                const double o = ld64(ru0, vcol, (unsigned)(v * NN + m) * CS);
                 Xl[v][m] = fl ? o : Xl[v][m];
                 Xr[v][m] = fr ? o : Xr[v][m];
             }
@@ -469,12 +471,12 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int b = 0; b < N; ++b) U1[v][b] = ld64(ru, vrow, (unsigned)(v * NN + b) * pstride);
+        for (int b = 0; b < N; ++b) U1[v][b] = ld64(ru, vrow, (unsigned)(v * N + b) * RS);
     if (a0 != 0.0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int b = 0; b < N; ++b) Un[v][b] = ld64(run, vrow, (unsigned)(v * NN + b) * pstride);
+            for (int b = 0; b < N; ++b) Un[v][b] = ld64(run, vrow, (unsigned)(v * N + b) * RS);
     }
     double R[NV][N];
 #pragma unroll
@@ -511,13 +513,13 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             for (int v = 0; v < NV; ++v)
 #pragma unroll
                 for (int b = 0; b < N; ++b)
-                    st64(rout, vrow, (unsigned)(v * NN + b) * pstride, a0 * Un[v][b] + (a1 * U1[v][b] + a2 * R[v][b]));
+                    st64(rout, vrow, (unsigned)(v * N + b) * RS, a0 * Un[v][b] + (a1 * U1[v][b] + a2 * R[v][b]));
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
                 for (int b = 0; b < N; ++b)
-                    st64(rout, vrow, (unsigned)(v * NN + b) * pstride, a1 * U1[v][b] + a2 * R[v][b]);
+                    st64(rout, vrow, (unsigned)(v * N + b) * RS, a1 * U1[v][b] + a2 * R[v][b]);
         }
     }
 }
@@ -571,13 +573,17 @@ __device__ __forceinline__ float vnorm(const EqPoint& q, const float* d, float i
     return SGN * v;
 }
 
-// Exterior collapse for the deviation form (FP64 deviation loaded, FP32
-// arithmetic), otherwise as ext_collapse.
+// Collapse of the exterior deviation across one edge for lane k (FP64 loaded,
+// FP32 arithmetic): the neighbour's row k (ROW: modes (k, b), summed over b)
+// or column k (modes (a, k), summed over a) with the basis values of its far
+// side NB_SIDE, or, at a fixed box edge, the element's own initial row/column
+// with the near side.  vnb / vown: byte offsets of mode (k, 0) resp. (0, k).
 template <int N, bool ROW, int NB_SIDE>
-__device__ __forceinline__ void ext_collapse_f(rsrc_t ru, rsrc_t ru0, unsigned pstride, unsigned vnb, unsigned vown,
-                                               bool fixed, bool wave_fixed, float (&T)[3]) {
+__device__ __forceinline__ void ext_collapse_f(rsrc_t ru, rsrc_t ru0, unsigned vnb, unsigned vown, bool fixed,
+                                               bool wave_fixed, float (&T)[3]) {
     constexpr BasisTab B = make_basis(N);
     constexpr int NN = N * N;
+    constexpr unsigned RS = N * tile_width(N) * 8, CS = tile_width(N) * 8;
 #pragma unroll
     for (int v = 0; v < 3; ++v) T[v] = 0.0f;
     if (!wave_fixed) {
@@ -585,7 +591,7 @@ __device__ __forceinline__ void ext_collapse_f(rsrc_t ru, rsrc_t ru0, unsigned p
         for (int v = 0; v < 3; ++v)
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const unsigned so = (unsigned)(v * NN + (ROW ? m : m * N)) * pstride;
+                const unsigned so = ROW ? (unsigned)(v * N + m) * RS : (unsigned)(v * NN + m) * CS;
                 T[v] += (float)(NB_SIDE > 0 ? B.pp[m] : B.pm[m]) * (float)ld64(ru, vnb, so);
             }
     } else {
@@ -593,7 +599,7 @@ __device__ __forceinline__ void ext_collapse_f(rsrc_t ru, rsrc_t ru0, unsigned p
         for (int v = 0; v < 3; ++v)
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const unsigned so = (unsigned)(v * NN + (ROW ? m : m * N)) * pstride;
+                const unsigned so = ROW ? (unsigned)(v * N + m) * RS : (unsigned)(v * NN + m) * CS;
                 const float un = (float)ld64(ru, vnb, so);
                 const float u0v = (float)ld64(ru0, vown, so);
                 T[v] += fixed ? (float)(NB_SIDE > 0 ? B.pm[m] : B.pp[m]) * u0v
@@ -646,9 +652,9 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
     const rsrc_t rdu = make_rsrc(du), rdu0 = make_rsrc(du0), rout = make_rsrc(out), rdun = make_rsrc(dun),
                  rleq = make_rsrc(leq);
-    const unsigned pstride = (unsigned)g.E * 8u, pstride4 = (unsigned)g.E * 4u;
-    const unsigned e = (unsigned)j * (unsigned)g.nx + (unsigned)i;
-    const unsigned vrow = (unsigned)(k * N) * pstride + e * 8u;
+    constexpr unsigned RS = N * EW * 8, RS4 = N * EW * 4;  // byte stride of (v * N + b) in a row
+    const unsigned eb = tiled_base<N, NV>(g, i, j);
+    const unsigned vrow = (eb + k * EW) * 8u;  // mode (k, 0) of this element
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
 
     // ---- phase 1: k = mode row
@@ -656,7 +662,7 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     for (int v = 0; v < NV; ++v) {
         float Ua[N];
 #pragma unroll
-        for (int b = 0; b < N; ++b) Ua[b] = (float)ld64(rdu, vrow, (unsigned)(v * NN + b) * pstride);
+        for (int b = 0; b < N; ++b) Ua[b] = (float)ld64(rdu, vrow, (unsigned)(v * N + b) * RS);
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             float c = 0.0f;
@@ -682,19 +688,18 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
         jt -= ot ? g.ny : 0;
         const bool fx = g.bc == 1, fl = fx && ol, fr = fx && orr, fb = fx && ob, ft = fx && ot;
         const bool wfx = __any(fl || fr), wfy = __any(fb || ft);
-        const unsigned vcol = (unsigned)k * pstride + e * 8u;
-        const unsigned kr = (unsigned)(k * N) * pstride, kc = (unsigned)k * pstride;
+        const unsigned vcol = (eb + k * N * EW) * 8u;
         float T[NV];
-        ext_collapse_f<N, true, +1>(rdu, rdu0, pstride, kr + ((unsigned)jb * g.nx + i) * 8u, vrow, fb, wfy, T);
+        ext_collapse_f<N, true, +1>(rdu, rdu0, (tiled_base<N, NV>(g, i, jb) + k * EW) * 8u, vrow, fb, wfy, T);
 #pragma unroll
         for (int v = 0; v < NV; ++v) S[NV * NN + (2 * NV + v) * N + k] = T[v];
-        ext_collapse_f<N, true, -1>(rdu, rdu0, pstride, kr + ((unsigned)jt * g.nx + i) * 8u, vrow, ft, wfy, T);
+        ext_collapse_f<N, true, -1>(rdu, rdu0, (tiled_base<N, NV>(g, i, jt) + k * EW) * 8u, vrow, ft, wfy, T);
 #pragma unroll
         for (int v = 0; v < NV; ++v) S[NV * NN + (3 * NV + v) * N + k] = T[v];
-        ext_collapse_f<N, false, +1>(rdu, rdu0, pstride, kc + ((unsigned)j * g.nx + il) * 8u, vcol, fl, wfx, T);
+        ext_collapse_f<N, false, +1>(rdu, rdu0, (tiled_base<N, NV>(g, il, j) + k * N * EW) * 8u, vcol, fl, wfx, T);
 #pragma unroll
         for (int v = 0; v < NV; ++v) S[NV * NN + (4 * NV + v) * N + k] = T[v];
-        ext_collapse_f<N, false, -1>(rdu, rdu0, pstride, kc + ((unsigned)j * g.nx + ir) * 8u, vcol, fr, wfx, T);
+        ext_collapse_f<N, false, -1>(rdu, rdu0, (tiled_base<N, NV>(g, ir, j) + k * N * EW) * 8u, vcol, fr, wfx, T);
 #pragma unroll
         for (int v = 0; v < NV; ++v) S[NV * NN + (5 * NV + v) * N + k] = T[v];
     }
@@ -841,7 +846,7 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     const float pmk = (float)pick<N>(B.pm, k), ppk = (float)pick<N>(B.pp, k);
     const float idx = (float)g.idx, idy = (float)g.idy;
     const float* H = S + 2 * NV * NN;
-    const unsigned vrow4 = (unsigned)(k * N) * pstride4 + e * 4u;
+    const unsigned vrow4 = (eb + k * EW) * 4u;
     // L_eq, du and du^n of the row, issued before any store (out may alias du^n)
     float Le[NV][N];
     double U1[NV][N], Un[NV][N];
@@ -849,14 +854,14 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            Le[v][b] = ld32(rleq, vrow4, (unsigned)(v * NN + b) * pstride4);
-            U1[v][b] = ld64(rdu, vrow, (unsigned)(v * NN + b) * pstride);
+            Le[v][b] = ld32(rleq, vrow4, (unsigned)(v * N + b) * RS4);
+            U1[v][b] = ld64(rdu, vrow, (unsigned)(v * N + b) * RS);
         }
     if (a0 != 0.0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int b = 0; b < N; ++b) Un[v][b] = ld64(rdun, vrow, (unsigned)(v * NN + b) * pstride);
+            for (int b = 0; b < N; ++b) Un[v][b] = ld64(rdun, vrow, (unsigned)(v * N + b) * RS);
     }
     float R[NV][N];
 #pragma unroll
@@ -893,7 +898,7 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int b = 0; b < N; ++b) {
-                const unsigned po = (unsigned)(v * NN + b) * pstride;
+                const unsigned po = (unsigned)(v * N + b) * RS;
                 const double L = (double)Le[v][b] + (double)R[v][b];
                 const double base = a1 * U1[v][b] + a2 * L;
                 st64(rout, vrow, po, a0 != 0.0 ? a0 * Un[v][b] + base : base);
@@ -922,6 +927,7 @@ __global__ void __launch_bounds__(64) k_project(const Geo g, const double* __res
     const long long e = (long long)blockIdx.x * 64 + threadIdx.x;
     if (e >= g.E) return;
     const long long E = g.E;
+    const unsigned base = tiled_base<N, NV>(g, (int)(e % g.nx), (int)(e / g.nx));
     double C[NV][NN];
 #pragma unroll
     for (int k = 0; k < NN; ++k) {
@@ -948,8 +954,18 @@ __global__ void __launch_bounds__(64) k_project(const Geo g, const double* __res
 #pragma unroll
                     for (int r = 0; r < N; ++r)
                         s += C[v][q * N + r] * (T.wh[q] * T.wh[r] * T.phi[a][q] * T.phi[b][r]);
-                u[(long long)(v * NN + a * N + b) * E + e] = s;
+                u[base + mode_off<N>(v, a, b)] = s;
             }
+}
+
+// means of every variable of element e into out[v * E + e]
+template <int N, int NV>
+__global__ void __launch_bounds__(256) k_means(const Geo g, const double* __restrict__ u, double* __restrict__ out) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.E) return;
+    const unsigned base = tiled_base<N, NV>(g, (int)(e % g.nx), (int)(e / g.nx));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v * g.E + e] = u[base + mode_off<N>(v, 0, 0)];
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -1084,18 +1100,23 @@ __global__ void __launch_bounds__(256) k_dt(const Geo g, int nn, const double* _
     double dte = INFINITY;
     bool bad = false;
     if (e < g.E) {
-        const long long E = g.E;
-        double U[4];
-        U[0] = u[e];
-        U[1] = u[(long long)nn * E + e];
-        U[2] = u[(long long)2 * nn * E + e];
-        U[3] = CL == CL_ADI ? u[(long long)3 * nn * E + e] : 0.0;
-        if (eq) {  // deviation form: means of u_eq + du
-            U[0] += eq[e];
-            U[1] += eq[(long long)nn * E + e];
-            U[2] += eq[(long long)2 * nn * E + e];
-        }
         const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        // tiled layout with a run-time tile width: mean of variable v at
+        // base + v * nn * ew
+        constexpr int NV = CL == CL_ADI ? 4 : 3;
+        const int ti = i / g.ew;
+        const unsigned vs = (unsigned)(nn * g.ew);
+        const unsigned base = (unsigned)(j * g.tiles_x + ti) * (unsigned)NV * vs + (unsigned)(i - ti * g.ew);
+        double U[4];
+        U[0] = u[base];
+        U[1] = u[base + vs];
+        U[2] = u[base + 2 * vs];
+        U[3] = CL == CL_ADI ? u[base + 3 * vs] : 0.0;
+        if (eq) {  // deviation form: means of u_eq + du
+            U[0] += eq[base];
+            U[1] += eq[base + vs];
+            U[2] += eq[base + 2 * vs];
+        }
         const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
         double p, c;
         pressure<CL>(g, U, 1.0 / U[0], xc, yc, p, c);
@@ -1162,7 +1183,8 @@ __device__ __forceinline__ double ramp(const Geo& g, double r, double& td) {
 // Damping with N lanes per element (same split as k_stage_c): lane k first
 // holds mode row k of u and of u0 and contracts them in y, then Gauss row k
 // (node values, nodal increments, x projection), then mode row k again
-// (y projection and the update).  EW = 64 / N listed elements per wave.
+// (y projection and the update).  One listed tile (EW = 64 / N elements) per
+// wave; elements of the tile outside the damping zones get zero increments.
 template <int N, int CL>
 __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const double* __restrict__ u0,
                                                const double* __restrict__ eq, const int* __restrict__ list, int nlist,
@@ -1173,18 +1195,19 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
     constexpr int EW = 64 / N;
     constexpr int SLOT = 2 * NV * NN;
     __shared__ double lds[(EW + 1) * SLOT];
+    constexpr unsigned RS = N * EW * 8;  // byte stride of (v * N + b) in a row
     const int lane = threadIdx.x;
     const int sl = lane / N, k = lane - sl * N;
-    const int li = blockIdx.x * EW + sl;
-    const bool active = sl < EW && li < nlist;
-    const int e = list[active ? li : blockIdx.x * EW];  // idle lanes shadow a listed element
+    const int tile = list[blockIdx.x];
+    const int j = tile / g.tiles_x;
+    const int i0 = (tile - j * g.tiles_x) * EW;
+    const bool active = sl < EW && i0 + sl < g.nx;
+    const int i = active ? i0 + sl : i0;  // idle lanes shadow a valid element and store nothing
     double* S = lds + sl * SLOT;
     const double dt = scp->dt;
-    const int i = e % g.nx, j = e / g.nx;
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
     const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), req = make_rsrc(eq ? eq : u0);
-    const unsigned pstride = (unsigned)g.E * 8u;
-    const unsigned vrow = (unsigned)(k * N) * pstride + (unsigned)e * 8u;
+    const unsigned vrow = (tiled_base<N, NV>(g, i, j) + k * EW) * 8u;  // mode (k, 0)
 
     // mode row k: y contraction of u (full state) and u0
     double Ud[NV][N];
@@ -1193,7 +1216,7 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
         double A[N], A0[N];
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const unsigned so = (unsigned)(v * NN + b) * pstride;
+            const unsigned so = (unsigned)(v * N + b) * RS;
             Ud[v][b] = ld64(ru, vrow, so);
             A[b] = eq ? ld64(req, vrow, so) + Ud[v][b] : Ud[v][b];
             A0[b] = ld64(ru0, vrow, so);
@@ -1284,7 +1307,7 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
                 double s = 0.0;
 #pragma unroll
                 for (int r = 0; r < N; ++r) s += B.wphi[b][r] * S[(v * N + r) * N + k];
-                st64(ru, vrow, (unsigned)(v * NN + b) * pstride, Ud[v][b] + s);
+                st64(ru, vrow, (unsigned)(v * N + b) * RS, Ud[v][b] + s);
             }
     }
 }
@@ -1317,13 +1340,17 @@ __global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, double t, 
     double s = 0.0;
     if (e < g.E) {
         double M[1][NN], W[1][NN];
-#pragma unroll
-        for (int m = 0; m < NN; ++m) {
-            const long long idx = (long long)m * g.E + e;
-            M[0][m] = eq ? eq[idx] + u[idx] : u[idx];
-        }
-        eval_nodes<N, 1>(M, W);
         const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        // density modes (the variable count only sets the tile stride)
+        const unsigned base = g.closure == 2 ? tiled_base<N, 4>(g, i, j) : tiled_base<N, 3>(g, i, j);
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                const unsigned idx = base + mode_off<N>(0, a, b);
+                M[0][a * N + b] = eq ? eq[idx] + u[idx] : u[idx];
+            }
+        eval_nodes<N, 1>(M, W);
         const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
         const double area = g.dx * g.dy;
 #pragma unroll
@@ -1402,6 +1429,18 @@ hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0,
 
 int dt_blocks(const Geo& g) { return (int)((g.E + 255) / 256); }
 
+hipError_t launch_means(int n, int nvar, const Geo& g, const double* u, double* out, hipStream_t s) {
+    const int blocks = (int)((g.E + 255) / 256);
+    if (nvar == 3) {
+        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_means<NT, 3>), dim3(blocks), dim3(256), 0, s, g, u, out));
+    } else if (nvar == 4) {
+        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_means<NT, 4>), dim3(blocks), dim3(256), 0, s, g, u, out));
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_dt(int n, const Geo& g, const double* u, const double* eq, double* dt_part, unsigned int* bad_part,
                      hipStream_t s) {
     const int blocks = dt_blocks(g);
@@ -1445,11 +1484,8 @@ hipError_t launch_step_begin(const Geo& g, StepBlock* sb, const double* dt_part,
 hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const double* eq, const int* list,
                        int nlist, const StageCoeffs* sc, hipStream_t s) {
     if (nlist <= 0) return hipSuccess;
-    DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, {
-        constexpr int EW = 64 / NT;
-        const int blocks = (nlist + EW - 1) / EW;
-        hipLaunchKernelGGL((k_damp_c<NT, CT>), dim3(blocks), dim3(64), 0, s, g, u, u0, eq, list, nlist, sc);
-    }));
+    DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_damp_c<NT, CT>), dim3(nlist), dim3(64), 0, s, g,
+                                                                  u, u0, eq, list, nlist, sc)));
     return hipGetLastError();
 }
 

@@ -21,14 +21,15 @@ __device__ __forceinline__ double minmod3(double a, double b, double c) {
 
 // mean of variable v of the neighbour across edge f (0 W, 1 E, 2 S, 3 N);
 // at a fixed box edge the exterior mean is the element's own initial mean
+template <int N, int NV>
 __device__ __forceinline__ double nb_mean(const Geo& g, const double* __restrict__ u, const double* __restrict__ u0,
-                                          int nn, int i, int j, int v, int f) {
+                                          int i, int j, int v, int f) {
     int in = i + (f == 1) - (f == 0), jn = j + (f == 3) - (f == 2);
     const bool outside = in < 0 || in >= g.nx || jn < 0 || jn >= g.ny;
-    if (outside && g.bc == 1) return u0[(long long)v * nn * g.E + (long long)j * g.nx + i];
+    if (outside && g.bc == 1) return u0[tiled_base<N, NV>(g, i, j) + mode_off<N>(v, 0, 0)];
     in = (in + g.nx) % g.nx;
     jn = (jn + g.ny) % g.ny;
-    return u[(long long)v * nn * g.E + (long long)jn * g.nx + in];
+    return u[tiled_base<N, NV>(g, in, jn) + mode_off<N>(v, 0, 0)];
 }
 
 // mode: 0 = flags from the modal-decay sensor (s > s0), 1 = flags given.
@@ -40,10 +41,10 @@ __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const 
                                                   int mode, int apply, const unsigned char* __restrict__ flag_in,
                                                   unsigned char* flag_out, unsigned char* changed_out,
                                                   float* sensor_out) {
-    constexpr int NN = N * N;
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= g.E) return;
-    const long long E = g.E;
+    const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+    const unsigned base = tiled_base<N, NV>(g, i, j);
     bool flag;
     if (mode == 0) {
         double top = 0.0, all = 0.0;
@@ -51,7 +52,7 @@ __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const 
         for (int a = 0; a < N; ++a)
 #pragma unroll
             for (int b = 0; b < N; ++b) {
-                const double v = u[(long long)(a * N + b) * E + e];
+                const double v = u[base + mode_off<N>(0, a, b)];
                 all += v * v;
                 if (a == N - 1 || b == N - 1) top += v * v;
             }
@@ -64,16 +65,15 @@ __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const 
     if (flag_out) flag_out[e] = flag ? 1 : 0;
     bool changed = false;
     if (flag) {
-        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
         const double r3 = sqrt(3.0);
         double sx[NV], sy[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double m = u[(long long)v * NN * E + e];
-            const double ax = r3 * u[(long long)(v * NN + 1 * N + 0) * E + e];
-            const double ay = r3 * u[(long long)(v * NN + 0 * N + 1) * E + e];
-            const double lx = minmod3(ax, nb_mean(g, u, u0, NN, i, j, v, 1) - m, m - nb_mean(g, u, u0, NN, i, j, v, 0));
-            const double ly = minmod3(ay, nb_mean(g, u, u0, NN, i, j, v, 3) - m, m - nb_mean(g, u, u0, NN, i, j, v, 2));
+            const double m = u[base + mode_off<N>(v, 0, 0)];
+            const double ax = r3 * u[base + mode_off<N>(v, 1, 0)];
+            const double ay = r3 * u[base + mode_off<N>(v, 0, 1)];
+            const double lx = minmod3(ax, nb_mean<N, NV>(g, u, u0, i, j, v, 1) - m, m - nb_mean<N, NV>(g, u, u0, i, j, v, 0));
+            const double ly = minmod3(ay, nb_mean<N, NV>(g, u, u0, i, j, v, 3) - m, m - nb_mean<N, NV>(g, u, u0, i, j, v, 2));
             sx[v] = lx;
             sy[v] = ly;
             if (lx != ax || ly != ay) changed = true;
@@ -88,8 +88,7 @@ __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const 
 #pragma unroll
                     for (int b = 0; b < N; ++b) {
                         if (a == 0 && b == 0) continue;
-                        const long long idx = (long long)(v * NN + a * N + b) * E + e;
-                        u[idx] = (a == 1 && b == 0) ? sx[v] / r3 : (a == 0 && b == 1) ? sy[v] / r3 : 0.0;
+                        u[base + mode_off<N>(v, a, b)] = (a == 1 && b == 0) ? sx[v] / r3 : (a == 0 && b == 1) ? sy[v] / r3 : 0.0;
                     }
         }
     }
@@ -120,12 +119,13 @@ __global__ void __launch_bounds__(256) k_features(const Geo g, const double* __r
     constexpr int NN = N * N;
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= g.E) return;
+    const unsigned base = tiled_base<N, NV>(g, (int)(e % g.nx), (int)(e / g.nx));
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const double d = fabs(u[(long long)v * NN * g.E + e]) + scale[v];
+        const double d = fabs(u[base + mode_off<N>(v, 0, 0)]) + scale[v];
 #pragma unroll
         for (int m = 0; m < NN; ++m)
-            f[e * (NV * NN) + v * NN + m] = f2bf((float)(u[(long long)(v * NN + m) * g.E + e] / d));
+            f[e * (NV * NN) + v * NN + m] = f2bf((float)(u[base + mode_off<N>(v, m / N, m % N)] / d));
     }
 }
 
@@ -286,16 +286,18 @@ __global__ void __launch_bounds__(256) k_mlp_flags(const Geo g, const double* __
         const long long e = tile * 16 + i;
         const bool valid = e < E;
         const long long el = valid ? e : E - 1;  // in-bounds loads on a ragged last tile
+        const unsigned base = tiled_base<4, 4>(g, (int)(el % g.nx), (int)(el / g.nx));
         f32x4 c1[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) c1[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const double d = fabs(u[(long long)s * NN * E + el]) + scale[s];
+            const double d = fabs(u[base + mode_off<4>(s, 0, 0)]) + scale[s];
             bf16x4 b;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const short fv = (short)f2bf((float)(u[(long long)(s * NN + 4 * gq + k) * E + el] / d));
+                // mode m = 4 gq + k = (a, b) with a = gq, b = k
+                const short fv = (short)f2bf((float)(u[base + mode_off<4>(s, gq, k)] / d));
                 b[k] = valid ? fv : (short)0;
             }
 #pragma unroll

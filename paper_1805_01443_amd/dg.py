@@ -86,8 +86,19 @@ class Config:
         return self.nx * self.ny
 
     @property
+    def tile_width(self):
+        """elements per tile of the state layout (64 / order)"""
+        return 64 // self.order
+
+    @property
+    def tiles_x(self):
+        return -(-self.nx // self.tile_width)
+
+    @property
     def state_shape(self):
-        return (self.nvar, self.order * self.order, self.nx * self.ny)
+        """a state tensor in the element-tiled layout of dg.h:
+        [j][tile][var][b][a][slot]"""
+        return (self.ny, self.tiles_x, self.nvar, self.order, self.order, self.tile_width)
 
     def to_c(self) -> dg_config:
         c = dg_config()
@@ -111,6 +122,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, dp, cp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(dg_config)
         L.dg_get_nodes.argtypes = [cp, dp, dp]
+        L.dg_state_size.argtypes = [cp]
+        L.dg_state_size.restype = C.c_longlong
         L.dg_init.argtypes = [cp, dp, vp, vp, C.POINTER(vp)]
         L.dg_full_state.argtypes = [vp, vp, vp]
         L.dg_rhs.argtypes = [vp, C.c_double, vp, vp]
@@ -138,7 +151,7 @@ def lib():
     return _lib
 
 
-EXPORTS = ("dg_get_nodes", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
+EXPORTS = ("dg_get_nodes", "dg_state_size", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
            "dg_last_error", "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled",
            "dg_mlp_feature_scales", "dg_mlp_features", "dg_mlp_params", "dg_mlp_forward", "dg_mlp_train_step",
            "dg_capture")
@@ -187,6 +200,37 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+
+def dg_state_size(cfg: Config) -> int:
+    """doubles in one state array (padding included)"""
+    c = cfg.to_c()
+    n = lib().dg_state_size(C.byref(c))
+    if n < 0:
+        raise DGError(int(n), (lib().dg_last_error(None) or b"").decode())
+    return int(n)
+
+
+def to_planes(cfg: Config, u):
+    """A state (tiled layout; torch tensor or numpy array) as [var][a*n + b][e]
+    with e = j*nx + i, padding dropped (the layout the oracle uses)."""
+    n, W, TX = cfg.order, cfg.tile_width, cfg.tiles_x
+    x = u.reshape(cfg.state_shape)
+    x = x.permute(2, 4, 3, 0, 1, 5) if hasattr(x, "permute") else x.transpose(2, 4, 3, 0, 1, 5)
+    x = x.reshape(cfg.nvar, n * n, cfg.ny, TX * W)[..., :cfg.nx]
+    return x.reshape(cfg.nvar, n * n, cfg.n_elem)
+
+
+def from_planes(cfg: Config, planes, device="cuda"):
+    """Inverse of to_planes: [var][a*n + b][e] (numpy) to a tensor in the
+    tiled layout (padding zero)."""
+    import torch
+    n, W, TX = cfg.order, cfg.tile_width, cfg.tiles_x
+    p = np.asarray(planes, dtype=np.float64).reshape(cfg.nvar, n, n, cfg.ny, cfg.nx)
+    full = np.zeros((cfg.nvar, n, n, cfg.ny, TX * W))
+    full[..., :cfg.nx] = p
+    x = full.reshape(cfg.nvar, n, n, cfg.ny, TX, W).transpose(3, 4, 0, 2, 1, 5)  # [j][t][v][b][a][s]
+    return torch.tensor(np.ascontiguousarray(x), device=device)
 
 
 def dg_init(cfg: Config, prim, device="cuda"):

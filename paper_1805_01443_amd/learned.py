@@ -215,7 +215,7 @@ def evaluate_run(seed, nx, steps, every, params, theta, torch, s0=None, log=prin
     n = min(a["steps"], b["steps"])
     out["steps_completed"] = {"plain": a["steps"], "learned": b["steps"]}
     if a["steps"] == b["steps"]:
-        rho_p, rho_l = a["u"][0], b["u"][0]
+        rho_p, rho_l = dg.to_planes(cfg, a["u"])[0], dg.to_planes(cfg, b["u"])[0]
         out["density_rel_L2_diff"] = float(((rho_l - rho_p) ** 2).sum().sqrt() / (rho_p ** 2).sum().sqrt())
     if n > 0:
         out["torque_series_rel_diff"] = float((b["tq"][:n] - a["tq"][:n]).abs().max() / a["tq"][:n].abs().max())

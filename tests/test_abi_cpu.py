@@ -20,7 +20,7 @@ def _declared_symbols():
     for fn in os.listdir(os.path.join(ROOT, "include")):
         if fn.endswith(".h"):
             txt = open(os.path.join(ROOT, "include", fn)).read()
-            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(dg_\w+)\s*\(", txt, re.M))
+            names |= set(re.findall(r"^\s*(?:const\s+)?(?:\w+\s+)*\w+\s*\**\s*(dg_\w+)\s*\(", txt, re.M))
     return names
 
 
@@ -92,3 +92,31 @@ def test_product_path_does_not_import_the_oracle():
             if fn.endswith((".py", ".hip", ".cpp", ".h")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert not re.search(r"(import\s+oracle|from\s+oracle|liboracle|dg_oracle|or_rhs)", txt), fn
+
+
+@pytest.mark.parametrize("cfg", [W.wave(nx=70, order=3).replace(ny=9), W.disc(nx=26, order=5),
+                                 W.disc_ring(nx=40, order=4), W.wave(nx=5, order=2).replace(ny=3)])
+def test_state_size_and_tiled_layout(cfg):
+    """dg_state_size and the binding's layout conversion follow the formula of
+    the state layout in dg.h: mode (a, b) of variable v of element (i, j) at
+    ((t * nvar + v) * n + b) * n * W + a * W + s, t = j * TX + i / W, s = i % W."""
+    n, Wd = cfg.order, 64 // cfg.order
+    TX = -(-cfg.nx // Wd)
+    size = dg.dg_state_size(cfg)
+    assert size == cfg.nvar * n * n * TX * Wd * cfg.ny
+    pl = np.random.default_rng(0).normal(size=(cfg.nvar, n * n, cfg.n_elem))
+    u = np.zeros(size)
+    for e in range(cfg.n_elem):
+        i, j = e % cfg.nx, e // cfg.nx
+        t, s = j * TX + i // Wd, i % Wd
+        for v in range(cfg.nvar):
+            for a in range(n):
+                for b in range(n):
+                    u[((t * cfg.nvar + v) * n + b) * n * Wd + a * Wd + s] = pl[v, a * n + b, e]
+    assert np.array_equal(dg.to_planes(cfg, u), pl)
+    assert np.array_equal(dg.from_planes(cfg, pl, device="cpu").numpy().ravel(), u)
+
+
+def test_state_size_rejects_bad_config():
+    with pytest.raises(dg.DGError):
+        dg.dg_state_size(W.wave(nx=8).replace(order=9))

@@ -29,6 +29,11 @@ def ocfg(cfg):
     return O.cfg(dataclasses.asdict(cfg))
 
 
+def planes(cfg, u):
+    """a device state as [var][mode][element] (numpy)"""
+    return dg.to_planes(cfg, u.detach().cpu().numpy())
+
+
 def ring_setup(nx=48, order=4, s0=-2.4, limiter=dg.LIMITER_MODAL_DECAY, jump=False):
     """The ring workload; with jump=True the density and energy are doubled
     inside r = 1.6 (a discontinuity that the sensor flags)."""
@@ -50,7 +55,7 @@ def test_indicator_flags_labels_and_limited_state():
     T = torch()
     cfg, oc, h, u, uo = ring_setup(jump=True)
     u0 = uo.copy()
-    ug = T.tensor(uo, device="cuda")
+    ug = dg.from_planes(cfg, uo)
     E = cfg.n_elem
     fl = T.zeros(E, dtype=T.uint8, device="cuda")
     ch = T.zeros(E, dtype=T.uint8, device="cuda")
@@ -65,7 +70,7 @@ def test_indicator_flags_labels_and_limited_state():
     assert np.array_equal(fl.cpu().numpy().astype(bool), fo)
     ul, cho = O.minmod(oc, uo, u0, fo)
     assert np.array_equal(ch.cpu().numpy().astype(bool), cho)
-    err = np.max(np.abs(ug.cpu().numpy() - ul)) / np.max(np.abs(ul))
+    err = np.max(np.abs(planes(cfg, ug) - ul)) / np.max(np.abs(ul))
     assert err <= 1e-15
     h.close()
 
@@ -81,7 +86,7 @@ def test_limited_steps_parity():
         dg.dg_sync(h)
         uo, _ = O.step_limited(oc, uo, t, 1e-3, u0, cfg.limiter_s0)
         t += 1e-3
-        a = u.cpu().numpy()
+        a = planes(cfg, u)
         err = max(np.max(np.abs(a[v] - uo[v])) / np.max(np.abs(uo[v])) for v in range(cfg.nvar))
         print(f"[limited step {k}] rel err {err:.3e}", flush=True)
         assert err <= 1e-12
@@ -100,7 +105,7 @@ def test_features_bitwise():
     assert np.allclose(sc, np.sqrt(np.mean(means ** 2, axis=1)), rtol=1e-14, atol=0)
     # the same state on both sides (modes that vanish by symmetry carry
     # different round-off in the two projections)
-    fo = O.mlp_features(oc, u.cpu().numpy(), sc)
+    fo = O.mlp_features(oc, planes(cfg, u), sc)
     fo16 = np.array([O.bf16(v) for v in fo.ravel()]).reshape(fo.shape)
     got = (f.cpu().numpy().astype(np.int32) & 0xFFFF).astype(np.uint32) << 16
     got = got.view(np.float32).astype(np.float64)

@@ -44,6 +44,11 @@ def relerr(a, b, mask=None):
     return [float(np.max(np.abs(a[v] - b[v])) / max(np.max(np.abs(b[v])), 1e-300)) for v in range(a.shape[0])]
 
 
+def planes(cfg, u):
+    """a device state as [var][mode][element] (numpy)"""
+    return dg.to_planes(cfg, u.detach().cpu().numpy())
+
+
 def radii(cfg):
     """radius of every element centre"""
     dx, dy = (cfg.x1 - cfg.x0) / cfg.nx, (cfg.y1 - cfg.y0) / cfg.ny
@@ -90,7 +95,7 @@ def test_full_state_reconstructs_the_fp64_projection():
     dg.dg_full_state(hm, du0, full)
     h64, u64 = dg.dg_init(cfg.replace(precision=dg.PRECISION_FP64), prim)
     T.cuda.synchronize()
-    assert max(relerr(full.cpu().numpy(), u64.cpu().numpy())) < 1e-15
+    assert max(relerr(planes(cfg, full), planes(cfg, u64))) < 1e-15
     hm.close()
     h64.close()
 
@@ -108,7 +113,7 @@ def test_mixed_rhs_error_against_oracle(order):
     T.cuda.synchronize()
     uo = O.project(oc, prim)
     ro = O.rhs(oc, 0.37, uo, u0=uo)
-    rg = r.cpu().numpy()
+    rg = planes(cfg, r)
     err_all = relerr(rg, ro)
     err = relerr(rg, ro, annulus(cfg))
     worst = int(np.argmax(np.max(np.abs(rg - ro), axis=(0, 1))))
@@ -143,13 +148,13 @@ def test_mixed_steps_and_torque_against_fp64_gpu():
     full = T.empty_like(du)
     dg.dg_full_state(hm, du, full)
     T.cuda.synchronize()
-    e_all = relerr(full.cpu().numpy(), u.cpu().numpy())
-    e = relerr(full.cpu().numpy(), u.cpu().numpy(), annulus(cfg))
+    e_all = relerr(planes(cfg, full), planes(cfg, u))
+    e = relerr(planes(cfg, full), planes(cfg, u), annulus(cfg))
     print(f"[mixed 5 steps] whole-box state rel err {e_all}", flush=True)
     # deviation from the equilibrium: error relative to the evolved deviation itself
     dev64 = u - (full - du)
     ed = (full - u).abs().max().item() / dev64.abs().max().item()
-    _, sabs = O.torque(ocfg(cfg), t64.item(), u.cpu().numpy())
+    _, sabs = O.torque(ocfg(cfg), t64.item(), planes(cfg, u))
     print(f"[mixed 5 steps] state rel err {e}, rel to deviation {ed:.3e}, "
           f"torque {gm.item():.12e} vs {g64.item():.12e}", flush=True)
     assert max(e) <= BOUND
