@@ -38,7 +38,7 @@ class _Cfg(C.Structure):
         ("bc", C.c_int), ("star", C.c_int), ("gm", C.c_double), ("r_core", C.c_double),
         ("q", C.c_double), ("eps", C.c_double), ("rp", C.c_double), ("phi0", C.c_double),
         ("damping", C.c_int), ("rd_in", C.c_double), ("rd_out", C.c_double),
-        ("cfl", C.c_double), ("rk", C.c_int),
+        ("cfl", C.c_double), ("rk", C.c_int), ("positivity", C.c_int),
     ]
 
 
@@ -77,6 +77,9 @@ def lib():
         U8 = C.POINTER(C.c_ubyte)
         _lib.or_indicator.argtypes = [cp, P, P]
         _lib.or_minmod.argtypes = [cp, P, P, U8, U8]
+        _lib.or_gauss_lobatto.argtypes = [C.c_int, P, P]
+        _lib.or_pp_lobatto_points.argtypes = [C.c_int]
+        _lib.or_positivity.argtypes = [cp, P, U8, P]
         _lib.or_step_limited.argtypes = [cp, P, C.c_double, C.c_double, P, C.c_double]
         _lib.or_step_limited.restype = C.c_double
         _lib.or_mlp_features.argtypes = [cp, P, P, P]
@@ -92,7 +95,8 @@ def lib():
 
 _DEFAULTS = dict(n=3, nvar=3, nx=8, ny=8, x0=0.0, x1=1.0, y0=0.0, y1=1.0, closure=0, cs=1.0,
                  h=0.05, gamma=1.4, bc=0, star=0, gm=1.0, r_core=0.4, q=0.0, eps=0.03,
-                 rp=1.0, phi0=0.0, damping=0, rd_in=0.4, rd_out=2.3, cfl=0.2, rk=0)
+                 rp=1.0, phi0=0.0, damping=0, rd_in=0.4, rd_out=2.3, cfl=0.2, rk=0,
+                 positivity=0)
 
 
 def cfg(fields=None, **kw):
@@ -269,7 +273,29 @@ def minmod(c, u, u0, flags):
     return u, ch.astype(bool)
 
 
+def gauss_lobatto(L):
+    x = np.zeros(L)
+    w = np.zeros(L)
+    if lib().or_gauss_lobatto(int(L), _p(x), _p(w)) != 0:
+        raise ValueError("unsupported number of Gauss-Lobatto points")
+    return x, w
+
+
+def pp_lobatto_points(np_):
+    return int(lib().or_pp_lobatto_points(int(np_)))
+
+
+def positivity(c, u):
+    """returns (limited u, changed mask, theta[E, 2])"""
+    u = _f64(u).copy()
+    ch = np.zeros(n_elem(c), dtype=np.uint8)
+    th = np.zeros((n_elem(c), 2))
+    lib().or_positivity(C.byref(c), _p(u), _u8(ch), _p(th))
+    return u, ch.astype(bool), th
+
+
 def step_limited(c, u, t, dt_fixed, u0, s0):
+    """s0 = inf: no minmod flags (positivity alone if c.positivity)"""
     u = _f64(u).copy()
     d = lib().or_step_limited(C.byref(c), _p(u), float(t), float(dt_fixed), _p(_f64(u0)), float(s0))
     return u, d

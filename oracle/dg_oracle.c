@@ -80,6 +80,44 @@ int or_gauss_legendre(int n, double *x, double *w)
     return 0;
 }
 
+int or_gauss_lobatto(int L, double *x, double *w)
+{
+    if (L < 2 || L > OR_MAXN + 1) return -1;
+    const double pi = 3.14159265358979323846;
+    int k = L - 1; /* interior nodes: roots of P_k' */
+    for (int i = 0; i < L; ++i) {
+        double z;
+        if (i == 0)
+            z = -1.0;
+        else if (i == k)
+            z = 1.0;
+        else {
+            z = -cos(pi * i / k); /* Chebyshev-Gauss-Lobatto start */
+            for (int it = 0; it < 100; ++it) {
+                /* Newton on P_k'; P_k'' from Legendre's equation
+                 * (1 - z^2) P'' = 2 z P' - k (k+1) P */
+                double d1 = legendre_dp(k, z);
+                double d2 = (2.0 * z * d1 - k * (k + 1.0) * legendre_p(k, z)) / (1.0 - z * z);
+                double dz = d1 / d2;
+                z -= dz;
+                if (fabs(dz) < 1e-17) break;
+            }
+            if (2 * i == k) z = 0.0;
+        }
+        double pk = legendre_p(k, z);
+        x[i] = z;
+        w[i] = 2.0 / (k * (k + 1.0) * pk * pk);
+    }
+    return 0;
+}
+
+int or_pp_lobatto_points(int np)
+{
+    int L = 2;
+    while (2 * L - 3 < np) ++L;
+    return L;
+}
+
 /* ------------------------------------------------------------------ */
 /* per-configuration tables                                             */
 /* ------------------------------------------------------------------ */
@@ -380,6 +418,15 @@ double or_dt(const or_cfg *c, const double *u)
     tables T;
     make_tables(c, &T);
     long E = (long)c->nx * c->ny;
+    double fac = 1.0 / (2.0 * (c->n - 1) + 1.0);
+    if (c->positivity) {
+        /* Sec. 2.4: min(1/(2N_p+1), w_1/2), w_1 of the rule normalised to sum 1 */
+        double xl[OR_MAXN + 1], wl[OR_MAXN + 1];
+        or_gauss_lobatto(or_pp_lobatto_points(c->n - 1), xl, wl);
+        double w1 = 0.5 * wl[0];
+        if (0.5 * w1 < fac) fac = 0.5 * w1;
+    }
+    fac *= c->cfl;
     double dtmin = INFINITY;
     for (long e = 0; e < E; ++e) {
         int i = (int)(e % c->nx), j = (int)(e / c->nx);
@@ -389,7 +436,7 @@ double or_dt(const or_cfg *c, const double *u)
         closure(c, U, elem_xc(c, &T, i), elem_yc(c, &T, j), &p, &cs);
         double sx = (fabs(U[1] / U[0]) + cs) / T.dx;
         double sy = (fabs(U[2] / U[0]) + cs) / T.dy;
-        double dtk = c->cfl / (2.0 * (c->n - 1) + 1.0) / (sx + sy);
+        double dtk = fac / (sx + sy);
         if (dtk < dtmin) dtmin = dtk;
     }
     return dtmin;

@@ -44,10 +44,18 @@ typedef struct {
     double rd_in, rd_out;
     double cfl;
     int rk;           /* Appendix A table: 0 SSP(3,3), 1 SSP(2,2), 2 SSP(5,4), 3 Cash-Karp */
+    int positivity;   /* 1: positivity-preserving limiter after every stage (Sec. 2.4) */
 } or_cfg;
 
 /* Sec. 2.2, eq. (3): Gauss-Legendre nodes (ascending) and weights on [-1,1]. */
 int or_gauss_legendre(int n, double *x, double *w);
+/* Gauss-Lobatto nodes (ascending, both ends included) and weights on [-1,1],
+ * L >= 2 points: the interior nodes are the roots of P'_{L-1}, the weights
+ * 2 / (L (L-1) P_{L-1}(x)^2). */
+int or_gauss_lobatto(int L, double *x, double *w);
+/* Sec. 2.4: the Gauss-Lobatto rule of the positivity limiter for degree N_p
+ * has the fewest points L with 2L - 3 >= N_p */
+int or_pp_lobatto_points(int np);
 /* Sec. 2.2: orthonormal Legendre basis phi_a = sqrt(2a+1) P_a and derivative. */
 double or_phi(int a, double x);
 double or_dphi(int a, double x);
@@ -61,7 +69,9 @@ void or_eval_nodes(const or_cfg *c, const double *u, double *out);
 /* eq. (3): du/dt = L(u) at time t.  u0 (initial modes) supplies the exterior
  * traces when bc == 1 and may be NULL for periodic boxes. */
 void or_rhs(const or_cfg *c, double t, const double *u, const double *u0, double *rhs);
-/* Sec. 2.3: global CFL time step from the element means */
+/* Sec. 2.3: global CFL time step from the element means; with c->positivity
+ * the factor C/(2N_p+1) becomes C min(1/(2N_p+1), w_1/2), w_1 the end weight
+ * of the limiter's Gauss-Lobatto rule normalised to sum 1 (Sec. 2.4) */
 double or_dt(const or_cfg *c, const double *u);
 
 /* Algorithm 1 / Appendix A in Butcher form for a generic right-hand side */
@@ -101,8 +111,26 @@ void or_indicator(const or_cfg *c, const double *u, double *s);
  * the limited slopes and drops every other mode; changed[e] = 1 then. */
 void or_minmod(const or_cfg *c, double *u, const double *u0, const unsigned char *flag,
                unsigned char *changed);
-/* one SSP-RK3 step in Shu-Osher form with the limiter after every stage
- * (flags from or_indicator > s0); returns dt */
+/* Sec. 2.4: positivity-preserving limiter of Zhang & Shu (2010) on every
+ * element, in place.  The test points of element K are the tensor sets
+ * (Gauss-Lobatto in x) x (Gauss in y) and (Gauss in x) x (Gauss-Lobatto in
+ * y), Gauss-Lobatto of or_pp_lobatto_points(N_p) points.  With
+ * eps = min(1e-13, mean density, pressure of the means):
+ *   density:  theta1 = min(1, (mean - eps) / (mean - min over the points)),
+ *             the density's non-mean modes scaled by theta1;
+ *   pressure (adiabatic closure only): at every point where the
+ *             pressure of (density-limited) state w is below eps, t solves
+ *             p(mean + t (w - mean)) = eps on [0, 1); theta2 = min of those t
+ *             (1 if none); every variable's non-mean modes scaled by theta2.
+ * The isothermal closures have p proportional to the density, so the density
+ * step covers them.  Elements whose means are not admissible (mean density
+ * or pressure <= 0) are left as they are.  changed[e] = 1 where a mode
+ * changed; theta (may be NULL) receives theta1, theta2 per element. */
+void or_positivity(const or_cfg *c, double *u, unsigned char *changed, double *theta);
+/* one SSP-RK3 step in Shu-Osher form with the limiter after every stage:
+ * the minmod limiter on the elements with indicator > s0 (s0 = +inf: none),
+ * then, if c->positivity, or_positivity; returns dt (with c->positivity the
+ * CFL factor is C min(1/(2N_p+1), w_1/2), see or_dt) */
 double or_step_limited(const or_cfg *c, double *u, double t, double dt_fixed, const double *u0,
                        double s0);
 

@@ -90,6 +90,110 @@ void or_minmod(const or_cfg *c, double *u, const double *u0, const unsigned char
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* positivity-preserving limiter (Sec. 2.4; Zhang & Shu 2010)            */
+/* ------------------------------------------------------------------ */
+
+#define PP_MAXP 16 /* points per direction of either rule, generous */
+
+/* value of variable v of element e at reference point (xi, eta) */
+static double point_value(const or_cfg *c, const double *u, long e, int v, double xi, double eta)
+{
+    long E = (long)c->nx * c->ny;
+    int n = c->n;
+    double s = 0.0;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) s += u[((long)v * n * n + a * n + b) * E + e] * or_phi(a, xi) * or_phi(b, eta);
+    return s;
+}
+
+static double pressure_of(const or_cfg *c, const double *U)
+{
+    return (c->gamma - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0]);
+}
+
+void or_positivity(const or_cfg *c, double *u, unsigned char *changed, double *theta)
+{
+    long E = (long)c->nx * c->ny;
+    int n = c->n, nn = n * n, nv = c->nvar;
+    const int adi = c->closure == 2;
+    /* the test points: (Lobatto x Gauss) and (Gauss x Lobatto) */
+    double xg[PP_MAXP], wg[PP_MAXP], xl[PP_MAXP], wl[PP_MAXP];
+    or_gauss_legendre(n, xg, wg);
+    int L = or_pp_lobatto_points(n - 1);
+    or_gauss_lobatto(L, xl, wl);
+    int np = 2 * L * n;
+    double *px = (double *)malloc(sizeof(double) * np), *py = (double *)malloc(sizeof(double) * np);
+    int k = 0;
+    for (int q = 0; q < L; ++q)
+        for (int r = 0; r < n; ++r) {
+            px[k] = xl[q];
+            py[k] = xg[r];
+            ++k;
+        }
+    for (int q = 0; q < n; ++q)
+        for (int r = 0; r < L; ++r) {
+            px[k] = xg[q];
+            py[k] = xl[r];
+            ++k;
+        }
+    for (long e = 0; e < E; ++e) {
+        double M[4];
+        for (int v = 0; v < nv; ++v) M[v] = u[((long)v * nn) * E + e];
+        double th1 = 1.0, th2 = 1.0;
+        changed[e] = 0;
+        double pbar = adi ? pressure_of(c, M) : M[0];
+        if (!(M[0] > 0.0) || !(pbar > 0.0)) {
+            if (theta) theta[2 * e] = theta[2 * e + 1] = 1.0;
+            continue;
+        }
+        double eps = 1e-13;
+        if (M[0] < eps) eps = M[0];
+        if (adi && pbar < eps) eps = pbar;
+        /* density */
+        double rmin = INFINITY;
+        for (int k2 = 0; k2 < np; ++k2) {
+            double r = point_value(c, u, e, 0, px[k2], py[k2]);
+            if (r < rmin) rmin = r;
+        }
+        if (rmin < eps) {
+            th1 = (M[0] - eps) / (M[0] - rmin);
+            for (int m = 1; m < nn; ++m) u[((long)m) * E + e] *= th1;
+        }
+        /* pressure, with the density already limited */
+        if (adi) {
+            for (int k2 = 0; k2 < np; ++k2) {
+                double W[4];
+                for (int v = 0; v < 4; ++v) W[v] = point_value(c, u, e, v, px[k2], py[k2]);
+                if (!(pressure_of(c, W) < eps)) continue;
+                /* p(M + t (W - M)) = eps, times 2 rho(t) / (gamma - 1):
+                 * 2 rho(t) E(t) - |m(t)|^2 - 2 eps rho(t) / (gamma - 1) = A t^2 + B t + C,
+                 * C > 0 at t = 0 and < 0 at t = 1; the root in (0, 1) */
+                double d[4];
+                for (int v = 0; v < 4; ++v) d[v] = W[v] - M[v];
+                double ge = 2.0 * eps / (c->gamma - 1.0);
+                double A = 2.0 * d[0] * d[3] - d[1] * d[1] - d[2] * d[2];
+                double B = 2.0 * (M[0] * d[3] + M[3] * d[0]) - 2.0 * (M[1] * d[1] + M[2] * d[2]) - ge * d[0];
+                double C0 = 2.0 * M[0] * M[3] - M[1] * M[1] - M[2] * M[2] - ge * M[0];
+                double t = 2.0 * C0 / (-B + sqrt(B * B - 4.0 * A * C0));
+                if (!(t >= 0.0)) t = 0.0;
+                if (t > 1.0) t = 1.0;
+                if (t < th2) th2 = t;
+            }
+            if (th2 < 1.0)
+                for (int v = 0; v < nv; ++v)
+                    for (int m = 1; m < nn; ++m) u[((long)v * nn + m) * E + e] *= th2;
+        }
+        if (theta) {
+            theta[2 * e] = th1;
+            theta[2 * e + 1] = th2;
+        }
+        changed[e] = th1 < 1.0 || th2 < 1.0;
+    }
+    free(px);
+    free(py);
+}
+
 static void limit_state(const or_cfg *c, double *u, const double *u0, double s0)
 {
     long E = (long)c->nx * c->ny;
@@ -98,6 +202,7 @@ static void limit_state(const or_cfg *c, double *u, const double *u0, double s0)
     or_indicator(c, u, s);
     for (long e = 0; e < E; ++e) fl[e] = s[e] > s0;
     or_minmod(c, u, u0, fl, ch);
+    if (c->positivity) or_positivity(c, u, ch, NULL);
     free(s);
     free(fl);
     free(ch);

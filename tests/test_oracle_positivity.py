@@ -1,0 +1,252 @@
+"""Pins of the oracle's positivity-preserving limiter (Sec. 2.4, the limiter of
+Zhang & Shu 2010) and of its time-step restriction, against closed forms,
+textbook quadrature facts and invariants evaluated independently of the oracle
+(numpy's Legendre series).  CPU only."""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+
+import oracle as O
+
+
+# ------------------------------------------------------------------ Gauss-Lobatto rules
+CLOSED = {
+    2: ([-1.0, 1.0], [1.0, 1.0]),
+    3: ([-1.0, 0.0, 1.0], [1 / 3, 4 / 3, 1 / 3]),
+    4: ([-1.0, -1 / math.sqrt(5), 1 / math.sqrt(5), 1.0], [1 / 6, 5 / 6, 5 / 6, 1 / 6]),
+    5: ([-1.0, -math.sqrt(3 / 7), 0.0, math.sqrt(3 / 7), 1.0], [1 / 10, 49 / 90, 32 / 45, 49 / 90, 1 / 10]),
+}
+
+
+@pytest.mark.parametrize("L", sorted(CLOSED))
+def test_lobatto_closed_forms(L):
+    x, w = O.gauss_lobatto(L)
+    assert np.allclose(x, CLOSED[L][0], rtol=0, atol=2e-16)
+    assert np.allclose(w, CLOSED[L][1], rtol=0, atol=4e-16)
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6])
+def test_lobatto_exact_to_degree_2L_minus_3(L):
+    x, w = O.gauss_lobatto(L)
+    for k in range(2 * L - 2):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.sum(w * x ** k) - exact) <= 1e-14
+    k = 2 * L - 2  # first even degree the rule misses
+    assert abs(np.sum(w * x ** k) - 2.0 / (k + 1)) > 1e-6
+
+
+def test_lobatto_points_for_degree():
+    # the fewest points with 2L - 3 >= N_p
+    assert [O.pp_lobatto_points(p) for p in range(1, 7)] == [2, 3, 3, 4, 4, 5]
+
+
+# ------------------------------------------------------------------ CFL restriction
+@pytest.mark.parametrize("order,w1", [(2, 1 / 2), (3, 1 / 6), (4, 1 / 6), (5, 1 / 12)])
+def test_dt_restriction_closed_form(order, w1):
+    """uniform state: dt = C min(1/(2N_p+1), w_1/2) / ((|v|+c)/dx + (|v|+c)/dy),
+    w_1 the end weight of the L-point rule normalised to sum 1"""
+    n = order
+    for pos in (0, 1):
+        c = O.cfg(n=n, nvar=3, nx=8, ny=4, closure=0, cs=1.0, cfl=0.2, positivity=pos)
+        E = 32
+        u = np.zeros((3, n * n, E))
+        u[0, 0] = 2.0
+        u[1, 0] = 2.0 * 0.5
+        u[2, 0] = 2.0 * -0.25
+        fac = 1.0 / (2 * (n - 1) + 1)
+        if pos:
+            fac = min(fac, w1 / 2)
+        want = 0.2 * fac / ((0.5 + 1.0) / (1 / 8) + (0.25 + 1.0) / (1 / 4))
+        assert abs(O.dt(c, u) - want) <= 1e-15 * want
+
+
+# ------------------------------------------------------------------ the limiter
+def adi_cfg(n=4, nx=6, ny=5):
+    return O.cfg(n=n, nvar=4, nx=nx, ny=ny, closure=2, gamma=1.4, bc=0, positivity=1)
+
+
+def eval_points(c, u, e):
+    """every variable at the limiter's test points of element e, evaluated with
+    numpy's Legendre series: (nvar, npoints)"""
+    n = c.n
+    L = O.pp_lobatto_points(n - 1)
+    xg = npleg.leggauss(n)[0]
+    xl = O.gauss_lobatto(L)[0]
+    pts = [(a, b) for a in xl for b in xg] + [(a, b) for a in xg for b in xl]
+    scale = np.sqrt(2 * np.arange(n) + 1.0)
+    out = np.zeros((c.nvar, len(pts)))
+    for v in range(c.nvar):
+        coef = u[v, :, e].reshape(n, n) * scale[:, None] * scale[None, :]
+        for k, (xi, eta) in enumerate(pts):
+            out[v, k] = npleg.legval2d(xi, eta, coef)
+    return out
+
+
+def pressure(U, gamma=1.4):
+    return (gamma - 1.0) * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / U[0])
+
+
+def smooth_state(c, rng, amp=0.02):
+    """an admissible state: means (1, 0.1, -0.2, 2.5), small higher modes"""
+    E = c.nx * c.ny
+    nn = c.n * c.n
+    u = rng.uniform(-amp, amp, (c.nvar, nn, E))
+    u[:, 0, :] = np.array([1.0, 0.1, -0.2, 2.5])[:, None]
+    return u
+
+
+def test_admissible_elements_are_untouched_bitwise():
+    c = adi_cfg()
+    u = smooth_state(c, np.random.default_rng(0))
+    ul, ch, th = O.positivity(c, u)
+    assert not ch.any() and np.all(th == 1.0)
+    assert np.array_equal(ul, u)
+
+
+def test_density_closed_form_linear_profile():
+    """rho = 1 + alpha sqrt(3) xi: the minimum over the points is at xi = -1
+    (a Lobatto end), 1 - sqrt(3) alpha; theta1 = (1 - eps)/(sqrt(3) alpha)"""
+    c = adi_cfg(n=3, nx=2, ny=1)
+    u = np.zeros((4, 9, 2))
+    u[0, 0] = 1.0
+    u[3, 0] = 2.5
+    alpha = 1.0
+    u[0, 1 * 3 + 0, 0] = alpha  # mode (1, 0)
+    ul, ch, th = O.positivity(c, u)
+    eps = 1e-13
+    want = (1.0 - eps) / (math.sqrt(3.0) * alpha)
+    assert abs(th[0, 0] - want) <= 1e-15
+    assert ch.tolist() == [True, False]
+    assert abs(ul[0, 3, 0] - alpha * want) <= 1e-15
+    # means bitwise, the limited density touches eps at xi = -1
+    assert np.array_equal(ul[:, 0], u[:, 0])
+    assert abs(eval_points(c, ul, 0)[0].min() - eps) <= 1e-15
+
+
+def test_pressure_closed_form_linear_energy():
+    """rho = 1, m = 0, E = Ebar + beta sqrt(3) eta: p is linear along the
+    segment, t = (Ebar - eps/(gamma-1)) / (sqrt(3) beta)"""
+    c = adi_cfg(n=4, nx=1, ny=1)
+    u = np.zeros((4, 16, 1))
+    u[0, 0] = 1.0
+    u[3, 0] = 1.0
+    beta = 2.0
+    u[3, 0 * 4 + 1] = beta  # mode (0, 1)
+    u[1, 2 * 4 + 3] = 1e-3  # a higher x-momentum mode that the scaling must shrink too
+    ul, ch, th = O.positivity(c, u)
+    eps = 1e-13
+    assert th[0, 0] == 1.0
+    # the momentum mode makes the minimum slightly lower than the linear
+    # closed form; compare against the closed form without it
+    u2 = u.copy()
+    u2[1, 11] = 0.0
+    ul2, _, th2 = O.positivity(c, u2)
+    want = (1.0 - eps / 0.4) / (math.sqrt(3.0) * beta)
+    assert abs(th2[0, 1] - want) <= 2e-15
+    assert th[0, 1] < th2[0, 1]
+    assert abs(ul[1, 11, 0] - 1e-3 * th[0, 1]) <= 1e-18
+    assert np.array_equal(ul[:, 0], u[:, 0])
+
+
+def test_pressure_closed_form_quadratic_momentum():
+    """rho = 1, E = Ebar, m_x = mu sqrt(3) xi: p(t) = (gamma-1)(Ebar - 3 mu^2 t^2 / 2)
+    at xi = +-1, so t = sqrt(2 (Ebar - eps/(gamma-1)) / (3 mu^2)) (the A != 0 root)"""
+    c = adi_cfg(n=3, nx=1, ny=1)
+    u = np.zeros((4, 9, 1))
+    u[0, 0] = 1.0
+    u[3, 0] = 1.0
+    mu = 1.5
+    u[1, 3] = mu
+    ul, ch, th = O.positivity(c, u)
+    want = math.sqrt(2.0 * (1.0 - 1e-13 / 0.4) / (3.0 * mu * mu))
+    assert abs(th[0, 1] - want) <= 1e-15
+    assert abs(ul[1, 3, 0] - mu * want) <= 1e-15
+
+
+def test_isothermal_closure_has_no_pressure_step():
+    c = O.cfg(n=3, nvar=3, nx=1, ny=1, closure=0, cs=1.0, positivity=1)
+    u = np.zeros((3, 9, 1))
+    u[0, 0] = 1.0
+    u[0, 1] = 1.0  # density -> negative at eta = -1
+    u[1, 3] = 50.0  # any momentum is admissible
+    ul, ch, th = O.positivity(c, u)
+    assert th[0, 1] == 1.0 and th[0, 0] < 1.0
+    assert ul[1, 3, 0] == 50.0
+
+
+def test_inadmissible_means_left_alone():
+    c = adi_cfg(n=3, nx=2, ny=1)
+    u = np.zeros((4, 9, 2))
+    u[0, 0] = [-1.0, 1.0]
+    u[3, 0] = [2.0, -0.5]  # element 1: negative mean pressure
+    u[0, 1] = 5.0
+    ul, ch, th = O.positivity(c, u)
+    assert not ch.any()
+    assert np.array_equal(ul, u)
+
+
+def test_random_states_limited_to_admissible_and_tight():
+    """random strongly oscillating states: after limiting every test point has
+    density and pressure >= eps (to round-off); theta is the largest such
+    factor, i.e. the binding point sits at eps; means are bitwise unchanged"""
+    c = adi_cfg(n=5, nx=7, ny=6)
+    rng = np.random.default_rng(42)
+    u = smooth_state(c, rng, amp=0.6)
+    ul, ch, th = O.positivity(c, u)
+    assert ch.sum() > 10
+    assert np.array_equal(ul[:, 0], u[:, 0])
+    eps = 1e-13
+    for e in range(c.nx * c.ny):
+        w = eval_points(c, ul, e)
+        p = pressure(w)
+        assert w[0].min() >= eps - 1e-13
+        assert p.min() >= eps - 1e-13
+        if th[e, 0] < 1.0 and th[e, 1] == 1.0:
+            assert abs(w[0].min() - eps) <= 1e-13
+        if th[e, 1] < 1.0:
+            assert abs(p.min() - eps) <= 1e-12
+        # higher modes are the original ones times the thetas
+        assert np.allclose(ul[0, 1:, e], u[0, 1:, e] * th[e, 0] * th[e, 1], rtol=1e-14, atol=1e-16)
+        assert np.allclose(ul[1:, 1:, e], u[1:, 1:, e] * th[e, 1], rtol=1e-14, atol=1e-16)
+
+
+def test_limiter_keeps_a_double_rarefaction_positive():
+    """Sec. 2.4's purpose: two gases receding at Mach 2.7 (rho = 1, p = 0.4,
+    v = -+2) open a near-vacuum.  At the same fixed dt, the scheme without the
+    limiter goes non-finite within a few steps; with it (applied to the
+    projected initial state too) every element mean stays admissible and every
+    test point keeps density and pressure >= eps for 100 steps."""
+    n, nx, ny = 3, 32, 2
+    base = dict(n=n, nvar=4, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=2.0 / nx, closure=2,
+                gamma=1.4, bc=0, cfl=1.0)
+    c0 = O.cfg(**base, positivity=0)
+    c1 = O.cfg(**base, positivity=1)
+    x, y = O.nodes(c0)
+    E = nx * ny
+    xm = x % 1.0
+    vx = np.where(xm < 0.5, -2.0, 2.0)
+    vx = np.where((xm < 0.02) | (xm > 0.98), 0.0, vx)
+    prim = np.stack([np.ones_like(x), vx, np.zeros_like(x), 0.4 * np.ones_like(x)]).reshape(4, E, n * n)
+    u0, ch0, _ = O.positivity(c1, O.project(c0, prim))
+    assert ch0.any()  # the projected jump already undershoots
+
+    def run(c, steps):
+        u = u0.copy()
+        with np.errstate(all="ignore"):
+            for k in range(steps):
+                u, _ = O.step_limited(c, u, k * 5e-4, 5e-4, u0, math.inf)
+                if not np.all(np.isfinite(u)):
+                    return u, False
+        return u, True
+
+    u1, ok1 = run(c1, 100)
+    assert ok1
+    assert np.all(u1[0, 0] > 0) and np.all(pressure(u1[:, 0]) > 0)
+    assert u1[0, 0].min() < 0.05  # the near-vacuum did open
+    for e in range(E):
+        w = eval_points(c1, u1, e)
+        assert w[0].min() >= 0.0 and pressure(w).min() >= 0.0
+    _, ok0 = run(c0, 20)
+    assert not ok0
