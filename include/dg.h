@@ -78,6 +78,8 @@ typedef struct dg_config {
     double limiter_s0;    /* modal-decay threshold on log10 of the top-mode energy share */
     double mlp_theta;     /* learned indicator: flag when sigmoid output > theta */
     int rk;               /* DG_RK_* (0 = SSP(3,3)) */
+    int positivity;       /* 1: positivity-preserving limiter (Sec. 2.4), see dg_positivity */
+    double pp_eps;        /* floor e0 of its eps (<= 0: 1e-13, Zhang & Shu's value) */
 } dg_config;
 
 typedef struct dg_handle dg_handle;
@@ -160,6 +162,24 @@ int dg_torque(dg_handle *h, double t, const double *t_dev, const double *u_dev, 
  * energy share, float). */
 int dg_troubled(dg_handle *h, double *u_dev, int apply, unsigned char *flag_dev, unsigned char *changed_dev,
                 float *sensor_dev);
+/* Positivity-preserving limiter of Sec. 2.4 (the scaling limiter of Zhang &
+ * Shu 2010), in place on every element of u_dev (device, the layout above).
+ * Test points of an element: the tensor sets (Gauss-Lobatto in x) x (Gauss in
+ * y) and (Gauss in x) x (Gauss-Lobatto in y), with the fewest Lobatto points L
+ * such that 2L - 3 >= N_p.  eps = min(e0, mean density, mean pressure), e0 =
+ * cfg->pp_eps (1e-13 when <= 0).
+ * The density's non-mean modes are scaled by theta1 = (mean - eps) / (mean -
+ * min) where its minimum over the points is below eps; then (adiabatic closure
+ * only) every variable's non-mean modes by theta2, the smallest t in [0, 1]
+ * with p(mean + t (w - mean)) = eps over the points w whose pressure is below
+ * eps.  Means never change; elements whose means are not admissible are left
+ * alone.  Outputs (device, may be NULL): changed_dev[e] (E bytes) = 1 where a
+ * mode changed, theta_dev[2e], theta_dev[2e+1] (2E doubles) = theta1, theta2.
+ * With cfg->positivity = 1 (SSP(3,3), FP64 form), dg_init limits the projected
+ * initial state, dg_rk_step limits every stage state after the minmod limiter
+ * (if any), and the CFL factor C/(2N_p+1) becomes C min(1/(2N_p+1), w_1/2),
+ * w_1 the end weight of the Lobatto rule normalised to sum 1. */
+int dg_positivity(dg_handle *h, double *u_dev, unsigned char *changed_dev, double *theta_dev);
 /* Feature scales s_v (RMS of the initial element means of variable v), host
  * array of nvar doubles. */
 int dg_mlp_feature_scales(dg_handle *h, double *scales_host);

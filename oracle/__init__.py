@@ -39,6 +39,7 @@ class _Cfg(C.Structure):
         ("q", C.c_double), ("eps", C.c_double), ("rp", C.c_double), ("phi0", C.c_double),
         ("damping", C.c_int), ("rd_in", C.c_double), ("rd_out", C.c_double),
         ("cfl", C.c_double), ("rk", C.c_int), ("positivity", C.c_int),
+        ("pp_eps", C.c_double),
     ]
 
 
@@ -96,7 +97,7 @@ def lib():
 _DEFAULTS = dict(n=3, nvar=3, nx=8, ny=8, x0=0.0, x1=1.0, y0=0.0, y1=1.0, closure=0, cs=1.0,
                  h=0.05, gamma=1.4, bc=0, star=0, gm=1.0, r_core=0.4, q=0.0, eps=0.03,
                  rp=1.0, phi0=0.0, damping=0, rd_in=0.4, rd_out=2.3, cfl=0.2, rk=0,
-                 positivity=0)
+                 positivity=0, pp_eps=0.0)
 
 
 def cfg(fields=None, **kw):

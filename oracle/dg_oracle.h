@@ -45,6 +45,7 @@ typedef struct {
     double cfl;
     int rk;           /* Appendix A table: 0 SSP(3,3), 1 SSP(2,2), 2 SSP(5,4), 3 Cash-Karp */
     int positivity;   /* 1: positivity-preserving limiter after every stage (Sec. 2.4) */
+    double pp_eps;    /* floor of the limiter's eps (<= 0: 1e-13) */
 } or_cfg;
 
 /* Sec. 2.2, eq. (3): Gauss-Legendre nodes (ascending) and weights on [-1,1]. */
@@ -115,7 +116,8 @@ void or_minmod(const or_cfg *c, double *u, const double *u0, const unsigned char
  * element, in place.  The test points of element K are the tensor sets
  * (Gauss-Lobatto in x) x (Gauss in y) and (Gauss in x) x (Gauss-Lobatto in
  * y), Gauss-Lobatto of or_pp_lobatto_points(N_p) points.  With
- * eps = min(1e-13, mean density, pressure of the means):
+ * eps = min(e0, mean density, pressure of the means), e0 = c->pp_eps, or
+ * 1e-13 (Zhang & Shu's value) when that is <= 0:
  *   density:  theta1 = min(1, (mean - eps) / (mean - min over the points)),
  *             the density's non-mean modes scaled by theta1;
  *   pressure (adiabatic closure only): at every point where the

@@ -147,7 +147,7 @@ void or_positivity(const or_cfg *c, double *u, unsigned char *changed, double *t
             if (theta) theta[2 * e] = theta[2 * e + 1] = 1.0;
             continue;
         }
-        double eps = 1e-13;
+        double eps = c->pp_eps > 0.0 ? c->pp_eps : 1e-13;
         if (M[0] < eps) eps = M[0];
         if (adi && pbar < eps) eps = pbar;
         /* density */

@@ -11,6 +11,8 @@
 * ``disc_mixed``  the sweep disc at order 5 in the mixed-precision deviation form.
 * ``disc_ring``   the adiabatic disc at order 4 with an over-pressure ring, for
                 the troubled-cell indicator.
+* ``rarefaction`` adiabatic gases receding at Mach 2.7 on a periodic strip,
+                with the positivity-preserving limiter.
 """
 from __future__ import annotations
 
@@ -48,6 +50,11 @@ def disc_ring(nx=1024, order=4):
     return c.replace(nvar=4, closure=CLOSURE_ADIABATIC, gamma=1.4)
 
 
+def rarefaction(nx=32, ny=2, order=3):
+    return Config(order=order, nvar=4, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=ny / nx,
+                  closure=CLOSURE_ADIABATIC, gamma=1.4, bc=BC_PERIODIC, cfl=1.0, positivity=1)
+
+
 def prim_for(cfg: Config, kind: str, seed=None, x=None, y=None):
     """Primitive node values [var][E][n^2] of a workload.  Node coordinates
     default to the library's (dg_get_nodes); tests pass the oracle's."""
@@ -67,6 +74,8 @@ def prim_for(cfg: Config, kind: str, seed=None, x=None, y=None):
         s0 = 1.0 if seed is None else synth.disc_sigma0(seed)
         rr = 1.6 if seed is None else synth.ring_radius(seed)
         fields = synth.disc_ring(x, y, gm=cfg.gm, h=cfg.h, r_core=cfg.r_core, sigma0=s0, r_ring=rr)
+    elif kind == "rarefaction":
+        fields = synth.double_rarefaction(x, y)
     else:
         raise ValueError(kind)
     return synth.pack_prim(fields, E, nn)
@@ -81,4 +90,4 @@ def sigma0_of(seed):
     return 1.0 if seed is None else synth.disc_sigma0(seed)
 
 
-__all__ = ["wave", "disc", "disc_sweep", "disc_ring", "prim_for", "dofs", "np"]
+__all__ = ["wave", "disc", "disc_sweep", "disc_ring", "rarefaction", "prim_for", "dofs", "np"]

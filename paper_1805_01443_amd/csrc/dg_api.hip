@@ -123,6 +123,12 @@ int validate(const dg_config* c, std::string* why) {
         return (*why = "the learned indicator takes 16 modes x 4 variables (order 4, nvar 4)", DG_EUNSUPPORTED);
     if (c->limiter == DG_LIMITER_LEARNED && !(c->mlp_theta > 0 && c->mlp_theta < 1))
         return (*why = "mlp_theta must be in (0, 1)", DG_EINVAL);
+    if (c->positivity != 0 && c->positivity != 1) return (*why = "positivity must be 0 or 1", DG_EINVAL);
+    if (!(c->pp_eps >= 0 && c->pp_eps < 1e300)) return (*why = "pp_eps must be finite and >= 0", DG_EINVAL);
+    if (c->positivity && c->rk != DG_RK_SSP33)
+        return (*why = "the positivity limiter is built for the SSP(3,3) table", DG_EUNSUPPORTED);
+    if (c->positivity && c->precision != DG_PRECISION_FP64)
+        return (*why = "the positivity limiter is built for the FP64 form", DG_EUNSUPPORTED);
     if ((double)c->nvar * c->order * c->order * state_slots(c) * 8.0 >= 4294967296.0)
         return (*why = "state arrays are limited to 4 GiB (32-bit buffer offsets)", DG_EUNSUPPORTED);
     return DG_OK;
@@ -171,6 +177,12 @@ void make_geo(const dg_config* c, Geo* g) {
     g->td_in = c->gm > 0 ? 2.0 * pi * std::sqrt(c->rd_in * c->rd_in * c->rd_in / c->gm) : 0.0;
     g->td_out = c->gm > 0 ? 2.0 * pi * std::sqrt(c->rd_out * c->rd_out * c->rd_out / c->gm) : 0.0;
     g->cfl_fac = c->cfl / (2.0 * (c->order - 1) + 1.0);
+    g->pp_eps = c->pp_eps > 0.0 ? c->pp_eps : 1e-13;
+    if (c->positivity) {
+        // Sec. 2.4: C min(1/(2N_p+1), w_1/2), w_1 of the limiter's Lobatto rule
+        const dgk::LobattoTab lt = dgk::make_lobatto(c->order);
+        g->cfl_fac = c->cfl * std::fmin(1.0 / (2.0 * (c->order - 1) + 1.0), lt.w1h);
+    }
     g->sigma0 = c->sigma0;
 }
 
@@ -240,7 +252,11 @@ void equilibrium_prim(const dg_config* c, std::vector<double>* prim) {
 // of a step (where an armed capture records the pre-limiter state)
 hipError_t limit(dg_handle* h, double* u, bool last) {
     const int lim = h->cfg.limiter;
-    if (lim == DG_LIMITER_NONE) return hipSuccess;
+    const int pp = h->cfg.positivity;
+    if (lim == DG_LIMITER_NONE)
+        return pp ? dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, 0.0, 2, 1, nullptr, nullptr, nullptr, nullptr,
+                                         1, nullptr, h->s)
+                  : hipSuccess;
     hipError_t e = hipSuccess;
     const bool cap = last && h->cap;
     if (cap) {
@@ -248,19 +264,20 @@ hipError_t limit(dg_handle* h, double* u, bool last) {
         if (h->cap_feat) e = dgk::launch_features(h->n, h->nvar, h->g, u, h->scale_dev, h->cap_feat, h->s);
         if (e == hipSuccess && (h->cap_flag || h->cap_label))
             e = dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, h->cfg.limiter_s0, 0, 0, nullptr, h->cap_flag,
-                                     h->cap_label, nullptr, h->s);
+                                     h->cap_label, nullptr, 0, nullptr, h->s);
         if (e != hipSuccess) return e;
     }
     if (lim == DG_LIMITER_MODAL_DECAY)
         return dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, h->cfg.limiter_s0, 0, 1, nullptr, nullptr, nullptr,
-                                    nullptr, h->s);
+                                    nullptr, pp, nullptr, h->s);
     const float th = (float)h->cfg.mlp_theta;
     const float zthr = std::log(th / (1.0f - th));  // sigmoid(z) > theta  <=>  z > logit(theta)
     e = dgk::launch_mlp_flags(h->g, u, h->scale_dev, h->mlp, h->flags, zthr, h->s);
     if (e == hipSuccess && cap && h->cap_mlp)
         e = hipMemcpyAsync(h->cap_mlp, h->flags, (size_t)h->E, hipMemcpyDeviceToDevice, h->s);
     if (e == hipSuccess)
-        e = dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, 0.0, 1, 1, h->flags, nullptr, nullptr, nullptr, h->s);
+        e = dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, 0.0, 1, 1, h->flags, nullptr, nullptr, nullptr, pp,
+                                 nullptr, h->s);
     return e;
 }
 
@@ -459,6 +476,10 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     if (e == hipSuccess && h->dev) e = hipMemsetAsync(h->leq, 0, state_bytes / 2, h->s);
     if (e == hipSuccess) e = hipMemcpyAsync(prim_dev, prim_nodes_host, prim_bytes, hipMemcpyHostToDevice, h->s);
     if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, u0_dev, h->s);
+    // the positivity limiter acts on the projected initial state too
+    if (e == hipSuccess && cfg->positivity)
+        e = dgk::launch_troubled(h->n, h->nvar, h->g, u0_dev, nullptr, 0.0, 2, 1, nullptr, nullptr, nullptr, nullptr, 1,
+                                 nullptr, h->s);
     if (e == hipSuccess) e = hipMemcpyAsync(h->u0, u0_dev, state_bytes, hipMemcpyDeviceToDevice, h->s);
     if (e == hipSuccess) e = hipStreamSynchronize(h->s);
     if (e != hipSuccess) {
@@ -585,8 +606,18 @@ int dg_troubled(dg_handle* h, double* u_dev, int apply, unsigned char* flag_dev,
     if (!u_dev) return fail(h, DG_EINVAL, "NULL state");
     if (h->dev) return fail(h, DG_EUNSUPPORTED, "the limiter runs on the FP64 form");
     DG_HIP(h, dgk::launch_troubled(h->n, h->nvar, h->g, u_dev, h->u0, h->cfg.limiter_s0, 0, apply ? 1 : 0, nullptr,
-                                   flag_dev, changed_dev, sensor_dev, h->s),
+                                   flag_dev, changed_dev, sensor_dev, 0, nullptr, h->s),
            "troubled cells");
+    return DG_OK;
+}
+
+int dg_positivity(dg_handle* h, double* u_dev, unsigned char* changed_dev, double* theta_dev) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    if (!u_dev) return fail(h, DG_EINVAL, "NULL state");
+    if (h->dev) return fail(h, DG_EUNSUPPORTED, "the limiter runs on the FP64 form");
+    DG_HIP(h, dgk::launch_troubled(h->n, h->nvar, h->g, u_dev, nullptr, 0.0, 2, 1, nullptr, nullptr, changed_dev,
+                                   nullptr, 1, theta_dev, h->s),
+           "positivity limiter");
     return DG_OK;
 }
 

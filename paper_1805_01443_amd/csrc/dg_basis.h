@@ -110,4 +110,40 @@ struct Basis {
     static constexpr BasisTab t = make_basis(N);
 };
 
+// Gauss-Lobatto rule of the positivity limiter (Sec. 2.4, after Zhang & Shu):
+// the fewest points L with 2L - 3 >= N_p, closed forms for L = 2..4 (which
+// covers n <= 5); w1h = half the end weight of the rule normalised to sum 1.
+struct LobattoTab {
+    int L;
+    double x[kMaxOrder];
+    double w1h;
+    double phi[kMaxOrder][kMaxOrder];  // phi_a(x_q)
+};
+
+constexpr LobattoTab make_lobatto(int n) {
+    LobattoTab t{};
+    int L = 2;
+    while (2 * L - 3 < n - 1) ++L;
+    t.L = L;
+    if (L == 2) {
+        t.x[0] = -1.0; t.x[1] = 1.0;
+        t.w1h = 0.5 * 0.5;
+    } else if (L == 3) {
+        t.x[0] = -1.0; t.x[1] = 0.0; t.x[2] = 1.0;
+        t.w1h = 0.5 / 6.0;
+    } else {
+        const double a = 1.0 / csqrt(5.0);
+        t.x[0] = -1.0; t.x[1] = -a; t.x[2] = a; t.x[3] = 1.0;
+        t.w1h = 0.5 / 12.0;
+    }
+    for (int a = 0; a < n; ++a)
+        for (int q = 0; q < L; ++q) t.phi[a][q] = csqrt(2.0 * a + 1.0) * cleg(a, t.x[q]);
+    return t;
+}
+
+template <int N>
+struct Lobatto {
+    static constexpr LobattoTab t = make_lobatto(N);
+};
+
 }  // namespace dgk

@@ -41,6 +41,7 @@ struct Geo {
     int damping;
     double rd_in, rd_out, rb_in, rb_out, td_in, td_out;
     double cfl_fac;             // C / (2 N_p + 1)
+    double pp_eps;              // positivity limiter: floor of eps
     double sigma0;              // deviation form: equilibrium Sigma0
 };
 
@@ -127,7 +128,7 @@ int torque_blocks(const Geo& g);
 hipError_t launch_means(int n, int nvar, const Geo& g, const double* u, double* out, hipStream_t s);
 hipError_t launch_troubled(int n, int nvar, const Geo& g, double* u, const double* u0, double s0, int mode, int apply,
                            const unsigned char* flag_in, unsigned char* flag_out, unsigned char* changed_out,
-                           float* sensor_out, hipStream_t s);
+                           float* sensor_out, int pp, double* theta_out, hipStream_t s);
 hipError_t launch_features(int n, int nvar, const Geo& g, const double* u, const double* scale, unsigned short* f,
                            hipStream_t s);
 hipError_t launch_mlp_forward(const unsigned short* x, long long n, const float* par, float* z, float* h1, float* h2,

@@ -169,6 +169,16 @@ __device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const do
 }
 
 // ------------------------------------------------------------------ stage kernel, N lanes per element
+// LDS doubles per element slot: at least `need`, rounded up to N modulo 16 so
+// that lane (s, k) reading entry k of slot s (s * SLOT + k) hits consecutive
+// 8-byte banks across a wavefront, and element-uniform reads of the slots of
+// one 16-lane group fall in distinct banks.
+constexpr int lds_slot(int need, int n) {
+    int s = need;
+    while (s % 16 != n % 16) ++s;
+    return s;
+}
+
 // Lane-dependent entry t[k] of a compile-time table (k < N): a select chain on
 // immediates.
 template <int N>
@@ -206,17 +216,20 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     constexpr BasisTab B = make_basis(N);
     constexpr int P1 = NV * NN + 6 * NV * N;      // C, six collapse vectors
     constexpr int P2 = 2 * NV * NN + 4 * NV * N;  // X, Y, four edge fluxes
-    constexpr int SLOT = P1 > P2 ? P1 : P2;
-    __shared__ double lds[(EW + 1) * SLOT];       // slot EW: lanes beyond EW * N
+    constexpr int SLOT = lds_slot(P1 > P2 ? P1 : P2, N);
+    __shared__ double lds[EW * SLOT];
 
     const int lane = threadIdx.x;
     const int sl = lane / N, k = lane - sl * N;
+    // Lanes beyond EW * N shadow slot 0's element (same i, j and k), so they
+    // compute and store exactly the values of lanes (0, k): they share slot 0.
+    const bool own = EW * N == 64 || sl < EW;
     const int tile = remap_tile(blockIdx.x, tiles_total);
     const int j = tile / tiles_x;
     const int i0 = (tile - j * tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
     const int i = active ? i0 + sl : i0;  // idle lanes shadow a valid element and store nothing
-    double* S = lds + sl * SLOT;
+    double* S = lds + (own ? sl : 0) * SLOT;
 
     const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
     const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), rout = make_rsrc(out), run = make_rsrc(un);

@@ -32,20 +32,137 @@ __device__ __forceinline__ double nb_mean(const Geo& g, const double* __restrict
     return u[tiled_base<N, NV>(g, in, jn) + mode_off<N>(v, 0, 0)];
 }
 
-// mode: 0 = flags from the modal-decay sensor (s > s0), 1 = flags given.
-// apply = 1: limit the flagged elements in place; 0: only report.
-// Outputs (each may be NULL): flag[e], changed[e] (minmod altered a slope),
-// sensor[e] (log10 of the top-degree density energy share).
+// ------------------------------------------------------------------ positivity
+// Positivity-preserving scaling of Zhang & Shu (Sec. 2.4) of one element in
+// place.  Test points: (Lobatto x Gauss) and (Gauss x Lobatto).  Density:
+// theta1 = (mean - eps) / (mean - min) where the minimum falls below eps;
+// pressure (adiabatic only): at each point of the density-limited state w
+// with p(w) < eps, the root t in [0, 1) of p(mean + t (w - mean)) = eps, as
+// the root of 2 rho E - |m|^2 - 2 eps rho / (gamma - 1) (quadratic in t);
+// theta2 = min t.  eps = min(e0, mean density, mean pressure).  Returns
+// whether a mode changed; th1, th2 receive the factors.
+
+// value at test point k of the polynomial with modes c[a * N + b]; points
+// 0 .. L*N-1 are (Lobatto q, Gauss r), the rest (Gauss q, Lobatto r)
+template <int N>
+__device__ __forceinline__ double pp_point(const double (&c)[N * N], int k) {
+    constexpr auto& G = Basis<N>::t;
+    constexpr auto& B = Lobatto<N>::t;
+    constexpr int L = B.L;
+    double s = 0.0;
+    if (k < L * N) {
+        const int q = k / N, r = k % N;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            double cb = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) cb = fma(c[a * N + b], B.phi[a][q], cb);
+            s = fma(cb, G.phi[b][r], s);
+        }
+    } else {
+        const int q = (k - L * N) / L, r = (k - L * N) % L;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            double ca = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) ca = fma(c[a * N + b], B.phi[b][r], ca);
+            s = fma(ca, G.phi[a][q], s);
+        }
+    }
+    return s;
+}
+
 template <int N, int NV>
+__device__ bool pp_scale(double* u, unsigned base, bool adiabatic, double gm1, double e0, double& th1, double& th2) {
+    constexpr int NN = N * N;
+    constexpr int NP = 2 * Lobatto<N>::t.L * N;
+    th1 = 1.0;
+    th2 = 1.0;
+    double m[NV][NN];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) m[v][a * N + b] = u[base + mode_off<N>(v, a, b)];
+    const double r0 = m[0][0];
+    double pbar = r0;
+    if (NV == 4 && adiabatic) pbar = gm1 * (m[3][0] - 0.5 * (m[1][0] * m[1][0] + m[2][0] * m[2][0]) / r0);
+    if (!(r0 > 0.0) || !(pbar > 0.0)) return false;
+    double eps = e0;
+    if (r0 < eps) eps = r0;
+    if (NV == 4 && adiabatic && pbar < eps) eps = pbar;
+    double rmin = INFINITY;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) rmin = fmin(rmin, pp_point<N>(m[0], k));
+    bool changed = false;
+    if (rmin < eps) {
+        th1 = (r0 - eps) / (r0 - rmin);
+#pragma unroll
+        for (int x = 1; x < NN; ++x) m[0][x] *= th1;
+        changed = true;
+    }
+    if constexpr (NV == 4) {
+        if (adiabatic) {
+            const double ge = 2.0 * eps / gm1;
+            const double C0 = 2.0 * r0 * m[3][0] - m[1][0] * m[1][0] - m[2][0] * m[2][0] - ge * r0;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                double W[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) W[v] = pp_point<N>(m[v], k);
+                const double pw = gm1 * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+                if (!(pw < eps)) continue;
+                double d[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) d[v] = W[v] - m[v][0];
+                const double A = 2.0 * d[0] * d[3] - d[1] * d[1] - d[2] * d[2];
+                const double B = 2.0 * (r0 * d[3] + m[3][0] * d[0]) - 2.0 * (m[1][0] * d[1] + m[2][0] * d[2]) - ge * d[0];
+                double t = 2.0 * C0 / (-B + sqrt(B * B - 4.0 * A * C0));
+                if (!(t >= 0.0)) t = 0.0;
+                if (t > 1.0) t = 1.0;
+                th2 = fmin(th2, t);
+            }
+            if (th2 < 1.0) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int x = 1; x < NN; ++x) m[v][x] *= th2;
+                changed = true;
+            }
+        }
+    }
+    if (changed) {
+        const int v0 = th2 < 1.0 ? NV : 1;  // variables whose modes changed
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (v >= v0) break;
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+                    if (a + b > 0) u[base + mode_off<N>(v, a, b)] = m[v][a * N + b];
+        }
+    }
+    return changed;
+}
+
+// mode: 0 = flags from the modal-decay sensor (s > s0), 1 = flags given,
+// 2 = no flags (the positivity scaling alone).  apply = 1: limit the flagged
+// elements in place; 0: only report.  PP (with apply): then the positivity
+// scaling on every element.  Outputs (each may be NULL): flag[e],
+// changed[e] (a mode changed), sensor[e] (log10 of the top-degree density
+// energy share), theta[2e], theta[2e+1] (the positivity factors).
+template <int N, int NV, bool PP>
 __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const double* __restrict__ u0, double s0,
                                                   int mode, int apply, const unsigned char* __restrict__ flag_in,
                                                   unsigned char* flag_out, unsigned char* changed_out,
-                                                  float* sensor_out) {
+                                                  float* sensor_out, double* theta_out) {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= g.E) return;
     const int i = (int)(e % g.nx), j = (int)(e / g.nx);
     const unsigned base = tiled_base<N, NV>(g, i, j);
-    bool flag;
+    bool flag = false;
     if (mode == 0) {
         double top = 0.0, all = 0.0;
 #pragma unroll
@@ -59,7 +176,7 @@ __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const 
         const double s = (all > 0.0 && top > 0.0) ? log10(top / all) : -300.0;
         flag = s > s0;
         if (sensor_out) sensor_out[e] = (float)s;
-    } else {
+    } else if (mode == 1) {
         flag = flag_in[e] != 0;
     }
     if (flag_out) flag_out[e] = flag ? 1 : 0;
@@ -90,6 +207,14 @@ __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const 
                         if (a == 0 && b == 0) continue;
                         u[base + mode_off<N>(v, a, b)] = (a == 1 && b == 0) ? sx[v] / r3 : (a == 0 && b == 1) ? sy[v] / r3 : 0.0;
                     }
+        }
+    }
+    if (PP && apply) {
+        double t1, t2;
+        if (pp_scale<N, NV>(u, base, g.closure == 2, g.gamma - 1.0, g.pp_eps, t1, t2)) changed = true;
+        if (theta_out) {
+            theta_out[2 * e] = t1;
+            theta_out[2 * e + 1] = t2;
         }
     }
     if (changed_out) changed_out[e] = changed ? 1 : 0;
@@ -441,10 +566,15 @@ __global__ void __launch_bounds__(256) k_mlp_adam(const float* __restrict__ grad
 
 hipError_t launch_troubled(int n, int nvar, const Geo& g, double* u, const double* u0, double s0, int mode, int apply,
                            const unsigned char* flag_in, unsigned char* flag_out, unsigned char* changed_out,
-                           float* sensor_out, hipStream_t s) {
+                           float* sensor_out, int pp, double* theta_out, hipStream_t s) {
     const int blocks = (int)((g.E + 255) / 256);
-    DGL_DISPATCH(n, nvar, hipLaunchKernelGGL((k_troubled<NT, VT>), dim3(blocks), dim3(256), 0, s, g, u, u0, s0, mode,
-                                             apply, flag_in, flag_out, changed_out, sensor_out));
+    if (pp) {
+        DGL_DISPATCH(n, nvar, hipLaunchKernelGGL((k_troubled<NT, VT, true>), dim3(blocks), dim3(256), 0, s, g, u, u0, s0,
+                                                 mode, apply, flag_in, flag_out, changed_out, sensor_out, theta_out));
+    } else {
+        DGL_DISPATCH(n, nvar, hipLaunchKernelGGL((k_troubled<NT, VT, false>), dim3(blocks), dim3(256), 0, s, g, u, u0,
+                                                 s0, mode, apply, flag_in, flag_out, changed_out, sensor_out, theta_out));
+    }
     return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ class dg_config(C.Structure):
         ("q", C.c_double), ("eps", C.c_double), ("rp", C.c_double), ("phi0", C.c_double),
         ("damping", C.c_int), ("rd_in", C.c_double), ("rd_out", C.c_double),
         ("cfl", C.c_double), ("precision", C.c_int), ("sigma0", C.c_double), ("limiter", C.c_int),
-        ("limiter_s0", C.c_double), ("mlp_theta", C.c_double), ("rk", C.c_int),
+        ("limiter_s0", C.c_double), ("mlp_theta", C.c_double), ("rk", C.c_int), ("positivity", C.c_int),
+        ("pp_eps", C.c_double),
     ]
 
 
@@ -76,6 +77,8 @@ class Config:
     limiter_s0: float = 0.0
     mlp_theta: float = 0.5
     rk: int = RK_SSP33
+    positivity: int = 0
+    pp_eps: float = 0.0
 
     @property
     def n(self):
@@ -134,6 +137,7 @@ def lib():
         L.dg_profile_begin.argtypes = [vp]
         L.dg_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.dg_troubled.argtypes = [vp, vp, C.c_int, vp, vp, vp]
+        L.dg_positivity.argtypes = [vp, vp, vp, vp]
         L.dg_mlp_feature_scales.argtypes = [vp, dp]
         L.dg_mlp_features.argtypes = [vp, vp, vp]
         L.dg_mlp_params.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
@@ -143,7 +147,7 @@ def lib():
         L.dg_last_error.argtypes = [vp]
         L.dg_last_error.restype = C.c_char_p
         for name in ("dg_get_nodes", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
-                     "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled",
+                     "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled", "dg_positivity",
                      "dg_mlp_feature_scales", "dg_mlp_features", "dg_mlp_params", "dg_mlp_forward",
                      "dg_mlp_train_step", "dg_capture"):
             getattr(L, name).restype = C.c_int
@@ -152,7 +156,7 @@ def lib():
 
 
 EXPORTS = ("dg_get_nodes", "dg_state_size", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
-           "dg_last_error", "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled",
+           "dg_last_error", "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled", "dg_positivity",
            "dg_mlp_feature_scales", "dg_mlp_features", "dg_mlp_params", "dg_mlp_forward", "dg_mlp_train_step",
            "dg_capture")
 MLP_NPARAM = 3169
@@ -280,6 +284,11 @@ def dg_full_state(h: Handle, dev, full):
 
 def dg_troubled(h: Handle, u, apply=False, flags=None, changed=None, sensor=None):
     _check(lib().dg_troubled(h.ptr, _ptr(u), int(bool(apply)), _ptr(flags), _ptr(changed), _ptr(sensor)), h.ptr)
+
+
+def dg_positivity(h: Handle, u, changed=None, theta=None):
+    """positivity limiter in place; changed: uint8 [E], theta: float64 [E, 2] (device)"""
+    _check(lib().dg_positivity(h.ptr, _ptr(u), _ptr(changed), _ptr(theta)), h.ptr)
 
 
 def dg_mlp_feature_scales(h: Handle):

@@ -113,6 +113,18 @@ def disc_ring(x, y, gm=1.0, h=0.05, r_core=0.4, sigma0=1.0, r_ring=1.6,
     return sigma, vx, vy, p
 
 
+def double_rarefaction(x, y, speed=2.0, rho=1.0, p=0.4, split=0.5, band=0.02):
+    """(rho, vx, vy, p): uniform gas with vx = -speed for x mod 1 < split and
+    +speed above (two gases receding from x = split, colliding at x = 0 mod 1),
+    vx = 0 within ``band`` of the collision line; the receding gases open a
+    near-vacuum (a strong test of positivity)."""
+    xm = np.mod(x, 1.0)
+    vx = np.where(xm < split, -speed, speed)
+    vx = np.where((xm < band) | (xm > 1.0 - band), 0.0, vx)
+    one = np.ones_like(xm)
+    return rho * one, vx, 0.0 * one, p * one
+
+
 def ring_radius(seed):
     """r_ring ~ U[1.4, 1.9] from the seed (index 2**62 + 1 is reserved for it)."""
     return 1.4 + 0.5 * float(uniform01(seed, (np.uint64(1) << np.uint64(62)) + np.uint64(1)))

@@ -1,0 +1,192 @@
+"""GPU parity of the positivity-preserving limiter (Sec. 2.4) against the
+oracle: the scaling factors and the limited state to 1e-12, the changed-element
+decisions exactly, the projected-and-limited initial state, and limited steps
+(alone and after the minmod limiter) including the restricted CFL step."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1805_01443_amd import configs as W
+from paper_1805_01443_amd import dg
+
+pytestmark = pytest.mark.gpu
+
+
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+def ocfg(cfg):
+    return O.cfg(dataclasses.asdict(cfg))
+
+
+def planes(cfg, u):
+    return dg.to_planes(cfg, u.detach().cpu().numpy())
+
+
+def relerr(a, b):
+    """per variable, relative to its max-norm floored at 1e-3 of the largest
+    variable's (the rarefaction's y momentum is zero up to round-off)"""
+    sc = max(np.max(np.abs(b[w])) for w in range(len(b)))
+    return max(np.max(np.abs(a[v] - b[v])) / max(np.max(np.abs(b[v])), 1e-3 * sc) for v in range(len(b)))
+
+
+def wild_state(cfg, seed, amp):
+    """admissible means, higher modes of amplitude amp on a checkerboard of
+    elements and amp / 50 on the others, [var][mode][E]"""
+    rng = np.random.default_rng(seed)
+    E, nn = cfg.n_elem, cfg.order ** 2
+    i = np.arange(E) % cfg.nx
+    j = np.arange(E) // cfg.nx
+    a = np.where((i + j) % 2 == 0, amp, amp / 50)
+    u = rng.uniform(-1, 1, (cfg.nvar, nn, E)) * a
+    means = [1.0, 0.1, -0.2, 2.5][:cfg.nvar]
+    u[:, 0, :] = np.array(means)[:, None] * (1.0 + 0.1 * rng.uniform(-1, 1, (cfg.nvar, E)))
+    return u
+
+
+@pytest.mark.parametrize("order,nvar", [(2, 4), (3, 4), (4, 4), (5, 4), (3, 3), (5, 3)])
+def test_positivity_kernel_against_oracle(order, nvar):
+    T = torch()
+    if nvar == 4:
+        cfg = W.rarefaction(nx=13, ny=11, order=order)
+    else:
+        cfg = W.wave(nx=13, order=order).replace(ny=11, positivity=1)
+    oc = ocfg(cfg)
+    prim = W.prim_for(cfg, "rarefaction" if nvar == 4 else "wave", x=O.nodes(oc)[0], y=O.nodes(oc)[1])
+    h, _ = dg.dg_init(cfg, prim)
+    u = wild_state(cfg, seed=order * 10 + nvar, amp=0.5)
+    ug = dg.from_planes(cfg, u)
+    E = cfg.n_elem
+    ch = T.zeros(E, dtype=T.uint8, device="cuda")
+    th = T.zeros((E, 2), dtype=T.float64, device="cuda")
+    dg.dg_positivity(h, ug, changed=ch, theta=th)
+    T.cuda.synchronize()
+    uo, cho, tho = O.positivity(oc, u)
+    print(f"[positivity] order {order} nvar {nvar}: {int(cho.sum())} of {E} limited", flush=True)
+    assert 0 < cho.sum() < E
+    assert np.array_equal(ch.cpu().numpy().astype(bool), cho)
+    assert np.max(np.abs(th.cpu().numpy() - tho)) <= 1e-13
+    assert relerr(planes(cfg, ug), uo) <= 1e-12
+    # means bitwise
+    assert np.array_equal(planes(cfg, ug)[:, 0], u[:, 0])
+    h.close()
+
+
+def test_init_limits_the_projection_and_steps_match():
+    """double rarefaction: dg_init's output is the oracle's projection after
+    the positivity limiter; then CFL-limited steps (restricted factor) match
+    the oracle's limited steps, dt included.  With Zhang & Shu's eps = 1e-13
+    the limited states carry point densities or pressures of 1e-13 computed
+    from O(1) modes, and the next stages amplify round-off without bound
+    (the oracle against itself with a 1e-15 perturbation differs by 3e-4
+    after 7 steps); with an eps floor of 1e-6 that sensitivity stays at
+    5e-13, so this parity test takes pp_eps = 1e-6."""
+    T = torch()
+    cfg = W.rarefaction(nx=32, ny=3, order=3).replace(pp_eps=1e-6)
+    oc = ocfg(cfg)
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, "rarefaction", x=x, y=y)
+    h, u = dg.dg_init(cfg, prim)
+    T.cuda.synchronize()
+    uo, ch, _ = O.positivity(oc, O.project(oc, prim))
+    assert ch.any()
+    assert relerr(planes(cfg, u), uo) <= 1e-13
+    u0 = uo.copy()
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    t = 0.0
+    for k in range(30):
+        dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
+        uo, dto = O.step_limited(oc, uo, t, 0.0, u0, math.inf)
+        t += dto
+        if k % 10 == 9:
+            dg.dg_sync(h)
+            err = relerr(planes(cfg, u), uo)
+            print(f"[positivity steps] step {k}: rel err {err:.3e}, dt {dt_dev.item():.6e} vs {dto:.6e}", flush=True)
+            assert abs(dt_dev.item() - dto) <= 1e-13 * dto
+            assert err <= 1e-12
+    assert abs(t_dev.item() - t) <= 1e-13 * t
+    assert uo[0, 0].min() < 0.3  # the near-vacuum is opening
+    h.close()
+
+
+def test_minmod_then_positivity_steps_match():
+    """the ring with a density jump: the modal-decay indicator + minmod, then
+    the positivity scaling, at every stage (fixed dt)"""
+    T = torch()
+    cfg = W.disc_ring(nx=40, order=4).replace(limiter=dg.LIMITER_MODAL_DECAY, limiter_s0=-3.0, positivity=1)
+    oc = ocfg(cfg)
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, "disc_ring", x=x, y=y)
+    r = np.sqrt(x ** 2 + y ** 2).reshape(cfg.n_elem, 16)
+    prim[0] *= np.where(r < 1.6, 2.0, 1.0)
+    prim[3] *= np.where(r < 1.6, 2.0, 1.0)
+    h, u = dg.dg_init(cfg, prim)
+    uo, _, _ = O.positivity(oc, O.project(oc, prim))
+    u0 = uo.copy()
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    t = 0.0
+    for k in range(3):
+        dg.dg_rk_step(h, u, t_dev, 1e-3, None)
+        uo, _ = O.step_limited(oc, uo, t, 1e-3, u0, cfg.limiter_s0)
+        t += 1e-3
+        dg.dg_sync(h)
+        err = relerr(planes(cfg, u), uo)
+        print(f"[minmod + positivity step {k}] rel err {err:.3e}", flush=True)
+        assert err <= 1e-12
+    h.close()
+
+
+def test_configuration_checks():
+    cfg = W.rarefaction()
+    prim = W.prim_for(cfg, "rarefaction")
+    for bad in (cfg.replace(positivity=2), cfg.replace(rk=dg.RK_SSP22)):
+        with pytest.raises(dg.DGError):
+            dg.dg_init(bad, prim)
+
+
+def test_default_eps_run_stays_admissible():
+    """Zhang & Shu's eps = 1e-13, 150 CFL steps of the double rarefaction on
+    the GPU: every element mean stays admissible and every test point keeps
+    density and pressure >= 0 up to round-off (the limiter's guarantee; a
+    property of any size, independent of the round-off sensitivity above)."""
+    from numpy.polynomial import legendre as npleg
+    T = torch()
+    cfg = W.rarefaction(nx=64, ny=2, order=4)
+    prim = W.prim_for(cfg, "rarefaction")
+    h, u = dg.dg_init(cfg, prim)
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    for _ in range(150):
+        dg.dg_rk_step(h, u, t_dev, 0.0, None)
+    dg.dg_sync(h)
+    a = planes(cfg, u)
+    assert np.all(np.isfinite(a))
+    n = cfg.order
+    L = O.pp_lobatto_points(n - 1)
+    xg = npleg.leggauss(n)[0]
+    xl = O.gauss_lobatto(L)[0]
+    sc = np.sqrt(2 * np.arange(n) + 1.0)
+    P = lambda xs: np.stack([npleg.legval(xs, np.eye(n)[m]) * sc[m] for m in range(n)])  # [mode][point]
+    pts = [(P(xl), P(xg)), (P(xg), P(xl))]
+    rmin = pmin = np.inf
+    for px, py in pts:
+        # value[v][e][p, q] = sum_ab u[v][a*n+b][e] phi_a(x_p) phi_b(y_q)
+        w = np.einsum("vabe,ap,bq->vepq", a.reshape(4, n, n, -1), px, py)
+        rmin = min(rmin, w[0].min())
+        pmin = min(pmin, (0.4 * (w[3] - 0.5 * (w[1] ** 2 + w[2] ** 2) / w[0])).min())
+    means = a[:, 0]
+    pm = 0.4 * (means[3] - 0.5 * (means[1] ** 2 + means[2] ** 2) / means[0])
+    print(f"[positivity eps 1e-13] t = {t_dev.item():.4f}: mean rho >= {means[0].min():.3e}, "
+          f"mean p >= {pm.min():.3e}, point rho >= {rmin:.3e}, point p >= {pmin:.3e}", flush=True)
+    assert means[0].min() > 0 and pm.min() > 0
+    # the pinned points sit at eps = 1e-13; evaluating them again from O(1)
+    # modes carries ~1e-15 of round-off
+    assert rmin >= -1e-12 and pmin >= -1e-12
+    assert means[0].min() < 0.1  # the near-vacuum did open
+    h.close()
