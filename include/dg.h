@@ -170,14 +170,14 @@ int dg_troubled(dg_handle *h, double *u_dev, int apply, unsigned char *flag_dev,
  * cfg->pp_eps (1e-13 when <= 0).
  * The density's non-mean modes are scaled by theta1 = (mean - eps) / (mean -
  * min) where its minimum over the points is below eps; then (adiabatic closure
- * only) every variable's non-mean modes by theta2, the smallest t in [0, 1]
- * with p(mean + t (w - mean)) = eps over the points w whose pressure is below
- * eps.  Means never change; elements whose means are not admissible are left
+ * only) every variable's non-mean modes by theta2, the smallest over the
+ * points w whose pressure is below eps of the largest t in [0, 1] with
+ * p(mean + t (w - mean)) >= eps (bisection, keeping the admissible end).  Means never change; elements whose means are not admissible are left
  * alone.  Outputs (device, may be NULL): changed_dev[e] (E bytes) = 1 where a
  * mode changed, theta_dev[2e], theta_dev[2e+1] (2E doubles) = theta1, theta2.
  * With cfg->positivity = 1 (SSP(3,3), FP64 form), dg_init limits the projected
  * initial state, dg_rk_step limits every stage state after the minmod limiter
- * (if any), and the CFL factor C/(2N_p+1) becomes C min(1/(2N_p+1), w_1/2),
+ * (if any) and the damped state after the damping, and the CFL factor C/(2N_p+1) becomes C min(1/(2N_p+1), w_1/2),
  * w_1 the end weight of the Lobatto rule normalised to sum 1. */
 int dg_positivity(dg_handle *h, double *u_dev, unsigned char *changed_dev, double *theta_dev);
 /* Feature scales s_v (RMS of the initial element means of variable v), host

@@ -121,8 +121,9 @@ void or_minmod(const or_cfg *c, double *u, const double *u0, const unsigned char
  *   density:  theta1 = min(1, (mean - eps) / (mean - min over the points)),
  *             the density's non-mean modes scaled by theta1;
  *   pressure (adiabatic closure only): at every point where the
- *             pressure of (density-limited) state w is below eps, t solves
- *             p(mean + t (w - mean)) = eps on [0, 1); theta2 = min of those t
+ *             pressure of (density-limited) state w is below eps, the largest
+ *             t in [0, 1] with p(mean + t (w - mean)) >= eps (64 bisection
+ *             steps, keeping the admissible end); theta2 = min of those t
  *             (1 if none); every variable's non-mean modes scaled by theta2.
  * The isothermal closures have p proportional to the density, so the density
  * step covers them.  Elements whose means are not admissible (mean density
@@ -131,7 +132,8 @@ void or_minmod(const or_cfg *c, double *u, const double *u0, const unsigned char
 void or_positivity(const or_cfg *c, double *u, unsigned char *changed, double *theta);
 /* one SSP-RK3 step in Shu-Osher form with the limiter after every stage:
  * the minmod limiter on the elements with indicator > s0 (s0 = +inf: none),
- * then, if c->positivity, or_positivity; returns dt (with c->positivity the
+ * then, if c->positivity, or_positivity; then the damping (if configured),
+ * followed by or_positivity once more; returns dt (with c->positivity the
  * CFL factor is C min(1/(2N_p+1), w_1/2), see or_dt) */
 double or_step_limited(const or_cfg *c, double *u, double t, double dt_fixed, const double *u0,
                        double s0);

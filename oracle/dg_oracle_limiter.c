@@ -166,19 +166,21 @@ void or_positivity(const or_cfg *c, double *u, unsigned char *changed, double *t
                 double W[4];
                 for (int v = 0; v < 4; ++v) W[v] = point_value(c, u, e, v, px[k2], py[k2]);
                 if (!(pressure_of(c, W) < eps)) continue;
-                /* p(M + t (W - M)) = eps, times 2 rho(t) / (gamma - 1):
-                 * 2 rho(t) E(t) - |m(t)|^2 - 2 eps rho(t) / (gamma - 1) = A t^2 + B t + C,
-                 * C > 0 at t = 0 and < 0 at t = 1; the root in (0, 1) */
-                double d[4];
-                for (int v = 0; v < 4; ++v) d[v] = W[v] - M[v];
-                double ge = 2.0 * eps / (c->gamma - 1.0);
-                double A = 2.0 * d[0] * d[3] - d[1] * d[1] - d[2] * d[2];
-                double B = 2.0 * (M[0] * d[3] + M[3] * d[0]) - 2.0 * (M[1] * d[1] + M[2] * d[2]) - ge * d[0];
-                double C0 = 2.0 * M[0] * M[3] - M[1] * M[1] - M[2] * M[2] - ge * M[0];
-                double t = 2.0 * C0 / (-B + sqrt(B * B - 4.0 * A * C0));
-                if (!(t >= 0.0)) t = 0.0;
-                if (t > 1.0) t = 1.0;
-                if (t < th2) th2 = t;
+                /* p(M + t (W - M)) is concave in t, >= eps at 0 and < eps at 1:
+                 * the admissible t form [0, t*].  Bisection, keeping the
+                 * admissible end (the closed-form root of the equivalent
+                 * quadratic loses digits near a double root, and a point
+                 * left at p < 0 breaks the sound speed) */
+                double lo = 0.0, hi = 1.0;
+                for (int it = 0; it < 64; ++it) {
+                    double mid = 0.5 * (lo + hi), S[4];
+                    for (int v = 0; v < 4; ++v) S[v] = M[v] + mid * (W[v] - M[v]);
+                    if (pressure_of(c, S) >= eps)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                if (lo < th2) th2 = lo;
             }
             if (th2 < 1.0)
                 for (int v = 0; v < nv; ++v)
@@ -226,7 +228,15 @@ double or_step_limited(const or_cfg *c, double *u, double t, double dt_fixed, co
     or_rhs(c, t + 0.5 * dt, u2, u0, k);
     for (long x = 0; x < N; ++x) u[x] = u[x] / 3.0 + 2.0 / 3.0 * (u2[x] + dt * k[x]);
     limit_state(c, u, u0, s0);
-    if (c->damping) or_damp(c, u, u0, dt);
+    if (c->damping) {
+        or_damp(c, u, u0, dt);
+        /* the damping changes the state once more: positivity again */
+        if (c->positivity) {
+            unsigned char *ch = (unsigned char *)malloc((size_t)c->nx * c->ny);
+            or_positivity(c, u, ch, NULL);
+            free(ch);
+        }
+    }
     free(k);
     free(u1);
     free(u2);

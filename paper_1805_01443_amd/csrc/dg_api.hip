@@ -586,9 +586,15 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     DG_HIP(h, limit(h, h->ws2, false), "limiter");
     DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2]), "stage 3");
     DG_HIP(h, limit(h, u_dev, true), "limiter");
-    if (h->cfg.damping)
+    if (h->cfg.damping) {
         DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
                "damping");
+        // the damped state gets the positivity scaling too
+        if (h->cfg.positivity)
+            DG_HIP(h, dgk::launch_troubled(h->n, h->nvar, h->g, u_dev, nullptr, 0.0, 2, 1, nullptr, nullptr, nullptr,
+                                           nullptr, 1, nullptr, h->s),
+                   "positivity after damping");
+    }
     return DG_OK;
 }
 

@@ -169,13 +169,13 @@ __device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const do
 }
 
 // ------------------------------------------------------------------ stage kernel, N lanes per element
-// LDS doubles per element slot: at least `need`, rounded up to N modulo 16 so
-// that lane (s, k) reading entry k of slot s (s * SLOT + k) hits consecutive
-// 8-byte banks across a wavefront, and element-uniform reads of the slots of
-// one 16-lane group fall in distinct banks.
-constexpr int lds_slot(int need, int n) {
+// LDS entries per element slot: at least `need`, rounded up to N modulo m
+// (16 for doubles, 32 for floats) so that lane (s, k) reading entry k of slot
+// s (s * SLOT + k) hits consecutive banks across a wavefront, and
+// element-uniform reads of the slots of one lane group fall in distinct banks.
+constexpr int lds_slot(int need, int n, int m = 16) {
     int s = need;
-    while (s % 16 != n % 16) ++s;
+    while (s % m != n % m) ++s;
     return s;
 }
 
@@ -200,9 +200,10 @@ __device__ __forceinline__ double pick(const double (&t)[kMaxOrder], int k) {
 //            physical flux and source, partial projections
 //            X[r][a] = sum_q w_q (2/dx phi_a'(q) f_x + phi_a(q) s),
 //            Y[r][a] = sum_q w_q phi_a(q) (2/dy) f_y; traces at point k of the
-//            four edges and their Rusanov fluxes;
+//            four edges and their Rusanov fluxes; the west/east lifts, which
+//            carry the same weight w_r phi_b(eta_r) in R, are folded into X;
 //   phase 3, k = mode row a: R[a][b] = sum_r w_r (phi_b(r) X[r][a] + phi_b'(r)
-//            Y[r][a]) minus the edge lifts; stage combination of row a.
+//            Y[r][a]) minus the south/north lifts; stage combination of row a.
 // Every integral is the same Gauss sum as in eq. (3); the density volume term
 // is taken by quadrature (exact for its polynomial integrand).
 template <int N, int CL>
@@ -215,7 +216,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     constexpr int EW = 64 / N;
     constexpr BasisTab B = make_basis(N);
     constexpr int P1 = NV * NN + 6 * NV * N;      // C, six collapse vectors
-    constexpr int P2 = 2 * NV * NN + 4 * NV * N;  // X, Y, four edge fluxes
+    constexpr int P2 = 2 * NV * NN + 2 * NV * N;  // X (with the west/east lifts), Y, south/north fluxes
     constexpr int SLOT = lds_slot(P1 > P2 ? P1 : P2, N);
     __shared__ double lds[EW * SLOT];
 
@@ -391,7 +392,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             const double fxx = g.rdx2 * fx[v], fyy = g.rdy2 * fy[v];
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                X[v][a] += B.wdphi[a][q] * fxx + B.wphi[a][q] * sy[v];
+                // the density equation has no source term
+                X[v][a] += v == 0 ? B.wdphi[a][q] * fxx : B.wdphi[a][q] * fxx + B.wphi[a][q] * sy[v];
                 Y[v][a] += B.wphi[a][q] * fyy;
             }
         }
@@ -426,6 +428,14 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             Uo[v] = so;
         }
         rusanov<CL, 0, 1>(g, Ui, Uo, xc + 0.5 * g.dx, yk, hf[1]);
+        // west/east lifts of row r enter R[a][b] with the same weight
+        // w_r phi_b(eta_r) as X[r][a]: X[r][a] -= (1/dx)(phi_a(-1) h_W + phi_a(1) h_E)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double hp = g.idx * (hf[1][v] + hf[0][v]), hm = g.idx * (hf[1][v] - hf[0][v]);
+#pragma unroll
+            for (int a = 0; a < N; ++a) X[v][a] -= B.pp[a] * ((a & 1) ? hm : hp);
+        }
         const double xk = xc + 0.5 * g.dx * xik;
         // south / north: own and exterior traces from the y collapses
 #pragma unroll
@@ -462,9 +472,9 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             S[((1 * NV + v) * N + k) * N + a] = Y[v][a];
         }
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < 2; ++f)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) S[2 * NV * NN + (f * NV + v) * N + k] = hf[f][v];
+        for (int v = 0; v < NV; ++v) S[2 * NV * NN + (f * NV + v) * N + k] = hf[2 + f][v];
     __syncthreads();
 
     // ---- phase 3: k = mode row a
@@ -476,7 +486,6 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         for (int m = 1; m < N; ++m) r = k == m ? B.wphi[m][q] : r;
         wrow[q] = r;
     }
-    const double pmk = pick<N>(B.pm, k), ppk = pick<N>(B.pp, k);
     const double* H = S + 2 * NV * NN;
     // the row's u and u^n, issued before any store (out may alias u^n, so a
     // load after a store could not be moved ahead of it); u comes back from L2
@@ -497,25 +506,15 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         double glb = 0.0, glt = 0.0;
 #pragma unroll
         for (int q = 0; q < N; ++q) {
-            glb += wrow[q] * H[(2 * NV + v) * N + q];
-            glt += wrow[q] * H[(3 * NV + v) * N + q];
-        }
-        double hw[N], he[N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            hw[r] = H[(0 * NV + v) * N + r];
-            he[r] = H[(1 * NV + v) * N + r];
+            glb += wrow[q] * H[(0 * NV + v) * N + q];
+            glt += wrow[q] * H[(1 * NV + v) * N + q];
         }
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            double acc = 0.0, glw = 0.0, gle = 0.0;
+            double acc = 0.0;
 #pragma unroll
-            for (int r = 0; r < N; ++r) {
+            for (int r = 0; r < N; ++r)
                 acc += B.wphi[b][r] * S[((0 * NV + v) * N + r) * N + k] + B.wdphi[b][r] * S[((1 * NV + v) * N + r) * N + k];
-                glw += B.wphi[b][r] * hw[r];
-                gle += B.wphi[b][r] * he[r];
-            }
-            acc -= g.idx * (pmk * glw + ppk * gle);
             acc -= g.idy * (B.pm[b] * glb + B.pp[b] * glt);
             R[v][b] = acc;
         }
@@ -649,18 +648,20 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     constexpr int EW = 64 / N;
     constexpr BasisTab B = make_basis(N);
     constexpr int P1 = NV * NN + 6 * NV * N;
-    constexpr int P2 = 2 * NV * NN + 4 * NV * N;
-    constexpr int SLOT = P1 > P2 ? P1 : P2;
-    __shared__ float lds[(EW + 1) * SLOT];
+    constexpr int P2 = 2 * NV * NN + 2 * NV * N;
+    constexpr int SLOT = lds_slot(P1 > P2 ? P1 : P2, N, 32);
+    __shared__ float lds[EW * SLOT];
 
     const int lane = threadIdx.x;
     const int sl = lane / N, k = lane - sl * N;
+    // lanes beyond EW * N shadow slot 0's element and share its slot
+    const bool own = EW * N == 64 || sl < EW;
     const int tile = remap_tile(blockIdx.x, tiles_total);
     const int j = tile / tiles_x;
     const int i0 = (tile - j * tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
     const int i = active ? i0 + sl : i0;
-    float* S = lds + sl * SLOT;
+    float* S = lds + (own ? sl : 0) * SLOT;
 
     const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
     const rsrc_t rdu = make_rsrc(du), rdu0 = make_rsrc(du0), rout = make_rsrc(out), rdun = make_rsrc(dun),
@@ -774,7 +775,9 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
             const float fxx = rdx2 * fx[v], fyy = rdy2 * fy[v];
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                X[v][a] += (float)B.wdphi[a][q] * fxx + (float)B.wphi[a][q] * sy[v];
+                // the density equation has no source term
+                X[v][a] += v == 0 ? (float)B.wdphi[a][q] * fxx
+                                  : (float)B.wdphi[a][q] * fxx + (float)B.wphi[a][q] * sy[v];
                 Y[v][a] += (float)B.wphi[a][q] * fyy;
             }
         }
@@ -807,6 +810,14 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
             dd[v] = so;
         }
         rusanov_dev<0, 1>(eq_at(g, xc + 0.5 * g.dx, yk), di, dd, hf[1]);
+        // west/east lifts folded into X (same weight w_r phi_b(eta_r) in R)
+        const float idx = (float)g.idx;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const float hp = idx * (hf[1][v] + hf[0][v]), hm = idx * (hf[1][v] - hf[0][v]);
+#pragma unroll
+            for (int a = 0; a < N; ++a) X[v][a] -= (float)B.pp[a] * ((a & 1) ? hm : hp);
+        }
         const double xk = xc + 0.5 * g.dx * xik;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -842,9 +853,9 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
             S[((1 * NV + v) * N + k) * N + a] = Y[v][a];
         }
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < 2; ++f)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) S[2 * NV * NN + (f * NV + v) * N + k] = hf[f][v];
+        for (int v = 0; v < NV; ++v) S[2 * NV * NN + (f * NV + v) * N + k] = hf[2 + f][v];
     __syncthreads();
 
     // ---- phase 3: k = mode row a
@@ -856,8 +867,7 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
         for (int m = 1; m < N; ++m) r = k == m ? B.wphi[m][q] : r;
         wrow[q] = (float)r;
     }
-    const float pmk = (float)pick<N>(B.pm, k), ppk = (float)pick<N>(B.pp, k);
-    const float idx = (float)g.idx, idy = (float)g.idy;
+    const float idy = (float)g.idy;
     const float* H = S + 2 * NV * NN;
     const unsigned vrow4 = (eb + k * EW) * 4u;
     // L_eq, du and du^n of the row, issued before any store (out may alias du^n)
@@ -882,26 +892,16 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
         float glb = 0.0f, glt = 0.0f;
 #pragma unroll
         for (int q = 0; q < N; ++q) {
-            glb += wrow[q] * H[(2 * NV + v) * N + q];
-            glt += wrow[q] * H[(3 * NV + v) * N + q];
-        }
-        float hw[N], he[N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            hw[r] = H[(0 * NV + v) * N + r];
-            he[r] = H[(1 * NV + v) * N + r];
+            glb += wrow[q] * H[(0 * NV + v) * N + q];
+            glt += wrow[q] * H[(1 * NV + v) * N + q];
         }
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            float acc = 0.0f, glw = 0.0f, gle = 0.0f;
+            float acc = 0.0f;
 #pragma unroll
-            for (int r = 0; r < N; ++r) {
+            for (int r = 0; r < N; ++r)
                 acc += (float)B.wphi[b][r] * S[((0 * NV + v) * N + r) * N + k] +
                        (float)B.wdphi[b][r] * S[((1 * NV + v) * N + r) * N + k];
-                glw += (float)B.wphi[b][r] * hw[r];
-                gle += (float)B.wphi[b][r] * he[r];
-            }
-            acc -= idx * (pmk * glw + ppk * gle);
             acc -= idy * ((float)B.pm[b] * glb + (float)B.pp[b] * glt);
             R[v][b] = acc;
         }

@@ -37,9 +37,10 @@ __device__ __forceinline__ double nb_mean(const Geo& g, const double* __restrict
 // place.  Test points: (Lobatto x Gauss) and (Gauss x Lobatto).  Density:
 // theta1 = (mean - eps) / (mean - min) where the minimum falls below eps;
 // pressure (adiabatic only): at each point of the density-limited state w
-// with p(w) < eps, the root t in [0, 1) of p(mean + t (w - mean)) = eps, as
-// the root of 2 rho E - |m|^2 - 2 eps rho / (gamma - 1) (quadratic in t);
-// theta2 = min t.  eps = min(e0, mean density, mean pressure).  Returns
+// with p(w) < eps, the largest t in [0, 1] with p(mean + t (w - mean)) >= eps
+// (p is concave along the segment), by 64 bisection steps that keep the
+// admissible end; theta2 = min t.  eps = min(e0, mean density, mean
+// pressure).  Returns
 // whether a mode changed; th1, th2 receive the factors.
 
 // value at test point k of the polynomial with modes c[a * N + b]; points
@@ -104,8 +105,6 @@ __device__ bool pp_scale(double* u, unsigned base, bool adiabatic, double gm1, d
     }
     if constexpr (NV == 4) {
         if (adiabatic) {
-            const double ge = 2.0 * eps / gm1;
-            const double C0 = 2.0 * r0 * m[3][0] - m[1][0] * m[1][0] - m[2][0] * m[2][0] - ge * r0;
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
                 double W[4];
@@ -113,15 +112,19 @@ __device__ bool pp_scale(double* u, unsigned base, bool adiabatic, double gm1, d
                 for (int v = 0; v < 4; ++v) W[v] = pp_point<N>(m[v], k);
                 const double pw = gm1 * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
                 if (!(pw < eps)) continue;
-                double d[4];
+                double lo = 0.0, hi = 1.0;
+                for (int it = 0; it < 64; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    double S[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) d[v] = W[v] - m[v][0];
-                const double A = 2.0 * d[0] * d[3] - d[1] * d[1] - d[2] * d[2];
-                const double B = 2.0 * (r0 * d[3] + m[3][0] * d[0]) - 2.0 * (m[1][0] * d[1] + m[2][0] * d[2]) - ge * d[0];
-                double t = 2.0 * C0 / (-B + sqrt(B * B - 4.0 * A * C0));
-                if (!(t >= 0.0)) t = 0.0;
-                if (t > 1.0) t = 1.0;
-                th2 = fmin(th2, t);
+                    for (int v = 0; v < 4; ++v) S[v] = m[v][0] + mid * (W[v] - m[v][0]);
+                    const double ps = gm1 * (S[3] - 0.5 * (S[1] * S[1] + S[2] * S[2]) / S[0]);
+                    if (ps >= eps)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                th2 = fmin(th2, lo);
             }
             if (th2 < 1.0) {
 #pragma unroll
