@@ -45,7 +45,10 @@ extern "C" {
 #define DG_ENONFINITE -5    /* device flagged a non-finite / non-positive mean */
 
 enum { DG_CLOSURE_ISOTHERMAL = 0, DG_CLOSURE_LOCALLY_ISOTHERMAL = 1, DG_CLOSURE_ADIABATIC = 2 };
-enum { DG_BC_PERIODIC = 0, DG_BC_FIXED_INITIAL = 1 };
+/* box edges: periodic; fixed (exterior trace = the element's initial trace,
+ * Sec. 3.1 ghost cells for the disc); gradient-free (exterior trace = the
+ * element's own current trace, the zero normal gradient of Sec. 4.2) */
+enum { DG_BC_PERIODIC = 0, DG_BC_FIXED_INITIAL = 1, DG_BC_GRADIENT_FREE = 2 };
 enum { DG_PRECISION_FP64 = 0, DG_PRECISION_MIXED = 1 };
 enum { DG_LIMITER_NONE = 0, DG_LIMITER_MODAL_DECAY = 1, DG_LIMITER_LEARNED = 2 };
 /* Runge-Kutta tables of Appendix A: SSP(3,3) with c_3 = 1/2 (the default),
@@ -64,7 +67,7 @@ typedef struct dg_config {
     double cs;            /* isothermal sound speed */
     double h;             /* aspect ratio: c_s^2 = h^2 GM / max(r, r_core) */
     double gamma;         /* adiabatic index */
-    int bc;               /* DG_BC_*: periodic, or exterior trace = initial trace */
+    int bc;               /* DG_BC_* */
     int star;             /* 1: stellar potential, harmonic core inside r_core */
     double gm, r_core;
     double q, eps;        /* planet mass ratio (0: no planet) and softening */

@@ -46,6 +46,7 @@ static double nb_mean(const or_cfg *c, const double *u, const double *u0, long e
     int in = i + (f == 1) - (f == 0), jn = j + (f == 3) - (f == 2);
     int outside = in < 0 || in >= c->nx || jn < 0 || jn >= c->ny;
     if (outside && c->bc == 1) return u0[((long)v * nn) * E + e];
+    if (outside && c->bc == 2) return u[((long)v * nn) * E + e]; /* gradient-free: own mean */
     in = (in + c->nx) % c->nx;
     jn = (jn + c->ny) % c->ny;
     return u[((long)v * nn) * E + (long)jn * c->nx + in];

@@ -13,13 +13,21 @@
                 the troubled-cell indicator.
 * ``rarefaction`` adiabatic gases receding at Mach 2.7 on a periodic strip,
                 with the positivity-preserving limiter.
+* ``vortex``      the isentropic vortex of Sec. 4.1 (beta = 5, gamma = 1.4) on the
+                periodic box [0, 10]^2.
+* ``gresho``      the Gresho vortex of Sec. 4.2 on [0, 1]^2 with gradient-free
+                box edges, gamma = 1.4.
+* ``paper_disc``  the adiabatic disc of Sec. 5.1: box [-2.25, 2.25]^2, Sigma0 = 1,
+                p0 = 2.5e-3, r_in = 0.4, r_ex = 1.75, gamma = 1.4, planet q = 6e-5
+                with softening 0.03, damping radii r_in 1.15^(3/2) and
+                r_ex 1.15^(-3/2).
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import synth
-from .dg import (BC_FIXED_INITIAL, BC_PERIODIC, CLOSURE_ADIABATIC, CLOSURE_ISOTHERMAL,
+from .dg import (BC_FIXED_INITIAL, BC_GRADIENT_FREE, BC_PERIODIC, CLOSURE_ADIABATIC, CLOSURE_ISOTHERMAL,
                  CLOSURE_LOCALLY_ISOTHERMAL, PRECISION_MIXED, Config, dg_get_nodes)
 
 
@@ -55,6 +63,24 @@ def rarefaction(nx=32, ny=2, order=3):
                   closure=CLOSURE_ADIABATIC, gamma=1.4, bc=BC_PERIODIC, cfl=1.0, positivity=1)
 
 
+def vortex(nx=40, order=3):
+    return Config(order=order, nvar=4, nx=nx, ny=nx, x0=0.0, x1=10.0, y0=0.0, y1=10.0,
+                  closure=CLOSURE_ADIABATIC, gamma=1.4, bc=BC_PERIODIC, cfl=0.2)
+
+
+def gresho(nx=40, order=3):
+    return Config(order=order, nvar=4, nx=nx, ny=nx, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+                  closure=CLOSURE_ADIABATIC, gamma=1.4, bc=BC_GRADIENT_FREE, cfl=0.2)
+
+
+def paper_disc(nx=320, order=5, q=6e-5):
+    f = 1.15 ** 1.5
+    return Config(order=order, nvar=4, nx=nx, ny=nx, x0=-2.25, x1=2.25, y0=-2.25, y1=2.25,
+                  closure=CLOSURE_ADIABATIC, gamma=1.4, h=0.05, bc=BC_FIXED_INITIAL, star=1, gm=1.0,
+                  r_core=0.4, q=q, eps=0.03, rp=1.0, phi0=0.0, damping=1, rd_in=0.4 * f, rd_out=1.75 / f,
+                  cfl=0.2)
+
+
 def prim_for(cfg: Config, kind: str, seed=None, x=None, y=None):
     """Primitive node values [var][E][n^2] of a workload.  Node coordinates
     default to the library's (dg_get_nodes); tests pass the oracle's."""
@@ -76,6 +102,12 @@ def prim_for(cfg: Config, kind: str, seed=None, x=None, y=None):
         fields = synth.disc_ring(x, y, gm=cfg.gm, h=cfg.h, r_core=cfg.r_core, sigma0=s0, r_ring=rr)
     elif kind == "rarefaction":
         fields = synth.double_rarefaction(x, y)
+    elif kind == "vortex":
+        fields = synth.isentropic_vortex(x, y)
+    elif kind == "gresho":
+        fields = synth.gresho(x, y)
+    elif kind == "paper_disc":
+        fields = synth.paper_disc(x, y, gm=cfg.gm, r_in=cfg.r_core)
     else:
         raise ValueError(kind)
     return synth.pack_prim(fields, E, nn)
@@ -90,4 +122,4 @@ def sigma0_of(seed):
     return 1.0 if seed is None else synth.disc_sigma0(seed)
 
 
-__all__ = ["wave", "disc", "disc_sweep", "disc_ring", "rarefaction", "prim_for", "dofs", "np"]
+__all__ = ["wave", "disc", "disc_sweep", "disc_ring", "rarefaction", "vortex", "gresho", "paper_disc", "prim_for", "dofs", "np"]

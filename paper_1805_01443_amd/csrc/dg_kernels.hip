@@ -250,7 +250,10 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     ir -= orr ? g.nx : 0;
     jb += ob ? g.ny : 0;
     jt -= ot ? g.ny : 0;
-    const bool fxd = g.bc == 1, fl = fxd && ol, fr = fxd && orr, fb = fxd && ob, ft = fxd && ot;
+    // box edges that are not periodic take the element's own row/column from
+    // u0: the initial state (fixed edge) or, for a gradient-free edge, the
+    // stage input itself (the caller passes u0 = u)
+    const bool fxd = g.bc != 0, fl = fxd && ol, fr = fxd && orr, fb = fxd && ob, ft = fxd && ot;
     const unsigned vcol = (eb + k * N * EW) * 8u;  // mode (0, k)
     const unsigned vb = (tiled_base<N, NV>(g, i, jb) + k * EW) * 8u, vt = (tiled_base<N, NV>(g, i, jt) + k * EW) * 8u;
     const unsigned vl = (tiled_base<N, NV>(g, il, j) + k * N * EW) * 8u;
@@ -297,17 +300,29 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             S[(v * N + k) * N + r] = c;
         }
         // own y collapses; exterior collapses with the neighbour's far side or,
-        // at a fixed box edge, the element's near side
-        double tm = 0.0, tp = 0.0, tb = 0.0, tt = 0.0, sl2 = 0.0, sr = 0.0;
+        // at a fixed box edge, the element's near side.  phi_m(-1) =
+        // (-1)^m phi_m(1): even and odd partial sums give either side.
+        double ue = 0.0, uo = 0.0, be = 0.0, bo = 0.0, te = 0.0, to = 0.0, le = 0.0, lo = 0.0, re = 0.0,
+               ro = 0.0;
 #pragma unroll
         for (int m = 0; m < N; ++m) {
-            tm += B.pm[m] * Ua[v][m];
-            tp += B.pp[m] * Ua[v][m];
-            tb += (fb ? B.pm[m] : B.pp[m]) * Xb[v][m];
-            tt += (ft ? B.pp[m] : B.pm[m]) * Xt[v][m];
-            sl2 += (fl ? B.pm[m] : B.pp[m]) * Xl[v][m];
-            sr += (fr ? B.pp[m] : B.pm[m]) * Xr[v][m];
+            if (m % 2 == 0) {
+                ue += B.pp[m] * Ua[v][m];
+                be += B.pp[m] * Xb[v][m];
+                te += B.pp[m] * Xt[v][m];
+                le += B.pp[m] * Xl[v][m];
+                re += B.pp[m] * Xr[v][m];
+            } else {
+                uo += B.pp[m] * Ua[v][m];
+                bo += B.pp[m] * Xb[v][m];
+                to += B.pp[m] * Xt[v][m];
+                lo += B.pp[m] * Xl[v][m];
+                ro += B.pp[m] * Xr[v][m];
+            }
         }
+        const double tm = ue - uo, tp = ue + uo;
+        const double tb = be + (fb ? -bo : bo), tt = te - (ft ? -to : to);
+        const double sl2 = le + (fl ? -lo : lo), sr = re - (fr ? -ro : ro);
         S[NV * NN + (0 * NV + v) * N + k] = tm;
         S[NV * NN + (1 * NV + v) * N + k] = tp;
         S[NV * NN + (2 * NV + v) * N + k] = tb;

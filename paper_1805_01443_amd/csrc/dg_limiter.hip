@@ -20,13 +20,15 @@ __device__ __forceinline__ double minmod3(double a, double b, double c) {
 }
 
 // mean of variable v of the neighbour across edge f (0 W, 1 E, 2 S, 3 N);
-// at a fixed box edge the exterior mean is the element's own initial mean
+// at a fixed box edge the exterior mean is the element's own initial mean, at
+// a gradient-free edge its own current mean
 template <int N, int NV>
 __device__ __forceinline__ double nb_mean(const Geo& g, const double* __restrict__ u, const double* __restrict__ u0,
                                           int i, int j, int v, int f) {
     int in = i + (f == 1) - (f == 0), jn = j + (f == 3) - (f == 2);
     const bool outside = in < 0 || in >= g.nx || jn < 0 || jn >= g.ny;
     if (outside && g.bc == 1) return u0[tiled_base<N, NV>(g, i, j) + mode_off<N>(v, 0, 0)];
+    if (outside && g.bc == 2) return u[tiled_base<N, NV>(g, i, j) + mode_off<N>(v, 0, 0)];
     in = (in + g.nx) % g.nx;
     jn = (jn + g.ny) % g.ny;
     return u[tiled_base<N, NV>(g, in, jn) + mode_off<N>(v, 0, 0)];

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdg.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_EUNSUPPORTED, DG_ENONFINITE = 0, -1, -2, -3, -4, -5
 CLOSURE_ISOTHERMAL, CLOSURE_LOCALLY_ISOTHERMAL, CLOSURE_ADIABATIC = 0, 1, 2
-BC_PERIODIC, BC_FIXED_INITIAL = 0, 1
+BC_PERIODIC, BC_FIXED_INITIAL, BC_GRADIENT_FREE = 0, 1, 2
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 LIMITER_NONE, LIMITER_MODAL_DECAY, LIMITER_LEARNED = 0, 1, 2
 RK_SSP33, RK_SSP22, RK_SSP54, RK_CASHKARP = 0, 1, 2, 3

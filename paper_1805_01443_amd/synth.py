@@ -113,6 +113,59 @@ def disc_ring(x, y, gm=1.0, h=0.05, r_core=0.4, sigma0=1.0, r_ring=1.6,
     return sigma, vx, vy, p
 
 
+def isentropic_vortex(x, y, t=0.0, beta=5.0, gamma=1.4, box=10.0, xc=5.0, yc=5.0):
+    """(rho, vx, vy, p) of the isentropic vortex of Sec. 4.1 on the periodic
+    box [0, box]^2, advected by the free stream (1, 1): the exact solution at
+    time t is the initial vortex centred at (xc + t, yc + t) (nearest periodic
+    image)."""
+    dx = np.mod(x - xc - t + 0.5 * box, box) - 0.5 * box
+    dy = np.mod(y - yc - t + 0.5 * box, box) - 0.5 * box
+    r2 = dx * dx + dy * dy
+    e = np.exp(1.0 - r2)
+    rho = (1.0 - (gamma - 1.0) * beta ** 2 / (8.0 * gamma * np.pi ** 2) * e) ** (1.0 / (gamma - 1.0))
+    g = beta / (2.0 * np.pi) * np.sqrt(e)
+    return rho, 1.0 - g * dy, 1.0 + g * dx, rho ** gamma
+
+
+def gresho(x, y, xc=0.5, yc=0.5):
+    """(rho, vx, vy, p) of the Gresho vortex of Sec. 4.2: rho = 1, v_phi =
+    5r, 2 - 5r, 0 on r < 0.2, 0.2 <= r < 0.4, r >= 0.4, and the pressure that
+    balances it."""
+    dx, dy = x - xc, y - yc
+    r = np.sqrt(dx * dx + dy * dy)
+    inner, mid = r < 0.2, (r >= 0.2) & (r < 0.4)
+    vphi = np.where(inner, 5.0 * r, np.where(mid, 2.0 - 5.0 * r, 0.0))
+    rs = np.maximum(r, 1e-300)
+    p = np.where(inner, 5.0 + 12.5 * r * r,
+                 np.where(mid, 9.0 - 4.0 * np.log(0.2) + 12.5 * r * r - 20.0 * r + 4.0 * np.log(rs),
+                          3.0 + 4.0 * np.log(2.0)))
+    return np.ones_like(r), -vphi * dy / rs, vphi * dx / rs, p
+
+
+def gresho_vorticity(x, y, xc=0.5, yc=0.5):
+    """Exact vorticity of the Gresho vortex: 10, 2/r - 10, 0."""
+    r = np.sqrt((x - xc) ** 2 + (y - yc) ** 2)
+    return np.where(r < 0.2, 10.0, np.where(r < 0.4, 2.0 / np.maximum(r, 1e-300) - 10.0, 0.0))
+
+
+def paper_disc(x, y, gm=1.0, sigma0=1.0, p0=2.5e-3, r_in=0.4, r_ex=1.75, h=0.05, rp=1.0):
+    """(Sigma, vx, vy, p) of the adiabatic disc of Sec. 5.1: Sigma = Sigma0/(1+f),
+    p = p0/(1+f), f = exp((r - r_ex)/(r_p h)); rotational equilibrium
+    v_phi^2 = r^2 Omega^2 - r c_iso^2 f / (r_p h (1+f)), c_iso^2 = p0/Sigma0,
+    with Omega^2 = GM/r_in^3 inside r_in (solid rotation) and GM/r^3 outside
+    (the printed formula's leading "Omega^2" read as r^2 Omega^2)."""
+    r = np.sqrt(x * x + y * y)
+    f = np.exp((r - r_ex) / (rp * h))
+    sigma = sigma0 / (1.0 + f)
+    p = p0 / (1.0 + f)
+    om2 = np.where(r <= r_in, gm / r_in ** 3, gm / np.maximum(r, 1e-300) ** 3)
+    c2 = p0 / sigma0
+    vphi2 = r * r * om2 - r * c2 * f / (rp * h * (1.0 + f))
+    vphi = np.sqrt(np.maximum(vphi2, 0.0))
+    rs = np.maximum(r, 1e-300)
+    return sigma, -vphi * y / rs, vphi * x / rs, p
+
+
 def double_rarefaction(x, y, speed=2.0, rho=1.0, p=0.4, split=0.5, band=0.02):
     """(rho, vx, vy, p): uniform gas with vx = -speed for x mod 1 < split and
     +speed above (two gases receding from x = split, colliding at x = 0 mod 1),

@@ -1,0 +1,190 @@
+"""The adiabatic validation problems of Sec. 4 on the GPU: parity with the
+oracle on the isentropic vortex (periodic box) and the Gresho vortex
+(gradient-free box edges), the empirical convergence order on the isentropic
+vortex (Sec. 4.1), and the Gresho errors against the paper's DG rows of
+Table 1 (tests/golden/gresho_table1.txt; loose checks, as in the paper's own
+comparison)."""
+import dataclasses
+import math
+import os
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+
+import oracle as O
+from paper_1805_01443_amd import configs as W
+from paper_1805_01443_amd import dg
+from paper_1805_01443_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "gresho_table1.txt")
+
+
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+def ocfg(cfg):
+    return O.cfg(dataclasses.asdict(cfg))
+
+
+def planes(cfg, u):
+    return dg.to_planes(cfg, u.detach().cpu().numpy())
+
+
+def relerr(a, b):
+    return [float(np.max(np.abs(a[v] - b[v])) / np.max(np.abs(b[v]))) for v in range(len(b))]
+
+
+@pytest.mark.parametrize("name,cfg,kind", [
+    ("vortex_p2", W.vortex(nx=20, order=3).replace(ny=17), "vortex"),
+    ("gresho_p3", W.gresho(nx=20, order=4).replace(ny=18), "gresho"),
+    ("gresho_p1", W.gresho(nx=23, order=2), "gresho"),
+])
+def test_parity_with_the_oracle(name, cfg, kind):
+    T = torch()
+    print(f"[parity] {name} order={cfg.order} nx={cfg.nx} ny={cfg.ny} bc={cfg.bc}", flush=True)
+    oc = ocfg(cfg)
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, kind, x=x, y=y)
+    h, u = dg.dg_init(cfg, prim)
+    uo = O.project(oc, prim)
+    assert max(relerr(planes(cfg, u), uo)) <= TOL
+    r = T.empty_like(u)
+    dg.dg_rhs(h, 0.1, u, r)
+    T.cuda.synchronize()
+    err = relerr(planes(cfg, r), O.rhs(oc, 0.1, uo, u0=uo))
+    print("  rhs rel err", err, flush=True)
+    assert max(err) <= TOL
+    u0 = uo.copy()
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    t = 0.0
+    for s in range(3):
+        dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
+        dg.dg_sync(h)
+        uo, dto = O.step(oc, uo, t, 0.0, u0=u0)
+        t += dto
+        assert abs(dt_dev.item() - dto) <= 1e-14 * dto
+        err = relerr(planes(cfg, u), uo)
+        print(f"  step {s}: rel err {err}", flush=True)
+        assert max(err) <= TOL
+    h.close()
+
+
+def node_values(cfg, a):
+    """[var][element][node] values at the volume Gauss nodes from planes a"""
+    return O.eval_nodes(ocfg(cfg), a).reshape(cfg.nvar, cfg.n_elem, cfg.order ** 2)
+
+
+def l1_weights(cfg):
+    """eq. (4) weights: (1/4) w_i w_j dx dy per node (node = q * n + r)"""
+    n = cfg.order
+    w = npleg.leggauss(n)[1]
+    dx = (cfg.x1 - cfg.x0) / cfg.nx
+    dy = (cfg.y1 - cfg.y0) / cfg.ny
+    return np.outer(w, w).ravel() * 0.25 * dx * dy
+
+
+def run_to(cfg, kind, t_end, dt):
+    T = torch()
+    prim = W.prim_for(cfg, kind)
+    h, u = dg.dg_init(cfg, prim)
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    nsteps = int(math.ceil(t_end / dt - 1e-9))
+    dt = t_end / nsteps
+    for _ in range(nsteps):
+        dg.dg_rk_step(h, u, t_dev, dt, None)
+    dg.dg_sync(h)
+    a = planes(cfg, u)
+    h.close()
+    return a, nsteps
+
+
+def cfl_dt(cfg, kind):
+    T = torch()
+    h, u = dg.dg_init(cfg, W.prim_for(cfg, kind))
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
+    dg.dg_sync(h)
+    d = dt_dev.item()
+    h.close()
+    return d
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_isentropic_vortex_convergence_order(order):
+    """Sec. 4.1: L1 density error (eq. (4) quadrature) after one crossing of
+    the periodic box, T = 10, on 16^2, 32^2, 64^2 elements; the empirical order
+    between the two finest meshes is at least N_p + 1 - 0.5.  Steps are fixed:
+    the CFL step of the coarsest mesh scaled by (dx ratio)^max(1, (N_p+1)/3),
+    so that RK3 does not cap the order at N_p >= 3 (reading of Sec. 4.1's
+    remark on the time order)."""
+    p = order - 1
+    meshes = (16, 32, 64)
+    dt0 = cfl_dt(W.vortex(nx=meshes[0], order=order), "vortex")
+    errs = []
+    for nx in meshes:
+        cfg = W.vortex(nx=nx, order=order)
+        dt = dt0 * (meshes[0] / nx) ** max(1.0, (p + 1) / 3.0)
+        a, nsteps = run_to(cfg, "vortex", 10.0, dt)
+        oc = ocfg(cfg)
+        x, y = O.nodes(oc)
+        ex = S.isentropic_vortex(x, y, t=10.0)[0]
+        err = float(np.sum(np.abs(node_values(cfg, a)[0] - ex) * l1_weights(cfg)))
+        errs.append(err)
+        print(f"[vortex] order {order} nx {nx}: {nsteps} steps, L1 density error {err:.3e}", flush=True)
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    print(f"[vortex] order {order}: empirical orders {rates}", flush=True)
+    assert rates[-1] >= p + 1 - 0.5, (errs, rates)
+
+
+def vorticity(cfg, a):
+    """omega = d(m_y/rho)/dx - d(m_x/rho)/dy at the volume Gauss nodes from the
+    modal polynomials (numpy Legendre series); [element][node]"""
+    n = cfg.order
+    xg = npleg.leggauss(n)[0]
+    sc = np.sqrt(2 * np.arange(n) + 1.0)
+    P = np.array([npleg.legval(xg, np.eye(n)[m]) * sc[m] for m in range(n)])          # [mode][q]
+    D = np.array([npleg.legval(xg, npleg.legder(np.eye(n)[m])) * sc[m] for m in range(n)])
+    dx = (cfg.x1 - cfg.x0) / cfg.nx
+    dy = (cfg.y1 - cfg.y0) / cfg.ny
+    m = a.reshape(cfg.nvar, n, n, -1)
+    val = lambda v: np.einsum("abe,aq,br->eqr", m[v], P, P)
+    ddx = lambda v: np.einsum("abe,aq,br->eqr", m[v], D, P) * (2.0 / dx)
+    ddy = lambda v: np.einsum("abe,aq,br->eqr", m[v], P, D) * (2.0 / dy)
+    rho, mx, my = val(0), val(1), val(2)
+    w = (ddx(2) - my / rho * ddx(0)) / rho - (ddy(1) - mx / rho * ddy(0)) / rho
+    return w.reshape(-1, n * n)
+
+
+def test_gresho_errors_against_table1():
+    """Sec. 4.2, Table 1: relative L1 errors of vorticity and density at
+    T = 3 on 40 x 40, orders 2-4.  Loose checks: each within a factor 3 of the
+    paper's value, and both decrease with the order as in the paper."""
+    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    res = []
+    for name, order, vort_pct, dens_pct in rows:
+        order = int(order)
+        cfg = W.gresho(nx=40, order=order)
+        dt = cfl_dt(cfg, "gresho")
+        a, nsteps = run_to(cfg, "gresho", 3.0, dt)
+        oc = ocfg(cfg)
+        x, y = O.nodes(oc)
+        wq = l1_weights(cfg)
+        rho = node_values(cfg, a)[0]
+        de = 100.0 * np.sum(np.abs(rho - 1.0) * wq) / np.sum(np.ones_like(rho) * wq)
+        om = vorticity(cfg, a)
+        ex = S.gresho_vorticity(x, y)
+        ve = 100.0 * np.sum(np.abs(om - ex) * wq) / np.sum(np.abs(ex) * wq)
+        print(f"[gresho] {name}: {nsteps} steps, L1 vorticity error {ve:.2f} % (paper {vort_pct}), "
+              f"L1 density error {de:.4f} % (paper {dens_pct})", flush=True)
+        res.append((ve, de, float(vort_pct), float(dens_pct)))
+    for ve, de, pv, pd in res:
+        assert pv / 3 <= ve <= pv * 3 and pd / 3 <= de <= pd * 3, res
+    assert res[0][0] > res[1][0] > res[2][0] and res[0][1] > res[1][1], res

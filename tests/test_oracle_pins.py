@@ -325,6 +325,34 @@ def test_disc_equilibrium_residual_decays_under_refinement():
     assert res[1] < res[0] / 4, res
 
 
+def test_paper_disc_equilibrium_and_the_vphi_reading():
+    """The adiabatic disc of Sec. 5.1 (Sigma0/(1+f), p0/(1+f)) with
+    v_phi^2 = r^2 Omega^2 - r c_iso^2 f/(h(1+f)) is a rotational equilibrium:
+    ||L(u_eq)|| on the undamped annulus decays under refinement.  The formula as
+    printed (Omega^2 in place of r^2 Omega^2) is not: its residual stays O(1)."""
+    def residual(nx, literal=False):
+        c = O.cfg(n=3, nvar=4, nx=nx, ny=nx, x0=-2.25, x1=2.25, y0=-2.25, y1=2.25, closure=2, gamma=1.4,
+                  star=1, bc=1, r_core=0.4)
+        X, Y = O.nodes(c)
+        rho, vx, vy, p = S.paper_disc(X, Y)
+        if literal:
+            r = np.sqrt(X * X + Y * Y)
+            f = np.exp((r - 1.75) / 0.05)
+            om2 = np.where(r <= 0.4, 1 / 0.4 ** 3, 1 / r ** 3)
+            vphi = np.sqrt(np.maximum(om2 - r * 2.5e-3 * f / (0.05 * (1 + f)), 0.0))
+            vx, vy = -vphi * Y / r, vphi * X / r
+        u = O.project(c, S.pack_prim((rho, vx, vy, p), X.shape[0], 9))
+        rr = O.rhs(c, 0.0, u, u0=u)
+        R = np.sqrt(X.mean(axis=1) ** 2 + Y.mean(axis=1) ** 2)
+        sel = (R > 0.7) & (R < 1.3)
+        return np.sqrt(np.mean(rr[1:3, :, sel] ** 2))
+    # (at 10 x 10 the projected energy minus the kinetic energy is negative at
+    # some nodes: p0 = 2.5e-3 is small against |v|^2 / 2)
+    r20, r40 = residual(20), residual(40)
+    assert r40 < r20 / 4, (r20, r40)
+    assert residual(40, literal=True) > 100 * r40
+
+
 # ---------------------------------------------------------------- damping
 def _disc_cfg(nx, **kw):
     d = dict(n=3, nx=nx, ny=nx, x0=-2.5, x1=2.5, y0=-2.5, y1=2.5, closure=1, star=1, bc=1,
@@ -421,3 +449,65 @@ def test_torque_single_element_vs_scipy_integral():
 
         ref, _ = integrate.dblquad(f, 1.2, 1.5, 0.1, 0.35, epsabs=1e-13, epsrel=1e-12)
         assert abs(g - ref) < tol * abs(ref), (n, g, ref)
+
+
+# ---------------------------------------------------------------- gradient-free box edges
+def test_gradient_free_edges_free_stream_and_mass_balance():
+    """Gradient-free edges (Sec. 4.2: exterior trace = own trace) keep a free
+    stream exactly, and the mass change equals minus the boundary integral of
+    m.n over the interior traces (the edge flux is the physical flux there),
+    evaluated independently with numpy's Legendre series and Gauss rule."""
+    n, nx, ny = 3, 6, 5
+    c = O.cfg(n=n, nvar=4, nx=nx, ny=ny, x0=0.0, x1=1.2, y0=0.0, y1=1.0, closure=2, gamma=1.4, bc=2)
+    X, Y = O.nodes(c)
+    E = nx * ny
+    one = np.ones_like(X)
+    u = O.project(c, S.pack_prim((1.3 * one, 0.3 * one, -0.2 * one, 0.9 * one), E, n * n))
+    assert np.max(np.abs(O.rhs(c, 0.0, u))) <= 1e-14
+    rng = np.random.default_rng(5)
+    u = O.project(c, S.pack_prim((1.0 + 0.2 * np.sin(3 * X + Y), 0.5 + 0.3 * np.cos(2 * Y), 0.2 * X - 0.1,
+                                  2.0 + 0.1 * X * Y), E, n * n))
+    u[:, 1:, :] += 1e-3 * rng.standard_normal(u[:, 1:, :].shape)
+    r = O.rhs(c, 0.0, u)
+    dx, dy = 1.2 / nx, 1.0 / ny
+    dmass = np.sum(r[0, 0, :]) * dx * dy  # orthonormal basis: mass = |K| u_00
+    xg, wg = npleg.leggauss(n)
+    sc = np.sqrt(2 * np.arange(n) + 1.0)
+    P = lambda z: np.array([npleg.legval(z, np.eye(n)[m]) * sc[m] for m in range(n)])
+    flux = 0.0
+    for e in range(E):
+        i, j = e % nx, e // nx
+        mod = lambda v: u[v, :, e].reshape(n, n)  # [a][b]
+        for side, (xi, eta, mv, sgn, length) in {
+                "W": (np.full(n, -1.0), xg, 1, -1.0, dy), "E": (np.full(n, 1.0), xg, 1, 1.0, dy),
+                "S": (xg, np.full(n, -1.0), 2, -1.0, dx), "N": (xg, np.full(n, 1.0), 2, 1.0, dx)}.items():
+            on = {"W": i == 0, "E": i == nx - 1, "S": j == 0, "N": j == ny - 1}[side]
+            if not on:
+                continue
+            vals = np.einsum("ab,ak,bk->k", mod(mv), P(xi), P(eta))
+            flux += sgn * np.sum(wg * vals) * 0.5 * length
+    assert abs(dmass + flux) <= 1e-13 * max(abs(flux), 1.0), (dmass, flux)
+
+
+# ---------------------------------------------------------------- isentropic vortex set-up
+def test_isentropic_vortex_is_a_translating_solution():
+    """The set-up of Sec. 4.1 (beta = 5, gamma = 1.4) is an exact solution
+    translating with (1, 1): the oracle's L(u) of the projected vortex matches
+    the projected d/dt of the exact field (central difference in t of the
+    generator): the RMS error of the element means falls more than 4x from
+    20 x 20 to 40 x 40 elements at order 3."""
+    errs = []
+    for nx in (20, 40):
+        c = O.cfg(n=3, nvar=4, nx=nx, ny=nx, x0=0.0, x1=10.0, y0=0.0, y1=10.0, closure=2, gamma=1.4, bc=0)
+        X, Y = O.nodes(c)
+        E = nx * nx
+        u = O.project(c, S.pack_prim(S.isentropic_vortex(X, Y), E, 9))
+        dlt = 1e-4
+        up = O.project(c, S.pack_prim(S.isentropic_vortex(X, Y, t=dlt), E, 9))
+        um = O.project(c, S.pack_prim(S.isentropic_vortex(X, Y, t=-dlt), E, 9))
+        dudt = (up - um) / (2 * dlt)
+        d = O.rhs(c, 0.0, u) - dudt
+        # RMS over the element means of all variables
+        errs.append(np.sqrt(np.mean(d[:, 0, :] ** 2)) / np.sqrt(np.mean(dudt[:, 0, :] ** 2)))
+    assert errs[1] < errs[0] / 4, errs
+    assert errs[1] < 0.01, errs
