@@ -46,8 +46,9 @@ extern "C" {
 
 enum { DG_CLOSURE_ISOTHERMAL = 0, DG_CLOSURE_LOCALLY_ISOTHERMAL = 1, DG_CLOSURE_ADIABATIC = 2 };
 /* box edges: periodic; fixed (exterior trace = the element's initial trace,
- * Sec. 3.1 ghost cells for the disc); gradient-free (exterior trace = the
- * element's own current trace, the zero normal gradient of Sec. 4.2) */
+ * Sec. 3.1 ghost cells for the disc); gradient-free (Sec. 4.2: a ghost element
+ * without gradient, i.e. the exterior state is the element's own current
+ * mean) */
 enum { DG_BC_PERIODIC = 0, DG_BC_FIXED_INITIAL = 1, DG_BC_GRADIENT_FREE = 2 };
 enum { DG_PRECISION_FP64 = 0, DG_PRECISION_MIXED = 1 };
 enum { DG_LIMITER_NONE = 0, DG_LIMITER_MODAL_DECAY = 1, DG_LIMITER_LEARNED = 2 };

@@ -391,8 +391,9 @@ void or_rhs(const or_cfg *c, double t, const double *u, const double *u0, double
                     /* fixed box edge: exterior state = initial interior trace */
                     eval_point(c, u0, e, xi, eta, Uo);
                 } else if (outside && c->bc == 2) {
-                    /* gradient-free box edge (Sec. 4.2): exterior = interior trace */
-                    eval_point(c, u, e, xi, eta, Uo);
+                    /* gradient-free box edge (Sec. 4.2): a ghost element with no
+                     * gradient, the element's own mean state */
+                    for (int v = 0; v < nv; ++v) Uo[v] = u[((long)v * T.nn) * E + e];
                 } else {
                     /* the same physical point seen from the neighbour */
                     double xin = f < 2 ? -xi : xi, etan = f < 2 ? eta : -eta;

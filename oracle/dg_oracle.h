@@ -36,7 +36,7 @@ typedef struct {
     double h;         /* aspect ratio: c_s^2 = h^2 GM / max(r, r_core) */
     double gamma;     /* adiabatic index */
     int bc;           /* 0 periodic, 1 exterior trace = initial trace, 2 gradient-free
-                         (exterior trace = the element's own current trace) */
+                         (exterior state = the element's own current mean) */
     int star;         /* 1: stellar potential (harmonic core inside r_core) */
     double gm, r_core;
     double q, eps;    /* planet mass ratio (0: no planet) and softening */

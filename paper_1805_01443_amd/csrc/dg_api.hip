@@ -214,10 +214,6 @@ void drop_events(dg_handle* h) {
 }
 
 // launch one stage kernel, bracketed by events while profiling
-// the state a box edge reads its exterior trace from: the initial state at a
-// fixed edge, the stage input itself at a gradient-free edge
-const double* exterior(const dg_handle* h, const double* u) { return h->cfg.bc == DG_BC_GRADIENT_FREE ? u : h->u0; }
-
 hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, const StageCoeffs* sc) {
     hipEvent_t a = nullptr, b = nullptr;
     if (h->prof) {
@@ -230,7 +226,7 @@ hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, c
         if (e != hipSuccess) return e;
     }
     hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, out, sc, h->s)
-                          : dgk::launch_stage(h->n, h->g, u, un, exterior(h, u), out, sc, h->s);
+                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, h->s);
     if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
     return e;
 }
@@ -542,7 +538,7 @@ int dg_rhs(dg_handle* h, double t, const double* u_dev, double* rhs_dev) {
     if (!u_dev || !rhs_dev || u_dev == rhs_dev) return fail(h, DG_EINVAL, "u_dev and rhs_dev must be distinct device arrays");
     DG_HIP(h, dgk::launch_set_coeffs(h->sc_rhs, h->g, t, 0.0, 0.0, 1.0, h->s), "dg_rhs coefficients");
     DG_HIP(h, h->dev ? dgk::launch_stage_dev(h->n, h->g, u_dev, nullptr, h->du0, h->leq, rhs_dev, h->sc_rhs, h->s)
-                     : dgk::launch_stage(h->n, h->g, u_dev, nullptr, exterior(h, u_dev), rhs_dev, h->sc_rhs, h->s),
+                     : dgk::launch_stage(h->n, h->g, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, h->s),
            "dg_rhs stage");
     return DG_OK;
 }

@@ -250,10 +250,12 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     ir -= orr ? g.nx : 0;
     jb += ob ? g.ny : 0;
     jt -= ot ? g.ny : 0;
-    // box edges that are not periodic take the element's own row/column from
-    // u0: the initial state (fixed edge) or, for a gradient-free edge, the
-    // stage input itself (the caller passes u0 = u)
+    // box edges that are not periodic: the exterior is the element's own
+    // initial row/column (fixed edge) or a ghost with no gradient, the
+    // element's own current mean (gradient-free edge: only mode (0, 0), held by
+    // lane k = 0 as Ua[v][0])
     const bool fxd = g.bc != 0, fl = fxd && ol, fr = fxd && orr, fb = fxd && ob, ft = fxd && ot;
+    const bool gfree = g.bc == 2;
     const unsigned vcol = (eb + k * N * EW) * 8u;  // mode (0, k)
     const unsigned vb = (tiled_base<N, NV>(g, i, jb) + k * EW) * 8u, vt = (tiled_base<N, NV>(g, i, jt) + k * EW) * 8u;
     const unsigned vl = (tiled_base<N, NV>(g, il, j) + k * N * EW) * 8u;
@@ -275,7 +277,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const double o = ld64(ru0, vrow, (unsigned)(v * N + m) * RS);
+                const double o = gfree ? ((k == 0 && m == 0) ? Ua[v][0] : 0.0)
+                                       : ld64(ru0, vrow, (unsigned)(v * N + m) * RS);
                 Xb[v][m] = fb ? o : Xb[v][m];
                 Xt[v][m] = ft ? o : Xt[v][m];
             }
@@ -285,7 +288,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const double o = ld64(ru0, vcol, (unsigned)(v * NN + m) * CS);
+                const double o = gfree ? ((k == 0 && m == 0) ? Ua[v][0] : 0.0)
+                                       : ld64(ru0, vcol, (unsigned)(v * NN + m) * CS);
                 Xl[v][m] = fl ? o : Xl[v][m];
                 Xr[v][m] = fr ? o : Xr[v][m];
             }

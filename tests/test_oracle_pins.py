@@ -453,10 +453,13 @@ def test_torque_single_element_vs_scipy_integral():
 
 # ---------------------------------------------------------------- gradient-free box edges
 def test_gradient_free_edges_free_stream_and_mass_balance():
-    """Gradient-free edges (Sec. 4.2: exterior trace = own trace) keep a free
-    stream exactly, and the mass change equals minus the boundary integral of
-    m.n over the interior traces (the edge flux is the physical flux there),
-    evaluated independently with numpy's Legendre series and Gauss rule."""
+    """Gradient-free edges (Sec. 4.2; reading: a ghost element without
+    gradient, the element's own mean) keep a free stream exactly; where the
+    boundary elements are flat the edge flux is the physical flux, so the mass
+    change equals minus the boundary integral of m.n (numpy Legendre series and
+    Gauss rule); and a lone element at rest with a density slope loses mass at
+    the Rusanov rate 1/2 alpha (mean - trace), alpha = max of the sound speeds
+    of trace and mean, in closed form."""
     n, nx, ny = 3, 6, 5
     c = O.cfg(n=n, nvar=4, nx=nx, ny=ny, x0=0.0, x1=1.2, y0=0.0, y1=1.0, closure=2, gamma=1.4, bc=2)
     X, Y = O.nodes(c)
@@ -468,25 +471,38 @@ def test_gradient_free_edges_free_stream_and_mass_balance():
     u = O.project(c, S.pack_prim((1.0 + 0.2 * np.sin(3 * X + Y), 0.5 + 0.3 * np.cos(2 * Y), 0.2 * X - 0.1,
                                   2.0 + 0.1 * X * Y), E, n * n))
     u[:, 1:, :] += 1e-3 * rng.standard_normal(u[:, 1:, :].shape)
+    ii, jj = np.arange(E) % nx, np.arange(E) // nx
+    edge = (ii == 0) | (ii == nx - 1) | (jj == 0) | (jj == ny - 1)
+    u[:, 1:, edge] = 0.0  # flat boundary elements
     r = O.rhs(c, 0.0, u)
     dx, dy = 1.2 / nx, 1.0 / ny
     dmass = np.sum(r[0, 0, :]) * dx * dy  # orthonormal basis: mass = |K| u_00
-    xg, wg = npleg.leggauss(n)
-    sc = np.sqrt(2 * np.arange(n) + 1.0)
-    P = lambda z: np.array([npleg.legval(z, np.eye(n)[m]) * sc[m] for m in range(n)])
     flux = 0.0
-    for e in range(E):
+    for e in np.nonzero(edge)[0]:
         i, j = e % nx, e // nx
-        mod = lambda v: u[v, :, e].reshape(n, n)  # [a][b]
-        for side, (xi, eta, mv, sgn, length) in {
-                "W": (np.full(n, -1.0), xg, 1, -1.0, dy), "E": (np.full(n, 1.0), xg, 1, 1.0, dy),
-                "S": (xg, np.full(n, -1.0), 2, -1.0, dx), "N": (xg, np.full(n, 1.0), 2, 1.0, dx)}.items():
-            on = {"W": i == 0, "E": i == nx - 1, "S": j == 0, "N": j == ny - 1}[side]
-            if not on:
-                continue
-            vals = np.einsum("ab,ak,bk->k", mod(mv), P(xi), P(eta))
-            flux += sgn * np.sum(wg * vals) * 0.5 * length
+        nxo = int(i == nx - 1) - int(i == 0)
+        nyo = int(j == ny - 1) - int(j == 0)
+        flux += u[1, 0, e] * nxo * dy + u[2, 0, e] * nyo * dx
     assert abs(dmass + flux) <= 1e-13 * max(abs(flux), 1.0), (dmass, flux)
+    # one element at rest, rho = rb + s sqrt(3) xi, uniform pressure
+    c1 = O.cfg(n=2, nvar=4, nx=1, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, closure=2, gamma=1.4, bc=2)
+    rb, s_, p = 1.0, 0.2, 0.7
+    u1 = np.zeros((4, 4, 1))
+    u1[0, 0] = rb
+    u1[0, 2] = s_  # mode (1, 0)
+    u1[3, 0] = p / 0.4
+    r1 = O.rhs(c1, 0.0, u1)
+    cs = lambda rho: math.sqrt(1.4 * p / rho)
+    re_, rw = rb + s_ * math.sqrt(3), rb - s_ * math.sqrt(3)
+    # west/east edges: F = -1/2 alpha (mean - trace) outward; south/north: traces = rho(xi) on
+    # the 2-point Gauss rule, whose average is the mean, so they cancel in the mass balance
+    dm = 0.5 * max(cs(re_), cs(rb)) * (rb - re_) + 0.5 * max(cs(rw), cs(rb)) * (rb - rw)
+    xg, wg = npleg.leggauss(2)
+    for sgn in (-1.0, 1.0):
+        for xq, wq in zip(xg, wg):
+            rho = rb + s_ * math.sqrt(3) * xq
+            dm += 0.5 * wq * 0.5 * max(cs(rho), cs(rb)) * (rb - rho)
+    assert abs(r1[0, 0, 0] - dm) <= 1e-14, (r1[0, 0, 0], dm)
 
 
 # ---------------------------------------------------------------- isentropic vortex set-up
