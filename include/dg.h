@@ -15,7 +15,9 @@
  *          run [v][b][a][s], so mode (a, b) of variable v (rho, rho vx,
  *          rho vy[, E]) of element (i, j) is
  *              u[((t * nvar + v) * n + b) * n * W + a * W + s].
- *          Slots past the end of a row are padding.  The array holds
+ *          Slots past the end of a row are padding: dg_init zeroes them in
+ *          u0_dev, and no call reads them or writes them in an output (an
+ *          output array keeps whatever its padding held).  The array holds
  *          dg_state_size(cfg) doubles.  (The paper keeps one matrix per mode,
  *          Sec. 3.1; tiles keep what one wavefront reads contiguous.)
  *   basis  phi_ab(xi, eta) = sqrt((2a+1)(2b+1)) P_a(xi) P_b(eta), orthonormal

@@ -177,6 +177,8 @@ void make_geo(const dg_config* c, Geo* g) {
     g->rd_out = c->rd_out;
     g->rb_in = c->rd_in / f;
     g->rb_out = c->rd_out * f;
+    g->irw_in = 1.0 / (g->rb_in - g->rd_in);
+    g->irw_out = 1.0 / (g->rb_out - g->rd_out);
     g->td_in = c->gm > 0 ? 2.0 * pi * std::sqrt(c->rd_in * c->rd_in * c->rd_in / c->gm) : 0.0;
     g->td_out = c->gm > 0 ? 2.0 * pi * std::sqrt(c->rd_out * c->rd_out * c->rd_out / c->gm) : 0.0;
     g->cfl_fac = c->cfl / (2.0 * (c->order - 1) + 1.0);

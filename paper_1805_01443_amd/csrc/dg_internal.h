@@ -40,6 +40,7 @@ struct Geo {
     // damping
     int damping;
     double rd_in, rd_out, rb_in, rb_out, td_in, td_out;
+    double irw_in, irw_out;     // 1 / (rb - rd) of each zone
     double cfl_fac;             // C / (2 N_p + 1)
     double pp_eps;              // positivity limiter: floor of eps
     double sigma0;              // deviation form: equilibrium Sigma0

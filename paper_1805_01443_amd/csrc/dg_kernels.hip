@@ -1199,12 +1199,12 @@ __device__ __forceinline__ void eval_nodes(const double (&M)[NV][N * N], double 
 // ramp R(r) of the wave-killing zones and the zone's damping period T_d
 __device__ __forceinline__ double ramp(const Geo& g, double r, double& td) {
     if (r < g.rd_in) {
-        const double s = (r - g.rd_in) / (g.rb_in - g.rd_in);
+        const double s = (r - g.rd_in) * g.irw_in;
         td = g.td_in;
         return s > 1.0 ? 1.0 : s * s;
     }
     if (r > g.rd_out) {
-        const double s = (r - g.rd_out) / (g.rb_out - g.rd_out);
+        const double s = (r - g.rd_out) * g.irw_out;
         td = g.td_out;
         return s > 1.0 ? 1.0 : s * s;
     }
@@ -1225,8 +1225,8 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
-    constexpr int SLOT = 2 * NV * NN;
-    __shared__ double lds[(EW + 1) * SLOT];
+    constexpr int SLOT = lds_slot(2 * NV * NN, N);
+    __shared__ double lds[EW * SLOT];
     constexpr unsigned RS = N * EW * 8;  // byte stride of (v * N + b) in a row
     const int lane = threadIdx.x;
     const int sl = lane / N, k = lane - sl * N;
@@ -1235,22 +1235,22 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
     const int i0 = (tile - j * g.tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
     const int i = active ? i0 + sl : i0;  // idle lanes shadow a valid element and store nothing
-    double* S = lds + sl * SLOT;
+    // lanes beyond EW * N shadow slot 0's element (same i, j, k) and share its slot
+    double* S = lds + ((EW * N == 64 || sl < EW) ? sl : 0) * SLOT;
     const double dt = scp->dt;
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
     const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), req = make_rsrc(eq ? eq : u0);
     const unsigned vrow = (tiled_base<N, NV>(g, i, j) + k * EW) * 8u;  // mode (k, 0)
 
     // mode row k: y contraction of u (full state) and u0
-    double Ud[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         double A[N], A0[N];
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             const unsigned so = (unsigned)(v * N + b) * RS;
-            Ud[v][b] = ld64(ru, vrow, so);
-            A[b] = eq ? ld64(req, vrow, so) + Ud[v][b] : Ud[v][b];
+            const double ud = ld64(ru, vrow, so);
+            A[b] = eq ? ld64(req, vrow, so) + ud : ud;
             A0[b] = ld64(ru0, vrow, so);
         }
 #pragma unroll
@@ -1299,9 +1299,9 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
 #pragma unroll
         for (int v = 0; v < NV; ++v) D[v] = 0.0;
         if (R > 0.0) {
-            const double w = dt * R / (td + dt * R);
-            const double rho = W[0], vx = W[1] / rho, vy = W[2] / rho;
-            const double rho0 = W0[0], vx0 = W0[1] / rho0, vy0 = W0[2] / rho0;
+            const double w = dt * R * rcp64(td + dt * R);
+            const double rho = W[0], ir = rcp64(rho), vx = W[1] * ir, vy = W[2] * ir;
+            const double rho0 = W0[0], ir0 = rcp64(rho0), vx0 = W0[1] * ir0, vy0 = W0[2] * ir0;
             const double drho = w * (rho0 - rho);
             const double dvx = w * (vx0 - vx), dvy = w * (vy0 - vy);
             const double vx1 = vx + dvx, vy1 = vy + dvy;
@@ -1310,8 +1310,8 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
             D[2] = rho * dvy + drho * vy1;
             if constexpr (NV == 4) {
                 const double gm1 = g.gamma - 1.0;
-                const double T1 = gm1 * (W[3] - 0.5 * rho * (vx * vx + vy * vy)) / rho;
-                const double T0 = gm1 * (W0[3] - 0.5 * rho0 * (vx0 * vx0 + vy0 * vy0)) / rho0;
+                const double T1 = gm1 * (W[3] - 0.5 * rho * (vx * vx + vy * vy)) * ir;
+                const double T0 = gm1 * (W0[3] - 0.5 * rho0 * (vx0 * vx0 + vy0 * vy0)) * ir0;
                 const double dT = w * (T0 - T1);
                 const double dp = rho * dT + drho * (T1 + dT);
                 const double dke = 0.5 * (drho * (vx1 * vx1 + vy1 * vy1) + rho * (dvx * (vx1 + vx) + dvy * (vy1 + vy)));
@@ -1330,8 +1330,14 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
         for (int a = 0; a < N; ++a) S[(v * N + k) * N + a] = P[v][a];
     __syncthreads();
 
-    // mode row k: y projection and update
+    // mode row k: y projection and update; the row of u comes back from L2
+    // (fewer live registers across the phases), all loads before the stores
     if (active) {
+        double Ud[NV][N];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) Ud[v][b] = ld64(ru, vrow, (unsigned)(v * N + b) * RS);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -1364,11 +1370,16 @@ __global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, double t, 
                                                          double* __restrict__ partials) {
     constexpr BasisTab T = make_basis(N);
     __shared__ double red[4];
+    __shared__ double pxy[2];
     constexpr int NN = N * N;
     const long long e = (long long)blockIdx.x * kTorqueBlock + threadIdx.x;
-    const double tt = t_dev ? *t_dev : t;
-    double xp, yp;
-    planet_at(g, tt, xp, yp);
+    // the planet position, once per block
+    if (threadIdx.x == 0) {
+        const double tt = t_dev ? *t_dev : t;
+        planet_at(g, tt, pxy[0], pxy[1]);
+    }
+    __syncthreads();
+    const double xp = pxy[0], yp = pxy[1];
     double s = 0.0;
     if (e < g.E) {
         double M[1][NN], W[1][NN];
@@ -1392,8 +1403,8 @@ __global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, double t, 
                 const double x = xc + 0.5 * g.dx * T.xi[q], y = yc + 0.5 * g.dy * T.xi[r];
                 const double m = W[0][q * N + r] * T.wh[q] * T.wh[r] * area;
                 const double dx = x - xp, dy = y - yp;
-                const double d2 = dx * dx + dy * dy + g.eps2;
-                const double k = m / (d2 * sqrt(d2));
+                const double id = rsq64(dx * dx + dy * dy + g.eps2);
+                const double k = m * (id * id * id);
                 s += xp * (k * dy) - yp * (k * dx);
             }
     }

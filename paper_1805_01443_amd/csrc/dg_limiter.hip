@@ -35,121 +35,177 @@ __device__ __forceinline__ double nb_mean(const Geo& g, const double* __restrict
 }
 
 // ------------------------------------------------------------------ positivity
-// Positivity-preserving scaling of Zhang & Shu (Sec. 2.4) of one element in
-// place.  Test points: (Lobatto x Gauss) and (Gauss x Lobatto).  Density:
+// Positivity-preserving scaling of Zhang & Shu (Sec. 2.4), in place on every
+// element.  Test points: (Lobatto x Gauss) and (Gauss x Lobatto).  Density:
 // theta1 = (mean - eps) / (mean - min) where the minimum falls below eps;
 // pressure (adiabatic only): at each point of the density-limited state w
 // with p(w) < eps, the largest t in [0, 1] with p(mean + t (w - mean)) >= eps
 // (p is concave along the segment), by 64 bisection steps that keep the
 // admissible end; theta2 = min t.  eps = min(e0, mean density, mean
-// pressure).  Returns
-// whether a mode changed; th1, th2 receive the factors.
-
-// value at test point k of the polynomial with modes c[a * N + b]; points
-// 0 .. L*N-1 are (Lobatto q, Gauss r), the rest (Gauss q, Lobatto r)
-template <int N>
-__device__ __forceinline__ double pp_point(const double (&c)[N * N], int k) {
-    constexpr auto& G = Basis<N>::t;
-    constexpr auto& B = Lobatto<N>::t;
-    constexpr int L = B.L;
-    double s = 0.0;
-    if (k < L * N) {
-        const int q = k / N, r = k % N;
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-            double cb = 0.0;
-#pragma unroll
-            for (int a = 0; a < N; ++a) cb = fma(c[a * N + b], B.phi[a][q], cb);
-            s = fma(cb, G.phi[b][r], s);
-        }
-    } else {
-        const int q = (k - L * N) / L, r = (k - L * N) % L;
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            double ca = 0.0;
-#pragma unroll
-            for (int b = 0; b < N; ++b) ca = fma(c[a * N + b], B.phi[b][r], ca);
-            s = fma(ca, G.phi[a][q], s);
-        }
-    }
-    return s;
-}
-
+// pressure).
+// N lanes per element (lane (s, k), EW = 64 / N elements per wavefront, one
+// wavefront per block): lane k holds mode row k of every variable and
+// contracts it in y at the Gauss and at the Lobatto points; through LDS, lane
+// k then evaluates the test points with x-index k (Lobatto x Gauss for k < L,
+// Gauss x Lobatto for k < N), the N lanes reduce the density minimum, take
+// theta1, check the pressure of the density-limited point values
+// (rho~ = mean + theta1 (rho - mean)), reduce theta2, and each lane scales and
+// stores its row.
 template <int N, int NV>
-__device__ bool pp_scale(double* u, unsigned base, bool adiabatic, double gm1, double e0, double& th1, double& th2) {
-    constexpr int NN = N * N;
-    constexpr int NP = 2 * Lobatto<N>::t.L * N;
-    th1 = 1.0;
-    th2 = 1.0;
-    double m[NV][NN];
+__global__ void __launch_bounds__(64) k_pp_c(const Geo g, double* u, double e0, unsigned char* changed_out,
+                                             double* theta_out) {
+    constexpr auto& G = Basis<N>::t;
+    constexpr auto& Lb = Lobatto<N>::t;
+    constexpr int L = Lb.L;
+    constexpr int EW = 64 / N;
+    constexpr int SA = NV * N * N;           // [v][a][r]: row a at Gauss eta_r
+    constexpr int SB = NV * N * L;           // [v][a][r]: row a at Lobatto eta_r
+    constexpr int SLOT = SA + SB + NV + 2 * N;  // + means + per-lane minima
+    constexpr int NP = N + L;                // test points per lane (the first N need k < L)
+    __shared__ double lds[EW * SLOT];
+    const int lane = threadIdx.x;
+    const int sl = lane / N, k = lane - sl * N;
+    const bool own = EW * N == 64 || sl < EW;  // idle lanes shadow slot 0's element
+    const int tile = blockIdx.x;
+    const int j = tile / g.tiles_x;
+    const int i0 = (tile - j * g.tiles_x) * EW;
+    const bool active = sl < EW && i0 + sl < g.nx;
+    const int i = active ? i0 + sl : i0;
+    double* S = lds + (own ? sl : 0) * SLOT;
+    const unsigned base = tiled_base<N, NV>(g, i, j);
+    // row k contracted in y at the Gauss and at the Lobatto points
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+    for (int v = 0; v < NV; ++v) {
+        double Ua[N];
 #pragma unroll
-        for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) Ua[b] = u[base + mode_off<N>(v, k, b)];
 #pragma unroll
-            for (int b = 0; b < N; ++b) m[v][a * N + b] = u[base + mode_off<N>(v, a, b)];
-    const double r0 = m[0][0];
-    double pbar = r0;
-    if (NV == 4 && adiabatic) pbar = gm1 * (m[3][0] - 0.5 * (m[1][0] * m[1][0] + m[2][0] * m[2][0]) / r0);
-    if (!(r0 > 0.0) || !(pbar > 0.0)) return false;
+        for (int r = 0; r < N; ++r) {
+            double c = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) c = fma(Ua[b], G.phi[b][r], c);
+            S[(v * N + k) * N + r] = c;
+        }
+#pragma unroll
+        for (int r = 0; r < L; ++r) {
+            double c = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) c = fma(Ua[b], Lb.phi[b][r], c);
+            S[SA + (v * N + k) * L + r] = c;
+        }
+        if (k == 0) S[SA + SB + v] = Ua[0];  // the mean
+    }
+    __syncthreads();
+    double M[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) M[v] = S[SA + SB + v];
+    const bool adi = NV == 4 && g.closure == 2;
+    const double gm1 = g.gamma - 1.0;
+    double pbar = M[0];
+    if (adi) pbar = gm1 * (M[3] - 0.5 * (M[1] * M[1] + M[2] * M[2]) / M[0]);
+    const bool admissible = M[0] > 0.0 && pbar > 0.0;
     double eps = e0;
-    if (r0 < eps) eps = r0;
-    if (NV == 4 && adiabatic && pbar < eps) eps = pbar;
+    if (M[0] < eps) eps = M[0];
+    if (adi && pbar < eps) eps = pbar;
+    // basis values phi_a(x_k) at this lane's Lobatto and Gauss x
+    double pl[N], pg[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        double x = Lb.phi[a][0], y = G.phi[a][0];
+#pragma unroll
+        for (int m = 1; m < N; ++m) {
+            if (m < L) x = k == m ? Lb.phi[a][m] : x;
+            y = k == m ? G.phi[a][m] : y;
+        }
+        pl[a] = x;
+        pg[a] = y;
+    }
+    const bool hasA = k < L;
+    // value of variable v at this lane's test point p (p < N: (Lobatto x_k,
+    // Gauss eta_p); else (Gauss x_k, Lobatto eta_{p-N}))
+    auto point = [&](int v, int p) {
+        double s2 = 0.0;
+        if (p < N) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) s2 = fma(pl[a], S[(v * N + a) * N + p], s2);
+        } else {
+#pragma unroll
+            for (int a = 0; a < N; ++a) s2 = fma(pg[a], S[SA + (v * N + a) * L + (p - N)], s2);
+        }
+        return s2;
+    };
+    double rho[NP];
     double rmin = INFINITY;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) rmin = fmin(rmin, pp_point<N>(m[0], k));
-    bool changed = false;
-    if (rmin < eps) {
-        th1 = (r0 - eps) / (r0 - rmin);
-#pragma unroll
-        for (int x = 1; x < NN; ++x) m[0][x] *= th1;
-        changed = true;
+    for (int p = 0; p < NP; ++p) {
+        rho[p] = point(0, p);
+        if (p >= N || hasA) rmin = fmin(rmin, rho[p]);
     }
-    if constexpr (NV == 4) {
-        if (adiabatic) {
+    // element minimum over its N lanes
+    S[SA + SB + NV + k] = rmin;
+    __syncthreads();
+    double emin = INFINITY;
 #pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                double W[4];
+    for (int m = 0; m < N; ++m) emin = fmin(emin, S[SA + SB + NV + m]);
+    double th1 = 1.0, th2 = 1.0;
+    if (admissible && emin < eps) th1 = (M[0] - eps) / (M[0] - emin);
+    if (adi) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) W[v] = pp_point<N>(m[v], k);
-                const double pw = gm1 * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
-                if (!(pw < eps)) continue;
-                double lo = 0.0, hi = 1.0;
-                for (int it = 0; it < 64; ++it) {
-                    const double mid = 0.5 * (lo + hi);
-                    double S[4];
+        for (int p = 0; p < NP; ++p) {
+            if (!admissible || (p < N && !hasA)) continue;
+            double W[4];
+            W[0] = M[0] + th1 * (rho[p] - M[0]);
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) S[v] = m[v][0] + mid * (W[v] - m[v][0]);
-                    const double ps = gm1 * (S[3] - 0.5 * (S[1] * S[1] + S[2] * S[2]) / S[0]);
-                    if (ps >= eps)
-                        lo = mid;
-                    else
-                        hi = mid;
-                }
-                th2 = fmin(th2, lo);
+            for (int v = 1; v < 4; ++v) W[v] = point(v, p);
+            const double pw = gm1 * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+            if (!(pw < eps)) continue;
+            double lo = 0.0, hi = 1.0;
+            for (int it = 0; it < 64; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                double Sm[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Sm[v] = M[v] + mid * (W[v] - M[v]);
+                const double ps = gm1 * (Sm[3] - 0.5 * (Sm[1] * Sm[1] + Sm[2] * Sm[2]) / Sm[0]);
+                if (ps >= eps)
+                    lo = mid;
+                else
+                    hi = mid;
             }
-            if (th2 < 1.0) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int x = 1; x < NN; ++x) m[v][x] *= th2;
-                changed = true;
-            }
+            th2 = fmin(th2, lo);
         }
+        // element minimum over its N lanes (adi is uniform: no divergent barrier)
+        S[SA + SB + NV + N + k] = th2;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < N; ++m) th2 = fmin(th2, S[SA + SB + NV + N + m]);
     }
-    if (changed) {
-        const int v0 = th2 < 1.0 ? NV : 1;  // variables whose modes changed
+    const bool changed = th1 < 1.0 || th2 < 1.0;
+    if (active && changed) {
+        // the row again (from L2) scaled: density by theta1, then every
+        // variable by theta2; the means never change
+        const int v1 = th2 < 1.0 ? NV : 1;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            if (v >= v0) break;
+            if (v >= v1) break;
 #pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-                for (int b = 0; b < N; ++b)
-                    if (a + b > 0) u[base + mode_off<N>(v, a, b)] = m[v][a * N + b];
+            for (int b = 0; b < N; ++b) {
+                if (k == 0 && b == 0) continue;
+                const unsigned idx = base + mode_off<N>(v, k, b);
+                double x = u[idx];
+                if (v == 0) x *= th1;
+                x *= th2;
+                u[idx] = x;
+            }
         }
     }
-    return changed;
+    if (active && k == 0) {
+        const long long e = (long long)j * g.nx + i;
+        if (changed_out) changed_out[e] = changed ? 1 : 0;
+        if (theta_out) {
+            theta_out[2 * e] = th1;
+            theta_out[2 * e + 1] = th2;
+        }
+    }
 }
 
 // mode: 0 = flags from the modal-decay sensor (s > s0), 1 = flags given,
@@ -158,7 +214,7 @@ __device__ bool pp_scale(double* u, unsigned base, bool adiabatic, double gm1, d
 // scaling on every element.  Outputs (each may be NULL): flag[e],
 // changed[e] (a mode changed), sensor[e] (log10 of the top-degree density
 // energy share), theta[2e], theta[2e+1] (the positivity factors).
-template <int N, int NV, bool PP>
+template <int N, int NV>
 __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const double* __restrict__ u0, double s0,
                                                   int mode, int apply, const unsigned char* __restrict__ flag_in,
                                                   unsigned char* flag_out, unsigned char* changed_out,
@@ -212,14 +268,6 @@ __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const 
                         if (a == 0 && b == 0) continue;
                         u[base + mode_off<N>(v, a, b)] = (a == 1 && b == 0) ? sx[v] / r3 : (a == 0 && b == 1) ? sy[v] / r3 : 0.0;
                     }
-        }
-    }
-    if (PP && apply) {
-        double t1, t2;
-        if (pp_scale<N, NV>(u, base, g.closure == 2, g.gamma - 1.0, g.pp_eps, t1, t2)) changed = true;
-        if (theta_out) {
-            theta_out[2 * e] = t1;
-            theta_out[2 * e + 1] = t2;
         }
     }
     if (changed_out) changed_out[e] = changed ? 1 : 0;
@@ -573,12 +621,17 @@ hipError_t launch_troubled(int n, int nvar, const Geo& g, double* u, const doubl
                            const unsigned char* flag_in, unsigned char* flag_out, unsigned char* changed_out,
                            float* sensor_out, int pp, double* theta_out, hipStream_t s) {
     const int blocks = (int)((g.E + 255) / 256);
-    if (pp) {
-        DGL_DISPATCH(n, nvar, hipLaunchKernelGGL((k_troubled<NT, VT, true>), dim3(blocks), dim3(256), 0, s, g, u, u0, s0,
-                                                 mode, apply, flag_in, flag_out, changed_out, sensor_out, theta_out));
-    } else {
-        DGL_DISPATCH(n, nvar, hipLaunchKernelGGL((k_troubled<NT, VT, false>), dim3(blocks), dim3(256), 0, s, g, u, u0,
-                                                 s0, mode, apply, flag_in, flag_out, changed_out, sensor_out, theta_out));
+    // flags and minmod (skipped when there are no flags), then the positivity
+    // scaling with N lanes per element
+    if (mode != 2 || !pp) {
+        DGL_DISPATCH(n, nvar, hipLaunchKernelGGL((k_troubled<NT, VT>), dim3(blocks), dim3(256), 0, s, g, u, u0,
+                                                 s0, mode, apply, flag_in, flag_out, pp ? nullptr : changed_out,
+                                                 sensor_out, nullptr));
+    }
+    if (pp && apply) {
+        const int tiles = g.tiles_x * g.ny;
+        DGL_DISPATCH(n, nvar, hipLaunchKernelGGL((k_pp_c<NT, VT>), dim3(tiles), dim3(64), 0, s, g, u, g.pp_eps,
+                                                 changed_out, theta_out));
     }
     return hipGetLastError();
 }

@@ -76,7 +76,7 @@ CASES = [
     ("ring_p1", W.disc_ring(nx=64, order=2).replace(ny=48), "disc_ring"),
     # the paper's own adiabatic disc (Sec. 5.1); p0 = 2.5e-3 needs >= 20
     # elements across the box for positive projected pressures
-    ("paper_disc_p4", W.paper_disc(nx=36, order=5, q=1e-3).replace(ny=30), "paper_disc"),
+    ("paper_disc_p4", W.paper_disc(nx=36, order=5, q=1e-3, positivity=0).replace(ny=30), "paper_disc"),
 ]
 
 
@@ -102,7 +102,7 @@ def test_projection_and_rhs_parity(name, cfg, kind):
     ("wave_p4", W.wave(nx=40, order=5).replace(ny=12), "wave", 3),
     ("disc_p4_damped", W.disc(nx=26, order=5, q=1e-3), "disc", 3),
     ("ring_p3", W.disc_ring(nx=40, order=4), "disc_ring", 3),
-    ("paper_disc_p4_damped", W.paper_disc(nx=36, order=5, q=1e-3), "paper_disc", 3),
+    ("paper_disc_p4_damped", W.paper_disc(nx=36, order=5, q=1e-3, positivity=0), "paper_disc", 3),
 ])
 def test_rk_steps_parity(name, cfg, kind, nsteps):
     T = torch()

@@ -190,3 +190,32 @@ def test_default_eps_run_stays_admissible():
     assert rmin >= -1e-12 and pmin >= -1e-12
     assert means[0].min() < 0.1  # the near-vacuum did open
     h.close()
+
+
+def test_paper_disc_with_positivity_steps_match():
+    """The paper's adiabatic disc (Sec. 5.1) as it runs, with the positivity
+    limiter behind every stage and after the damping: three CFL steps against
+    the oracle's limited steps (no minmod)."""
+    T = torch()
+    cfg = W.paper_disc(nx=36, order=5, q=1e-3).replace(ny=34)
+    oc = ocfg(cfg)
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, "paper_disc", x=x, y=y)
+    h, u = dg.dg_init(cfg, prim)
+    uo, ch, _ = O.positivity(oc, O.project(oc, prim))
+    print(f"[paper disc] {int(ch.sum())} of {cfg.n_elem} elements limited at t = 0", flush=True)
+    assert relerr(planes(cfg, u), uo) <= 1e-13
+    u0 = uo.copy()
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    t = 0.0
+    for k in range(3):
+        dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
+        uo, dto = O.step_limited(oc, uo, t, 0.0, u0, math.inf)
+        t += dto
+        dg.dg_sync(h)
+        err = relerr(planes(cfg, u), uo)
+        print(f"[paper disc] step {k}: rel err {err:.3e}, dt {dt_dev.item():.6e} vs {dto:.6e}", flush=True)
+        assert abs(dt_dev.item() - dto) <= 1e-13 * dto
+        assert err <= 1e-12
+    h.close()
