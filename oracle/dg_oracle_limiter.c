@@ -18,6 +18,7 @@ void or_indicator(const or_cfg *c, const double *u, double *s)
 {
     long E = (long)c->nx * c->ny;
     int n = c->n, p = c->n - 1;
+    #pragma omp parallel for schedule(static)
     for (long e = 0; e < E; ++e) {
         double top = 0.0, all = 0.0;
         for (int a = 0; a < n; ++a)
@@ -59,6 +60,7 @@ void or_minmod(const or_cfg *c, double *u, const double *u0, const unsigned char
     int n = c->n, nn = n * n, nv = c->nvar;
     const double r3 = sqrt(3.0);
     /* means are never modified, so neighbours may be read from u in place */
+    #pragma omp parallel for schedule(static)
     for (long e = 0; e < E; ++e) {
         changed[e] = 0;
         if (!flag[e]) continue;
@@ -138,6 +140,7 @@ void or_positivity(const or_cfg *c, double *u, unsigned char *changed, double *t
             py[k] = xl[r];
             ++k;
         }
+    #pragma omp parallel for schedule(static)
     for (long e = 0; e < E; ++e) {
         double M[4];
         for (int v = 0; v < nv; ++v) M[v] = u[((long)v * nn) * E + e];

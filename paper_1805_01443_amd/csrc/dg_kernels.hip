@@ -1054,15 +1054,16 @@ __global__ void __launch_bounds__(256) k_step_begin(const Geo g, StepBlock* sb, 
                                                     const unsigned int* __restrict__ bad_part, int nblk,
                                                     double* t_dev, double dt_fixed, double* dt_used, int nst) {
     const double dtmin = reduce_dt_partials(dt_part, bad_part, nblk, sb);
-    if (threadIdx.x != 0) return;
     const double t = *t_dev;
+    __syncthreads();  // every thread has read t^n before thread 0 advances it
     const double dt = dt_fixed > 0.0 ? dt_fixed : dtmin;
-    const bool two = nst == 2;
-    const double cst[3] = {0.0, 1.0, 0.5};
-    const double a0[3] = {0.0, two ? 0.5 : 0.75, 1.0 / 3.0};
-    const double a1[3] = {1.0, two ? 0.5 : 0.25, 2.0 / 3.0};
-    const double a2[3] = {1.0, two ? 0.5 : 0.25, 2.0 / 3.0};
-    for (int s = 0; s < nst; ++s) {
+    const int s = threadIdx.x;  // one thread per stage (the planet positions in parallel)
+    if (s < nst) {
+        const bool two = nst == 2;
+        const double cst[3] = {0.0, 1.0, 0.5};
+        const double a0[3] = {0.0, two ? 0.5 : 0.75, 1.0 / 3.0};
+        const double a1[3] = {1.0, two ? 0.5 : 0.25, 2.0 / 3.0};
+        const double a2[3] = {1.0, two ? 0.5 : 0.25, 2.0 / 3.0};
         StageCoeffs c;
         c.t = t + cst[s] * dt;
         planet_at(g, c.t, c.xp, c.yp);
@@ -1073,8 +1074,10 @@ __global__ void __launch_bounds__(256) k_step_begin(const Geo g, StepBlock* sb, 
         c.pad = 0.0;
         sb->st[s] = c;
     }
-    *t_dev = t + dt;
-    if (dt_used) *dt_used = dt;
+    if (s == 0) {
+        *t_dev = t + dt;
+        if (dt_used) *dt_used = dt;
+    }
 }
 
 // Butcher-form step: stage times and planet positions, k_i = L(y_i)

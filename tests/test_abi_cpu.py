@@ -63,6 +63,11 @@ def dataclass_fields(cfg):
     (dict(q=-1.0), dg.DG_EINVAL),
     (dict(rk=7), dg.DG_EINVAL),
     (dict(rk=dg.RK_CASHKARP, limiter=dg.LIMITER_MODAL_DECAY), dg.DG_EUNSUPPORTED),
+    (dict(positivity=2), dg.DG_EINVAL),
+    (dict(positivity=1, rk=dg.RK_SSP22), dg.DG_EUNSUPPORTED),
+    (dict(pp_eps=-1.0), dg.DG_EINVAL),
+    (dict(pp_eps=float("nan")), dg.DG_EINVAL),
+    (dict(bc=3), dg.DG_EINVAL),
 ])
 def test_init_rejects_bad_configs_without_a_device(bad, code):
     cfg = W.wave(nx=8).replace(**bad)

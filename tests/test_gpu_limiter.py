@@ -221,3 +221,30 @@ def test_fused_learned_flags_match_features_then_forward():
     print(f"[fused flags] {int(ref.sum())} of {E} flagged", flush=True)
     assert np.array_equal(got, ref)
     h.close()
+
+
+def test_full_size_ring_limited_step_parity():
+    """The benchmark's limited form at its full size (ring, 1024 x 1024, order
+    4, modal-decay indicator + minmod + positivity limiter): the projected and
+    limited initial state and one CFL step against the oracle."""
+    import math
+    from paper_1805_01443_amd import learned
+    T = torch()
+    cfg = learned.ring_config(1024)
+    oc = ocfg(cfg)
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, "disc_ring", seed=0, x=x, y=y)
+    print("[full ring] 1024x1024 order 4 adiabatic, limited, one step", flush=True)
+    h, u = dg.dg_init(cfg, prim)
+    dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
+    dg.dg_sync(h)
+    uo, _, _ = O.positivity(oc, O.project(oc, prim))
+    uo, dto = O.step_limited(oc, uo, 0.0, 0.0, uo.copy(), cfg.limiter_s0)
+    assert abs(dt_dev.item() - dto) <= 1e-14 * dto
+    a = planes(cfg, u)
+    err = max(np.max(np.abs(a[v] - uo[v])) / np.max(np.abs(uo[v])) for v in range(cfg.nvar))
+    print(f"  rel err {err:.3e}", flush=True)
+    assert err <= 1e-12
+    h.close()
