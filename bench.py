@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--no-limited", action="store_true", help="skip the modal vs learned limiter comparison")
+    ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU-share (1024 x 128 strip) run")
     ap.add_argument("--ring-nx", type=int, default=1024)
     ap.add_argument("--ring-steps", type=int, default=200)
     ap.add_argument("--seed", type=int, default=None,
@@ -215,6 +216,28 @@ def run_limited(a):
     return out
 
 
+def run_shard(a, order):
+    """One GPU's share of the 1024^2 disc split into eight strips of 1024 x 128
+    elements: the strip y in [0, 0.625] (the planet's orbit crosses it), run
+    alone with fixed-initial edges standing in for the neighbours' halo.  Same
+    kernels, same element size as the 1024^2 disc."""
+    from paper_1805_01443_amd import configs as W
+    base = W.disc(nx=1024, order=order)
+    cfg = base.replace(ny=128, y0=0.0, y1=(base.y1 - base.y0) / 8)
+    r = run_disc(cfg, W.prim_for(cfg, "disc"), a.steps, a.warmup, profile=True)
+    state_bytes = cfg.nvar * order ** 2 * cfg.n_elem * 8
+    avg = r["stage_ms"] / 1e3 / max(r["launches"], 1)
+    ach = state_bytes * 8.0 / 3.0 / avg / 1e9
+    dofs = cfg.n_elem * order ** 2
+    return {"workload": f"disc1024_strip128_p{order - 1}_fp64", "nx": cfg.nx, "ny": cfg.ny,
+            "y_range": [cfg.y0, cfg.y1], "dofs": dofs,
+            "value": dofs * 3 * a.steps / r["elapsed"], "unit": "DOF-stage/s",
+            "ms_per_step": r["elapsed"] * 1e3 / a.steps, "stage_kernel_us": avg * 1e6,
+            "hbm_GBps_alg": ach, "hbm_frac": ach / HBM_PEAK_GBPS,
+            "note": "one of eight 1024x128 strips of the 1024^2 disc on one GPU; no halo exchange "
+                    "(fixed-initial strip edges)"}
+
+
 def disc_workload(a, order):
     from paper_1805_01443_amd import configs as W
     if a.seed is None:
@@ -313,6 +336,8 @@ def main():
                       "note": "FP32 deviation arithmetic about the projected equilibrium; FP64 state, "
                               "stage combination, damping, dt and torque"}}
     del r64
+    if not a.no_shard:
+        out.setdefault("forms", {})["shard"] = run_shard(a, cfg.order)
     if not a.no_limited:
         out.setdefault("forms", {})["limited"] = run_limited(a)
     if not a.no_cpu_baseline:

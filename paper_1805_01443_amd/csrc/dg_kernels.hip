@@ -102,28 +102,6 @@ __device__ __forceinline__ double cs2_loc(const Geo& g, double r2, double ir) {
     return g.h2gm * (r2 > g.rc2 ? ir : g.irc);
 }
 
-// gradient of the stellar (harmonic core inside r_core, point mass outside)
-// plus softened planet potential
-__device__ __forceinline__ void grad_phi(const Geo& g, double x, double y, double xp, double yp,
-                                         double& gx, double& gy) {
-    gx = 0.0;
-    gy = 0.0;
-    if (g.star) {
-        const double r2 = x * x + y * y;
-        const double r = sqrt(r2);
-        const double k = r < g.r_core ? g.rc3inv : g.gm / (r2 * r);
-        gx = k * x;
-        gy = k * y;
-    }
-    if (g.q > 0.0) {
-        const double dx = x - xp, dy = y - yp;
-        const double d2 = dx * dx + dy * dy + g.eps2;
-        const double k = g.q / (d2 * sqrt(d2));
-        gx += k * dx;
-        gy += k * dy;
-    }
-}
-
 // Rusanov flux through an axis-aligned edge with outward normal SGN * e_AX
 template <int CL, int AX, int SGN>
 __device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const double* Uo, double x,
@@ -192,18 +170,25 @@ __device__ __forceinline__ double pick(const double (&t)[kMaxOrder], int k) {
 // out = a0 u^n + a1 u + a2 L(u, t), with the N lanes of an element sharing
 // its tensor-product contractions.  Lane (s, k): element slot s = lane / N of
 // the wave (EW = 64 / N consecutive elements of one row), index k = lane % N.
-// Transposes between the lanes of an element go through LDS:
+// Transposes between the lanes of an element go through LDS, single values
+// per lane through lane permutes:
 //   phase 1, k = mode row a: own row u[v][a][.] -> C[v][a][r] = sum_b u[v][a][b]
-//            phi_b(eta_r); y collapses of the own row (both sides) and of the y
-//            neighbours' rows, x collapses of the x neighbours' columns;
-//   phase 2, k = Gauss row r: node values at (xi_q, eta_r) for every q, the
-//            physical flux and source, partial projections
-//            X[r][a] = sum_q w_q (2/dx phi_a'(q) f_x + phi_a(q) s),
-//            Y[r][a] = sum_q w_q phi_a(q) (2/dy) f_y; traces at point k of the
-//            four edges and their Rusanov fluxes; the west/east lifts, which
-//            carry the same weight w_r phi_b(eta_r) in R, are folded into X;
-//   phase 3, k = mode row a: R[a][b] = sum_r w_r (phi_b(r) X[r][a] + phi_b'(r)
-//            Y[r][a]) minus the south/north lifts; stage combination of row a.
+//            phi_b(eta_r) (LDS); y collapses of the own row (both sides) and of
+//            the y neighbours' rows, x collapses of the x neighbours' columns
+//            (registers; an x neighbour in the same wave hands over the
+//            collapse of its own column, so only the first and the last
+//            element of a wave read a neighbour's column);
+//   phase 2, k = Gauss row r: traces at point k of the four edges (the
+//            collapses of the element's rows a gathered from its lanes) and
+//            their Rusanov fluxes; the west/east lifts, which carry the same
+//            weight w_r phi_b(eta_r) in R as the x projection, start X; node
+//            values at (xi_q, eta_r) for every q, the physical flux and source,
+//            partial projections X[r][a] += sum_q w_q (2/dx phi_a'(q) f_x +
+//            phi_a(q) s), Y[r][a] = sum_q w_q phi_a(q) (2/dy) f_y;
+//   phase 3, k = mode row a: R[a][b] = sum_r w_r phi_b(r) X[r][a] minus the
+//            south/north lifts, plus sum_r w_r phi_b'(r) Y[r][a] (X and Y pass
+//            through the same LDS slot one after the other, which keeps the
+//            slot at C plus two flux rows); stage combination of row a.
 // Every integral is the same Gauss sum as in eq. (3); the density volume term
 // is taken by quadrature (exact for its polynomial integrand).
 template <int N, int CL>
@@ -215,9 +200,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
     constexpr BasisTab B = make_basis(N);
-    constexpr int P1 = NV * NN + 6 * NV * N;      // C, six collapse vectors
-    constexpr int P2 = 2 * NV * NN + 2 * NV * N;  // X (with the west/east lifts), Y, south/north fluxes
-    constexpr int SLOT = lds_slot(P1 > P2 ? P1 : P2, N);
+    constexpr int SLOT = lds_slot(NV * NN + 2 * NV * N, N);  // C, later X then Y; south/north fluxes
     __shared__ double lds[EW * SLOT];
 
     const int lane = threadIdx.x;
@@ -231,6 +214,11 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     const bool active = sl < EW && i0 + sl < g.nx;
     const int i = active ? i0 + sl : i0;  // idle lanes shadow a valid element and store nothing
     double* S = lds + (own ? sl : 0) * SLOT;
+    const int l0 = (own ? sl : 0) * N;  // lane of index 0 of the element
+    // The x neighbours inside the wave hand over their x collapses by lane
+    // permute; only the first slot (west) and the last slot or the end of the
+    // row (east) read the neighbour's column from memory.
+    const bool gw = l0 == 0, ge = l0 == (EW - 1) * N || i + 1 >= g.nx;
 
     const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
     const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), rout = make_rsrc(out), run = make_rsrc(un);
@@ -242,8 +230,9 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
 
     // ---- phase 1: k = mode row.  Every global load of the phase is issued
-    // before the first use: the own row k, the y neighbours' rows k and the x
-    // neighbours' columns k (at a fixed box edge the own initial row/column).
+    // before the first use: the own row k, the y neighbours' rows k and, where
+    // the x neighbour is outside the wave, its column k (periodic wrap; at a
+    // box edge that is not periodic the collapse is replaced afterwards).
     int il = i - 1, ir = i + 1, jb = j - 1, jt = j + 1;
     const bool ol = il < 0, orr = ir >= g.nx, ob = jb < 0, ot = jt >= g.ny;
     il += ol ? g.nx : 0;
@@ -253,47 +242,43 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     // box edges that are not periodic: the exterior is the element's own
     // initial row/column (fixed edge) or a ghost with no gradient, the
     // element's own current mean (gradient-free edge: only mode (0, 0), held by
-    // lane k = 0 as Ua[v][0])
+    // lane k = 0 as Ua[v][0]); either one enters as its trace on the shared edge
     const bool fxd = g.bc != 0, fl = fxd && ol, fr = fxd && orr, fb = fxd && ob, ft = fxd && ot;
     const bool gfree = g.bc == 2;
+    const bool wfy = __any(fb || ft), wfx = __any(fl || fr);  // wave-uniform
     const unsigned vcol = (eb + k * N * EW) * 8u;  // mode (0, k)
     const unsigned vb = (tiled_base<N, NV>(g, i, jb) + k * EW) * 8u, vt = (tiled_base<N, NV>(g, i, jt) + k * EW) * 8u;
     const unsigned vl = (tiled_base<N, NV>(g, il, j) + k * N * EW) * 8u;
     const unsigned vr = (tiled_base<N, NV>(g, ir, j) + k * N * EW) * 8u;
-    double Ua[NV][N], Xb[NV][N], Xt[NV][N], Xl[NV][N], Xr[NV][N];
+    double Ua[NV][N], Xb[NV][N], Xt[NV][N], Xo[NV][N], Xn[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int m = 0; m < N; ++m) {
-            const unsigned srow = (unsigned)(v * N + m) * RS, scol = (unsigned)(v * NN + m) * CS;
+            const unsigned srow = (unsigned)(v * N + m) * RS;
             Ua[v][m] = ld64(ru, vrow, srow);
             Xb[v][m] = ld64(ru, vb, srow);
             Xt[v][m] = ld64(ru, vt, srow);
-            Xl[v][m] = ld64(ru, vl, scol);
-            Xr[v][m] = ld64(ru, vr, scol);
         }
-    if (__any(fb || ft)) {  // wave-uniform: waves on a fixed bottom/top box edge
+    // x columns: Xo the own column k (its x collapses go to the x neighbours
+    // in the wave), Xn the neighbour's column k where that neighbour is
+    // outside the wave (west for the first slot, east for the last slot or
+    // the row end); a lane with both neighbours outside (a row ending after
+    // the first slot) takes the east one as Xo.  Lanes without such a
+    // neighbour read their own column twice (cached lines, values unused).
+    // No branch: these loads stay in flight with the others.
+    const bool gwe = gw && ge;
+    const unsigned vo = gwe ? vr : vcol, vn = gw ? vl : (ge ? vr : vcol);
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const double o = gfree ? ((k == 0 && m == 0) ? Ua[v][0] : 0.0)
-                                       : ld64(ru0, vrow, (unsigned)(v * N + m) * RS);
-                Xb[v][m] = fb ? o : Xb[v][m];
-                Xt[v][m] = ft ? o : Xt[v][m];
-            }
-    }
-    if (__any(fl || fr)) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const double o = gfree ? ((k == 0 && m == 0) ? Ua[v][0] : 0.0)
-                                       : ld64(ru0, vcol, (unsigned)(v * NN + m) * CS);
-                Xl[v][m] = fl ? o : Xl[v][m];
-                Xr[v][m] = fr ? o : Xr[v][m];
-            }
-    }
+        for (int m = 0; m < N; ++m) {
+            const unsigned scol = (unsigned)(v * NN + m) * CS;
+            Xo[v][m] = ld64(ru, vo, scol);
+            Xn[v][m] = ld64(ru, vn, scol);
+        }
+    // row k's collapses: own south / north, exterior south / north / west / east
+    double Tm[NV], Tp[NV], Tb[NV], Tt[NV], Tl[NV], Tr[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
@@ -303,36 +288,67 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             for (int b = 0; b < N; ++b) c += Ua[v][b] * B.phi[b][r];
             S[(v * N + k) * N + r] = c;
         }
-        // own y collapses; exterior collapses with the neighbour's far side or,
-        // at a fixed box edge, the element's near side.  phi_m(-1) =
+        // the exterior collapses take the neighbour's far side.  phi_m(-1) =
         // (-1)^m phi_m(1): even and odd partial sums give either side.
-        double ue = 0.0, uo = 0.0, be = 0.0, bo = 0.0, te = 0.0, to = 0.0, le = 0.0, lo = 0.0, re = 0.0,
-               ro = 0.0;
+        double ue = 0.0, uo = 0.0, be = 0.0, bo = 0.0, te = 0.0, to = 0.0, ce = 0.0, co = 0.0, ne = 0.0,
+               no = 0.0;
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             if (m % 2 == 0) {
                 ue += B.pp[m] * Ua[v][m];
                 be += B.pp[m] * Xb[v][m];
                 te += B.pp[m] * Xt[v][m];
-                le += B.pp[m] * Xl[v][m];
-                re += B.pp[m] * Xr[v][m];
+                ce += B.pp[m] * Xo[v][m];
+                ne += B.pp[m] * Xn[v][m];
             } else {
                 uo += B.pp[m] * Ua[v][m];
                 bo += B.pp[m] * Xb[v][m];
                 to += B.pp[m] * Xt[v][m];
-                lo += B.pp[m] * Xl[v][m];
-                ro += B.pp[m] * Xr[v][m];
+                co += B.pp[m] * Xo[v][m];
+                no += B.pp[m] * Xn[v][m];
             }
         }
-        const double tm = ue - uo, tp = ue + uo;
-        const double tb = be + (fb ? -bo : bo), tt = te - (ft ? -to : to);
-        const double sl2 = le + (fl ? -lo : lo), sr = re - (fr ? -ro : ro);
-        S[NV * NN + (0 * NV + v) * N + k] = tm;
-        S[NV * NN + (1 * NV + v) * N + k] = tp;
-        S[NV * NN + (2 * NV + v) * N + k] = tb;
-        S[NV * NN + (3 * NV + v) * N + k] = tt;
-        S[NV * NN + (4 * NV + v) * N + k] = sl2;
-        S[NV * NN + (5 * NV + v) * N + k] = sr;
+        Tm[v] = ue - uo;
+        Tp[v] = ue + uo;
+        Tb[v] = be + bo;
+        Tt[v] = te - to;
+        // ce +- co: east / west side of column Xo, ne +- no: of column Xn.
+        // A neighbour in the wave hands over the side of its own column that
+        // faces this element.
+        const double from_w = __shfl(ce + co, lane >= N ? lane - N : lane);
+        const double from_e = __shfl(ce - co, lane + N < 64 ? lane + N : lane);
+        Tl[v] = gw ? ne + no : from_w;
+        Tr[v] = ge ? (gwe ? ce - co : ne - no) : from_e;
+        // box edges: the element's own initial row/column (or the ghost) on the
+        // near side
+        if (wfy) {
+            double e = 0.0, o = 0.0;
+            if (gfree) {
+                e = k == 0 ? B.pp[0] * Ua[v][0] : 0.0;
+            } else {
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const double w = B.pp[m] * ld64(ru0, vrow, (unsigned)(v * N + m) * RS);
+                    if (m % 2 == 0) e += w; else o += w;
+                }
+            }
+            Tb[v] = fb ? e - o : Tb[v];
+            Tt[v] = ft ? e + o : Tt[v];
+        }
+        if (wfx) {
+            double e = 0.0, o = 0.0;
+            if (gfree) {
+                e = k == 0 ? B.pp[0] * Ua[v][0] : 0.0;
+            } else {
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const double w = B.pp[m] * ld64(ru0, vcol, (unsigned)(v * NN + m) * CS);
+                    if (m % 2 == 0) e += w; else o += w;
+                }
+            }
+            Tl[v] = fl ? e - o : Tl[v];
+            Tr[v] = fr ? e + o : Tr[v];
+        }
     }
     __syncthreads();
 
@@ -347,14 +363,79 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int a = 0; a < N; ++a) Cc[v][a] = S[(v * N + a) * N + k];
+    // edge traces at point k and their fluxes (outward normals); a collapse of
+    // row a is held by lane l0 + a
+    double* H = S + NV * NN;  // south / north fluxes [edge][v][point]
     double X[NV][N], Y[NV][N];
+    {
+        double Ui[NV], Uo[NV], hw[NV], he[NV], hs[NV];
+        // west / east: own traces from C, exterior from the x collapses
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NV; ++v) {
+            double si = 0.0, so = 0.0;
 #pragma unroll
-        for (int a = 0; a < N; ++a) {
-            X[v][a] = 0.0;
-            Y[v][a] = 0.0;
+            for (int a = 0; a < N; ++a) {
+                si += B.pm[a] * Cc[v][a];
+                so += phk[a] * __shfl(Tl[v], l0 + a);
+            }
+            Ui[v] = si;
+            Uo[v] = so;
         }
+        rusanov<CL, 0, -1>(g, Ui, Uo, xc - 0.5 * g.dx, yk, hw);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double si = 0.0, so = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += B.pp[a] * Cc[v][a];
+                so += phk[a] * __shfl(Tr[v], l0 + a);
+            }
+            Ui[v] = si;
+            Uo[v] = so;
+        }
+        rusanov<CL, 0, 1>(g, Ui, Uo, xc + 0.5 * g.dx, yk, he);
+        // west/east lifts of row r enter R[a][b] with the same weight
+        // w_r phi_b(eta_r) as X[r][a]: X[r][a] = -(1/dx)(phi_a(-1) h_W + phi_a(1) h_E)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double hp = g.idx * (he[v] + hw[v]), hm = g.idx * (he[v] - hw[v]);
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                X[v][a] = -(B.pp[a] * ((a & 1) ? hm : hp));
+                Y[v][a] = 0.0;
+            }
+        }
+        const double xk = xc + 0.5 * g.dx * xik;
+        // south / north: own and exterior traces from the y collapses
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double si = 0.0, so = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += phk[a] * __shfl(Tm[v], l0 + a);
+                so += phk[a] * __shfl(Tb[v], l0 + a);
+            }
+            Ui[v] = si;
+            Uo[v] = so;
+        }
+        rusanov<CL, 1, -1>(g, Ui, Uo, xk, yc - 0.5 * g.dy, hs);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) H[(0 * NV + v) * N + k] = hs[v];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double si = 0.0, so = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                si += phk[a] * __shfl(Tp[v], l0 + a);
+                so += phk[a] * __shfl(Tt[v], l0 + a);
+            }
+            Ui[v] = si;
+            Uo[v] = so;
+        }
+        rusanov<CL, 1, 1>(g, Ui, Uo, xk, yc + 0.5 * g.dy, hs);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) H[(1 * NV + v) * N + k] = hs[v];
+    }
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         double W[NV];
@@ -417,83 +498,11 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             }
         }
     }
-    // edge traces at point k and their fluxes (outward normals)
-    double hf[4][NV];
-    {
-        const double* Cl = S + NV * NN;
-        double Ui[NV], Uo[NV];
-        // west / east: own traces from C, exterior from the x collapses
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double si = 0.0, so = 0.0;
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                si += B.pm[a] * Cc[v][a];
-                so += phk[a] * Cl[(4 * NV + v) * N + a];
-            }
-            Ui[v] = si;
-            Uo[v] = so;
-        }
-        rusanov<CL, 0, -1>(g, Ui, Uo, xc - 0.5 * g.dx, yk, hf[0]);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double si = 0.0, so = 0.0;
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                si += B.pp[a] * Cc[v][a];
-                so += phk[a] * Cl[(5 * NV + v) * N + a];
-            }
-            Ui[v] = si;
-            Uo[v] = so;
-        }
-        rusanov<CL, 0, 1>(g, Ui, Uo, xc + 0.5 * g.dx, yk, hf[1]);
-        // west/east lifts of row r enter R[a][b] with the same weight
-        // w_r phi_b(eta_r) as X[r][a]: X[r][a] -= (1/dx)(phi_a(-1) h_W + phi_a(1) h_E)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double hp = g.idx * (hf[1][v] + hf[0][v]), hm = g.idx * (hf[1][v] - hf[0][v]);
-#pragma unroll
-            for (int a = 0; a < N; ++a) X[v][a] -= B.pp[a] * ((a & 1) ? hm : hp);
-        }
-        const double xk = xc + 0.5 * g.dx * xik;
-        // south / north: own and exterior traces from the y collapses
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double si = 0.0, so = 0.0;
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                si += phk[a] * Cl[(0 * NV + v) * N + a];
-                so += phk[a] * Cl[(2 * NV + v) * N + a];
-            }
-            Ui[v] = si;
-            Uo[v] = so;
-        }
-        rusanov<CL, 1, -1>(g, Ui, Uo, xk, yc - 0.5 * g.dy, hf[2]);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double si = 0.0, so = 0.0;
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                si += phk[a] * Cl[(1 * NV + v) * N + a];
-                so += phk[a] * Cl[(3 * NV + v) * N + a];
-            }
-            Ui[v] = si;
-            Uo[v] = so;
-        }
-        rusanov<CL, 1, 1>(g, Ui, Uo, xk, yc + 0.5 * g.dy, hf[3]);
-    }
-    __syncthreads();
+    __syncthreads();  // every lane has read C
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int a = 0; a < N; ++a) {
-            S[((0 * NV + v) * N + k) * N + a] = X[v][a];
-            S[((1 * NV + v) * N + k) * N + a] = Y[v][a];
-        }
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) S[2 * NV * NN + (f * NV + v) * N + k] = hf[2 + f][v];
+        for (int a = 0; a < N; ++a) S[((v * N + k) * N + a)] = X[v][a];
     __syncthreads();
 
     // ---- phase 3: k = mode row a
@@ -504,20 +513,6 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
         for (int m = 1; m < N; ++m) r = k == m ? B.wphi[m][q] : r;
         wrow[q] = r;
-    }
-    const double* H = S + 2 * NV * NN;
-    // the row's u and u^n, issued before any store (out may alias u^n, so a
-    // load after a store could not be moved ahead of it); u comes back from L2
-    double U1[NV][N], Un[NV][N];
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int b = 0; b < N; ++b) U1[v][b] = ld64(ru, vrow, (unsigned)(v * N + b) * RS);
-    if (a0 != 0.0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int b = 0; b < N; ++b) Un[v][b] = ld64(run, vrow, (unsigned)(v * N + b) * RS);
     }
     double R[NV][N];
 #pragma unroll
@@ -532,12 +527,42 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         for (int b = 0; b < N; ++b) {
             double acc = 0.0;
 #pragma unroll
-            for (int r = 0; r < N; ++r)
-                acc += B.wphi[b][r] * S[((0 * NV + v) * N + r) * N + k] + B.wdphi[b][r] * S[((1 * NV + v) * N + r) * N + k];
-            acc -= g.idy * (B.pm[b] * glb + B.pp[b] * glt);
-            R[v][b] = acc;
+            for (int r = 0; r < N; ++r) acc += B.wphi[b][r] * S[((v * N + r) * N + k)];
+            R[v][b] = acc - g.idy * (B.pm[b] * glb + B.pp[b] * glt);
         }
     }
+    __syncthreads();  // every lane has read X
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) S[((v * N + k) * N + a)] = Y[v][a];
+    __syncthreads();
+    // the row's u^n, loaded before any store (out may alias u^n, so a load
+    // after a store could not be moved ahead of it).  With three variables
+    // the row's u stays in registers from phase 1 (reloading it this late
+    // misses L2 for about a third more HBM reads per launch); with four the
+    // registers are not there, and it is reloaded.
+    constexpr bool keep_u = NV == 3;
+    double Un[NV][N], U1[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int b = 0; b < N; ++b) U1[v][b] = keep_u ? Ua[v][b] : ld64(ru, vrow, (unsigned)(v * N + b) * RS);
+    if (a0 != 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) Un[v][b] = ld64(run, vrow, (unsigned)(v * N + b) * RS);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < N; ++r) acc += B.wdphi[b][r] * S[((v * N + r) * N + k)];
+            R[v][b] += acc;
+        }
     if (active) {
         if (a0 != 0.0) {
 #pragma unroll
@@ -1354,73 +1379,101 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
 }
 
 // ------------------------------------------------------------------ torque
-constexpr int kTorqueBlock = 256;
+constexpr int kTorqueWaves = 4;      // tiles per block of the torque kernel
+constexpr int kTorqueFinal = 1024;   // threads of the final sum
 
 // deterministic block sum: fixed xor-butterfly inside each wavefront, then the
-// four wavefront sums in order
-__device__ __forceinline__ double block_sum_256(double s, double* red) {
+// wavefront sums in index order by thread 0 (its return value; other threads
+// get 0)
+template <int WAVES>
+__device__ __forceinline__ double block_sum(double s, double* red) {
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     double r = 0.0;
-    if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < WAVES; ++w) r += red[w];
     return r;
 }
 
+// N lanes per element, one tile (EW = 64 / N elements of a row) per
+// wavefront, four tiles per block: lane k contracts the density row k in y
+// (LDS), then evaluates the nodes (xi_k, eta_r), r < N, and their torque
+// terms; one partial per block, in a fixed lane and wavefront order, so the
+// sum is bitwise reproducible.
 template <int N>
-__global__ void __launch_bounds__(kTorqueBlock) k_torque(const Geo g, double t, const double* t_dev,
-                                                         const double* __restrict__ u, const double* __restrict__ eq,
-                                                         double* __restrict__ partials) {
+__global__ void __launch_bounds__(64 * kTorqueWaves) k_torque(const Geo g, double t, const double* t_dev,
+                                                              const double* __restrict__ u,
+                                                              const double* __restrict__ eq,
+                                                              double* __restrict__ partials) {
     constexpr BasisTab T = make_basis(N);
-    __shared__ double red[4];
+    constexpr int EW = 64 / N;
+    __shared__ double lds[kTorqueWaves][EW * N * N];
     __shared__ double pxy[2];
-    constexpr int NN = N * N;
-    const long long e = (long long)blockIdx.x * kTorqueBlock + threadIdx.x;
-    // the planet position, once per block
+    __shared__ double red[kTorqueWaves];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int sl = lane / N, k = lane - sl * N;
+    const bool own = EW * N == 64 || sl < EW;  // idle lanes shadow slot 0 and add nothing
+    const int tile = blockIdx.x * kTorqueWaves + wv;
+    const bool live = tile < g.tiles_x * g.ny;  // the last block may hold fewer tiles
+    const int j = live ? tile / g.tiles_x : 0;
+    const int i0 = live ? (tile - j * g.tiles_x) * EW : 0;
+    const bool active = live && sl < EW && i0 + sl < g.nx;
+    const int i = active ? i0 + sl : i0;
+    double* S = lds[wv] + (own ? sl : 0) * (N * N);
     if (threadIdx.x == 0) {
         const double tt = t_dev ? *t_dev : t;
         planet_at(g, tt, pxy[0], pxy[1]);
     }
+    // density row k (the variable count only sets the tile stride)
+    const unsigned base = g.closure == 2 ? tiled_base<N, 4>(g, i, j) : tiled_base<N, 3>(g, i, j);
+    double row[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        const unsigned idx = base + mode_off<N>(0, k, b);
+        row[b] = eq ? eq[idx] + u[idx] : u[idx];
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double c = 0.0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) c = fma(row[b], T.phi[b][r], c);
+        S[k * N + r] = c;
+    }
     __syncthreads();
     const double xp = pxy[0], yp = pxy[1];
+    double phk[N];  // phi_a(xi_k)
+#pragma unroll
+    for (int a = 0; a < N; ++a) phk[a] = pick<N>(T.phi[a], k);
+    const double x = g.x0 + (i + 0.5) * g.dx + 0.5 * g.dx * pick<N>(T.xi, k);
+    const double wk = pick<N>(T.wh, k) * g.dx * g.dy;
+    const double yc = g.y0 + (j + 0.5) * g.dy;
     double s = 0.0;
-    if (e < g.E) {
-        double M[1][NN], W[1][NN];
-        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
-        // density modes (the variable count only sets the tile stride)
-        const unsigned base = g.closure == 2 ? tiled_base<N, 4>(g, i, j) : tiled_base<N, 3>(g, i, j);
 #pragma unroll
-        for (int a = 0; a < N; ++a)
+    for (int r = 0; r < N; ++r) {
+        double rho = 0.0;
 #pragma unroll
-            for (int b = 0; b < N; ++b) {
-                const unsigned idx = base + mode_off<N>(0, a, b);
-                M[0][a * N + b] = eq ? eq[idx] + u[idx] : u[idx];
-            }
-        eval_nodes<N, 1>(M, W);
-        const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
-        const double area = g.dx * g.dy;
-#pragma unroll
-        for (int q = 0; q < N; ++q)
-#pragma unroll
-            for (int r = 0; r < N; ++r) {
-                const double x = xc + 0.5 * g.dx * T.xi[q], y = yc + 0.5 * g.dy * T.xi[r];
-                const double m = W[0][q * N + r] * T.wh[q] * T.wh[r] * area;
-                const double dx = x - xp, dy = y - yp;
-                const double id = rsq64(dx * dx + dy * dy + g.eps2);
-                const double k = m * (id * id * id);
-                s += xp * (k * dy) - yp * (k * dx);
-            }
+        for (int a = 0; a < N; ++a) rho = fma(phk[a], S[a * N + r], rho);
+        const double y = yc + 0.5 * g.dy * T.xi[r];
+        const double m = rho * (wk * T.wh[r]);
+        const double dx = x - xp, dy = y - yp;
+        const double id = rsq64(dx * dx + dy * dy + g.eps2);
+        const double kk = m * (id * id * id);
+        s += xp * (kk * dy) - yp * (kk * dx);
     }
-    const double b = block_sum_256(s, red);
+    if (!active) s = 0.0;
+    const double b = block_sum<kTorqueWaves>(s, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = b;
 }
 
-__global__ void __launch_bounds__(kTorqueBlock) k_torque_final(const double* __restrict__ partials, int nb,
+// one block: thread p adds the partials p, p + 1024, ... in order, then the
+// block sum in a fixed order
+__global__ void __launch_bounds__(kTorqueFinal) k_torque_final(const double* __restrict__ partials, int nb,
                                                                double* __restrict__ out) {
-    __shared__ double red[4];
+    __shared__ double red[kTorqueFinal / 64];
     double s = 0.0;
-    for (int k = threadIdx.x; k < nb; k += kTorqueBlock) s += partials[k];
-    const double b = block_sum_256(s, red);
+    for (int k = threadIdx.x; k < nb; k += kTorqueFinal) s += partials[k];
+    const double b = block_sum<kTorqueFinal / 64>(s, red);
     if (threadIdx.x == 0) *out = b;
 }
 
@@ -1561,13 +1614,14 @@ hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s) 
     return hipGetLastError();
 }
 
-int torque_blocks(const Geo& g) { return (int)((g.E + kTorqueBlock - 1) / kTorqueBlock); }
+// one partial per block of four tiles
+int torque_blocks(const Geo& g) { return (g.tiles_x * g.ny + kTorqueWaves - 1) / kTorqueWaves; }
 
 hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,
                          double* partials, int nblocks, double* out, hipStream_t s) {
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_torque<NT>), dim3(nblocks), dim3(kTorqueBlock), 0, s, g, t, t_dev, u, eq,
-                                        partials));
-    hipLaunchKernelGGL(k_torque_final, dim3(1), dim3(kTorqueBlock), 0, s, partials, nblocks, out);
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_torque<NT>), dim3(nblocks), dim3(64 * kTorqueWaves), 0, s, g, t, t_dev, u,
+                                         eq, partials));
+    hipLaunchKernelGGL(k_torque_final, dim3(1), dim3(kTorqueFinal), 0, s, partials, nblocks, out);
     return hipGetLastError();
 }
 
