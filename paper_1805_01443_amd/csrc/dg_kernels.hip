@@ -1198,32 +1198,6 @@ __global__ void __launch_bounds__(256) k_dt(const Geo g, int nn, const double* _
 }
 
 // ------------------------------------------------------------------ damping
-// nodal values of NV variables from modes (sum-factorised)
-template <int N, int NV>
-__device__ __forceinline__ void eval_nodes(const double (&M)[NV][N * N], double (&W)[NV][N * N]) {
-    constexpr BasisTab T = make_basis(N);
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-            double c[N];
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                double s = 0.0;
-#pragma unroll
-                for (int a = 0; a < N; ++a) s += T.phi[a][q] * M[v][a * N + b];
-                c[b] = s;
-            }
-#pragma unroll
-            for (int r = 0; r < N; ++r) {
-                double s = 0.0;
-#pragma unroll
-                for (int b = 0; b < N; ++b) s += c[b] * T.phi[b][r];
-                W[v][q * N + r] = s;
-            }
-        }
-}
-
 // ramp R(r) of the wave-killing zones and the zone's damping period T_d
 __device__ __forceinline__ double ramp(const Geo& g, double r, double& td) {
     if (r < g.rd_in) {

@@ -7,7 +7,7 @@ state of the last stage before limiting is captured (``dg_capture``): its bf16
 features and the plain indicator's flags, which are the labels.  All positives
 and as many random negatives are kept.  The MLP is trained with the
 library's own forward/backward/Adam kernels (``dg_mlp_train_step``).  Then, in
-DAgger rounds, the learned limiter itself runs the training seeds and the
+DAgger iterations, the learned limiter itself runs the training seeds and the
 states it visits (where its misses let oscillations grow) are labelled by the
 plain indicator and added to the data before retraining.  The flag threshold
 is chosen on a validation seed for a miss rate <= 1 %, and on a test seed the
@@ -368,7 +368,7 @@ def main(argv=None):
     ap.add_argument("--s0", type=float, default=None, help="modal-decay threshold (default -4 log10(order))")
     ap.add_argument("--no-positivity", action="store_true", help="without the positivity-preserving limiter")
     ap.add_argument("--dagger", type=int, default=2,
-                    help="rounds of data from the learned limiter's own runs, labelled by the plain indicator")
+                    help="iterations of data from the learned limiter's own runs, labelled by the plain indicator")
     a = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
@@ -391,7 +391,7 @@ def main(argv=None):
     dg.dg_mlp_params(h, set_params=init_params(0))
     t_tr = time.time()
     X, Y = augment_positives(torch.cat(Xs), torch.cat(Ys), torch)
-    log(f"[data] round 0: train {X.shape[0]} samples ({int(Y.sum().item())} positive, mirror images included)")
+    log(f"[data] iteration 0: train {X.shape[0]} samples ({int(Y.sum().item())} positive, mirror images included)")
     hist, pw = train(h, X, Y, a.epochs, a.batch, a.lr, 0, torch, log)
     theta = pick_theta(h, torch.cat(Xvs), torch.cat(Yvs), torch)
     # DAgger: the learned limiter's own runs (states it visits when it misses),
@@ -408,7 +408,7 @@ def main(argv=None):
         Xvs.append(Xv)
         Yvs.append(Yv)
         X, Y = augment_positives(torch.cat(Xs), torch.cat(Ys), torch)
-        log(f"[data] round {rnd}: train {X.shape[0]} samples ({int(Y.sum().item())} positive, mirror images "
+        log(f"[data] iteration {rnd}: train {X.shape[0]} samples ({int(Y.sum().item())} positive, mirror images "
             f"included), data collected with theta {theta:.3f}")
         h2, p2 = train(h, X, Y, a.epochs, a.batch, a.lr, rnd, torch, log)
         hist += h2
@@ -427,7 +427,7 @@ def main(argv=None):
     s0 = default_s0(4) if a.s0 is None else a.s0
     ev = evaluate_run(a.test_seed, a.nx, a.steps, a.every, params, theta, torch, s0, log, pos)
     res = {"nx": a.nx, "order": 4, "steps": a.steps, "s0": s0, "positivity": pos, "every": a.every,
-           "dagger_rounds": a.dagger, "train_seeds": a.train_seeds, "val_samples": int(Xv.shape[0]),
+           "dagger_iterations": a.dagger, "train_seeds": a.train_seeds, "val_samples": int(Xv.shape[0]),
            "val_positives": int(Yv.sum().item()),
            "val_seed": a.val_seed, "test_seed": a.test_seed, "train_samples": int(X.shape[0]),
            "train_positives": int(Y.sum().item()), "pos_weight": pw, "epochs": a.epochs, "batch": a.batch,

@@ -5,7 +5,7 @@ The committed network (paper_1805_01443_amd/mlp_ring_p3.json, trained by
 256^2, order 4, threshold chosen on seed 6) runs the held-out seed 7 for 24000
 steps (t = 3.25, past the steepening of the ring into shocks), next to the same
 run without a troubled-cell limiter (positivity limiter only) and with minmod
-on every element.  The plain modal-decay indicator judges: at the end it
+on every element.  The plain modal-decay indicator is the referee: at the end it
 flags the elements that still carry oscillations.
 
 Gains measured here: (1) against no troubled-cell limiter, the residual
@@ -61,7 +61,7 @@ def run(limiter, s0, theta, params, capture=False):
     dg.dg_sync(h)
     ms = (time.perf_counter() - t0) * 1e3 / STEPS
     h.close()
-    # the judge: the plain sensor on the final state
+    # the referee: the plain sensor on the final state
     hq, _ = dg.dg_init(learned.ring_config(NX, s0=s0), prim)
     dg.dg_troubled(hq, u, apply=False, flags=lab)
     dg.dg_sync(hq)
@@ -95,5 +95,5 @@ def test_trained_network_gains_over_no_indicator_and_over_limiting_everywhere():
     # (2) accuracy and cost against limiting every element
     assert dif["learned"] < 0.25 * dif["all"]
     assert ms_l < ms_a
-    # (3) the judge's miss rate on the network's own run
+    # (3) the referee's miss rate on the network's own run
     assert miss <= 0.01
