@@ -215,8 +215,10 @@ void drop_events(dg_handle* h) {
     h->ev.clear();
 }
 
-// launch one stage kernel, bracketed by events while profiling
-hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, const StageCoeffs* sc) {
+// launch one stage kernel, bracketed by events while profiling; pp: with the
+// positivity scaling fused (FP64 path)
+hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, const StageCoeffs* sc,
+                 bool pp = false) {
     hipEvent_t a = nullptr, b = nullptr;
     if (h->prof) {
         hipError_t e = hipEventCreate(&a);
@@ -228,7 +230,7 @@ hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, c
         if (e != hipSuccess) return e;
     }
     hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, out, sc, h->s)
-                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, h->s);
+                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, h->s);
     if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
     return e;
 }
@@ -504,7 +506,7 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
         e = hipMemcpyAsync(prim_dev, peq.data(), sizeof(double) * peq.size(), hipMemcpyHostToDevice, h->s);
         if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, h->eq, h->s);
         if (e == hipSuccess) e = dgk::launch_set_coeffs(h->sc_rhs, g0, 0.0, 0.0, 0.0, 1.0, h->s);
-        if (e == hipSuccess) e = dgk::launch_stage(h->n, g0, h->eq, nullptr, h->eq, h->ws1, h->sc_rhs, h->s);
+        if (e == hipSuccess) e = dgk::launch_stage(h->n, g0, h->eq, nullptr, h->eq, h->ws1, h->sc_rhs, false, h->s);
         if (e == hipSuccess) e = dgk::launch_to_f32(h->ws1, h->leq, N, h->s);
         if (e == hipSuccess) e = dgk::launch_add_state(u0_dev, h->eq, u0_dev, -1.0, N, h->s);
         if (e == hipSuccess) e = hipMemcpyAsync(h->du0, u0_dev, state_bytes, hipMemcpyDeviceToDevice, h->s);
@@ -540,7 +542,7 @@ int dg_rhs(dg_handle* h, double t, const double* u_dev, double* rhs_dev) {
     if (!u_dev || !rhs_dev || u_dev == rhs_dev) return fail(h, DG_EINVAL, "u_dev and rhs_dev must be distinct device arrays");
     DG_HIP(h, dgk::launch_set_coeffs(h->sc_rhs, h->g, t, 0.0, 0.0, 1.0, h->s), "dg_rhs coefficients");
     DG_HIP(h, h->dev ? dgk::launch_stage_dev(h->n, h->g, u_dev, nullptr, h->du0, h->leq, rhs_dev, h->sc_rhs, h->s)
-                     : dgk::launch_stage(h->n, h->g, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, h->s),
+                     : dgk::launch_stage(h->n, h->g, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, false, h->s),
            "dg_rhs stage");
     return DG_OK;
 }
@@ -585,12 +587,15 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     }
     DG_HIP(h, dgk::launch_step_begin(h->g, sb, h->dt_part, h->bad_part, h->dt_blocks, t_dev, dt_fixed,
                                                dt_used_dev, 3, h->s), "step begin");
-    DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
-    DG_HIP(h, limit(h, h->ws1, false), "limiter");
-    DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1]), "stage 2");
-    DG_HIP(h, limit(h, h->ws2, false), "limiter");
-    DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2]), "stage 3");
-    DG_HIP(h, limit(h, u_dev, true), "limiter");
+    // the positivity scaling alone (no troubled-cell limiter before it) runs
+    // inside the stage kernels
+    const bool fuse = h->cfg.positivity && h->cfg.limiter == DG_LIMITER_NONE && !h->dev;
+    DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0], fuse), "stage 1");
+    if (!fuse) DG_HIP(h, limit(h, h->ws1, false), "limiter");
+    DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1], fuse), "stage 2");
+    if (!fuse) DG_HIP(h, limit(h, h->ws2, false), "limiter");
+    DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2], fuse), "stage 3");
+    if (!fuse) DG_HIP(h, limit(h, u_dev, true), "limiter");
     if (h->cfg.damping) {
         DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
                "damping");

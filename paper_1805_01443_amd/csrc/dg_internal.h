@@ -93,8 +93,9 @@ struct StepBlock {
 // launchers (all asynchronous on `s`)
 hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim_dev, double* u_dev,
                           hipStream_t s);
+// pp: the positivity scaling fused into the stage (after the combination)
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0,
-                        double* out, const StageCoeffs* sc, hipStream_t s);
+                        double* out, const StageCoeffs* sc, bool pp, hipStream_t s);
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
 // CFL step per element; per-block minimum into dt_part[block] and a per-block

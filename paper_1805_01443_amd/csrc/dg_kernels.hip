@@ -2,15 +2,13 @@
 // SSP-RK3 stage update (Algorithm 1, Appendix A), the CFL reduction (Sec. 2.3),
 // wave-killing damping (Sec. 5.1) and the planet torque (Sec. 5.2 eq. (5)).
 //
-// Stage kernel layout: one thread per element, 64 consecutive elements of a
-// row per wavefront; the state is read plane by plane ([var][mode][element],
-// element fastest), so every load and store of a wavefront is one contiguous
-// 512-byte segment.  Each thread evaluates the Rusanov flux on its own four
-// edges; the neighbour's trace is recomputed from the neighbour's modes, which
-// the wavefront has just read (x neighbours: adjacent lanes) or the adjacent
-// row's wavefront reads on the same XCD (y neighbours), so the state crosses
-// HBM once per stage.  Volume integrals are sum-factorised per node column.
-// Quadrature and basis tables are compile-time constants (dg_basis.h).
+// The state is element-tiled (dg_internal.h): tiles of EW = 64 / N elements
+// of one row, entries [v][b][a][slot], so a mode row of the EW elements is one
+// contiguous run.  The stage, damping and torque kernels run N lanes per
+// element, one tile per wavefront: lane k works on mode row k (or Gauss row
+// k), and the tensor-product contractions are split between the element's
+// lanes with transposes through LDS and lane permutes.  Quadrature and basis
+// tables are compile-time constants (dg_basis.h).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,6 +16,7 @@
 
 #include "dg_basis.h"
 #include "dg_internal.h"
+#include "dg_pp.h"
 
 namespace dgk {
 
@@ -191,7 +190,7 @@ __device__ __forceinline__ double pick(const double (&t)[kMaxOrder], int k) {
 //            slot at C plus two flux rows); stage combination of row a.
 // Every integral is the same Gauss sum as in eq. (3); the density volume term
 // is taken by quadrature (exact for its polynomial integrand).
-template <int N, int CL>
+template <int N, int CL, bool PP>
 __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int tiles_total,
                                                 const double* __restrict__ u, const double* un,
                                                 const double* __restrict__ u0, double* out,
@@ -200,7 +199,11 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
     constexpr BasisTab B = make_basis(N);
-    constexpr int SLOT = lds_slot(NV * NN + 2 * NV * N, N);  // C, later X then Y; south/north fluxes
+    // C, later X then Y; south/north fluxes; with the positivity scaling
+    // fused, its rows and minima after that
+    constexpr int SLOT = lds_slot(PP && pp_slot<N, NV>() > NV * NN + 2 * NV * N ? pp_slot<N, NV>()
+                                                                               : NV * NN + 2 * NV * N,
+                                  N);
     __shared__ double lds[EW * SLOT];
 
     const int lane = threadIdx.x;
@@ -563,20 +566,32 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             for (int r = 0; r < N; ++r) acc += B.wdphi[b][r] * S[((v * N + r) * N + k)];
             R[v][b] += acc;
         }
+    // the new row; with PP the positivity scaling of Sec. 2.4 on it before
+    // the store (the same factors as the separate positivity pass on the
+    // stored state, bit for bit)
+    double O[NV][N];
+    if (a0 != 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) O[v][b] = a0 * Un[v][b] + (a1 * U1[v][b] + a2 * R[v][b]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) O[v][b] = a1 * U1[v][b] + a2 * R[v][b];
+    }
+    if constexpr (PP) {
+        __syncthreads();  // every lane has read Y
+        double th1, th2;
+        pp_factors<N, NV>(g, S, k, O, g.pp_eps, th1, th2);
+        pp_scale_row<N, NV>(k, th1, th2, O);
+    }
     if (active) {
-        if (a0 != 0.0) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int b = 0; b < N; ++b)
-                    st64(rout, vrow, (unsigned)(v * N + b) * RS, a0 * Un[v][b] + (a1 * U1[v][b] + a2 * R[v][b]));
-        } else {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int b = 0; b < N; ++b)
-                    st64(rout, vrow, (unsigned)(v * N + b) * RS, a1 * U1[v][b] + a2 * R[v][b]);
-        }
+            for (int b = 0; b < N; ++b) st64(rout, vrow, (unsigned)(v * N + b) * RS, O[v][b]);
     }
 }
 
@@ -1480,7 +1495,7 @@ hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim, dou
 }
 
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0, double* out,
-                        const StageCoeffs* sc, hipStream_t s) {
+                        const StageCoeffs* sc, bool pp, hipStream_t s) {
     // arrays that a launch does not read still get a valid base (buffer
     // resources are never built on a null pointer)
     if (!un) un = u;
@@ -1489,7 +1504,10 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
         constexpr int EW = 64 / NT;
         const int tx = (g.nx + EW - 1) / EW;
         const int tt = tx * g.ny;
-        hipLaunchKernelGGL((k_stage_c<NT, CT>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, sc);
+        if (pp)
+            hipLaunchKernelGGL((k_stage_c<NT, CT, true>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, sc);
+        else
+            hipLaunchKernelGGL((k_stage_c<NT, CT, false>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, sc);
     }));
     return hipGetLastError();
 }

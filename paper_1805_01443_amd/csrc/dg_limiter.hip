@@ -9,6 +9,7 @@
 
 #include "dg_basis.h"
 #include "dg_internal.h"
+#include "dg_pp.h"
 
 namespace dgk {
 
@@ -35,33 +36,15 @@ __device__ __forceinline__ double nb_mean(const Geo& g, const double* __restrict
 }
 
 // ------------------------------------------------------------------ positivity
-// Positivity-preserving scaling of Zhang & Shu (Sec. 2.4), in place on every
-// element.  Test points: (Lobatto x Gauss) and (Gauss x Lobatto).  Density:
-// theta1 = (mean - eps) / (mean - min) where the minimum falls below eps;
-// pressure (adiabatic only): at each point of the density-limited state w
-// with p(w) < eps, the largest t in [0, 1] with p(mean + t (w - mean)) >= eps
-// (p is concave along the segment), by 64 bisection steps that keep the
-// admissible end; theta2 = min t.  eps = min(e0, mean density, mean
-// pressure).
-// N lanes per element (lane (s, k), EW = 64 / N elements per wavefront, one
-// wavefront per block): lane k holds mode row k of every variable and
-// contracts it in y at the Gauss and at the Lobatto points; through LDS, lane
-// k then evaluates the test points with x-index k (Lobatto x Gauss for k < L,
-// Gauss x Lobatto for k < N), the N lanes reduce the density minimum, take
-// theta1, check the pressure of the density-limited point values
-// (rho~ = mean + theta1 (rho - mean)), reduce theta2, and each lane scales and
-// stores its row.
+// Positivity scaling (Sec. 2.4) with N lanes per element (lane (s, k), EW =
+// 64 / N elements per wavefront, one wavefront per block): lane k loads mode
+// row k of every variable; the factors come from pp_factors (dg_pp.h); each
+// lane of a changed element scales and stores its row.
 template <int N, int NV>
 __global__ void __launch_bounds__(64) k_pp_c(const Geo g, double* u, double e0, unsigned char* changed_out,
                                              double* theta_out) {
-    constexpr auto& G = Basis<N>::t;
-    constexpr auto& Lb = Lobatto<N>::t;
-    constexpr int L = Lb.L;
     constexpr int EW = 64 / N;
-    constexpr int SA = NV * N * N;           // [v][a][r]: row a at Gauss eta_r
-    constexpr int SB = NV * N * L;           // [v][a][r]: row a at Lobatto eta_r
-    constexpr int SLOT = SA + SB + NV + 2 * N;  // + means + per-lane minima
-    constexpr int NP = N + L;                // test points per lane (the first N need k < L)
+    constexpr int SLOT = pp_slot<N, NV>();
     __shared__ double lds[EW * SLOT];
     const int lane = threadIdx.x;
     const int sl = lane / N, k = lane - sl * N;
@@ -73,130 +56,26 @@ __global__ void __launch_bounds__(64) k_pp_c(const Geo g, double* u, double e0, 
     const int i = active ? i0 + sl : i0;
     double* S = lds + (own ? sl : 0) * SLOT;
     const unsigned base = tiled_base<N, NV>(g, i, j);
-    // row k contracted in y at the Gauss and at the Lobatto points
+    double Ua[NV][N];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        double Ua[N];
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int b = 0; b < N; ++b) Ua[b] = u[base + mode_off<N>(v, k, b)];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double c = 0.0;
-#pragma unroll
-            for (int b = 0; b < N; ++b) c = fma(Ua[b], G.phi[b][r], c);
-            S[(v * N + k) * N + r] = c;
-        }
-#pragma unroll
-        for (int r = 0; r < L; ++r) {
-            double c = 0.0;
-#pragma unroll
-            for (int b = 0; b < N; ++b) c = fma(Ua[b], Lb.phi[b][r], c);
-            S[SA + (v * N + k) * L + r] = c;
-        }
-        if (k == 0) S[SA + SB + v] = Ua[0];  // the mean
-    }
-    __syncthreads();
-    double M[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) M[v] = S[SA + SB + v];
-    const bool adi = NV == 4 && g.closure == 2;
-    const double gm1 = g.gamma - 1.0;
-    double pbar = M[0];
-    if (adi) pbar = gm1 * (M[3] - 0.5 * (M[1] * M[1] + M[2] * M[2]) / M[0]);
-    const bool admissible = M[0] > 0.0 && pbar > 0.0;
-    double eps = e0;
-    if (M[0] < eps) eps = M[0];
-    if (adi && pbar < eps) eps = pbar;
-    // basis values phi_a(x_k) at this lane's Lobatto and Gauss x
-    double pl[N], pg[N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-        double x = Lb.phi[a][0], y = G.phi[a][0];
-#pragma unroll
-        for (int m = 1; m < N; ++m) {
-            if (m < L) x = k == m ? Lb.phi[a][m] : x;
-            y = k == m ? G.phi[a][m] : y;
-        }
-        pl[a] = x;
-        pg[a] = y;
-    }
-    const bool hasA = k < L;
-    // value of variable v at this lane's test point p (p < N: (Lobatto x_k,
-    // Gauss eta_p); else (Gauss x_k, Lobatto eta_{p-N}))
-    auto point = [&](int v, int p) {
-        double s2 = 0.0;
-        if (p < N) {
-#pragma unroll
-            for (int a = 0; a < N; ++a) s2 = fma(pl[a], S[(v * N + a) * N + p], s2);
-        } else {
-#pragma unroll
-            for (int a = 0; a < N; ++a) s2 = fma(pg[a], S[SA + (v * N + a) * L + (p - N)], s2);
-        }
-        return s2;
-    };
-    double rho[NP];
-    double rmin = INFINITY;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        rho[p] = point(0, p);
-        if (p >= N || hasA) rmin = fmin(rmin, rho[p]);
-    }
-    // element minimum over its N lanes
-    S[SA + SB + NV + k] = rmin;
-    __syncthreads();
-    double emin = INFINITY;
-#pragma unroll
-    for (int m = 0; m < N; ++m) emin = fmin(emin, S[SA + SB + NV + m]);
-    double th1 = 1.0, th2 = 1.0;
-    if (admissible && emin < eps) th1 = (M[0] - eps) / (M[0] - emin);
-    if (adi) {
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            if (!admissible || (p < N && !hasA)) continue;
-            double W[4];
-            W[0] = M[0] + th1 * (rho[p] - M[0]);
-#pragma unroll
-            for (int v = 1; v < 4; ++v) W[v] = point(v, p);
-            const double pw = gm1 * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
-            if (!(pw < eps)) continue;
-            double lo = 0.0, hi = 1.0;
-            for (int it = 0; it < 64; ++it) {
-                const double mid = 0.5 * (lo + hi);
-                double Sm[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) Sm[v] = M[v] + mid * (W[v] - M[v]);
-                const double ps = gm1 * (Sm[3] - 0.5 * (Sm[1] * Sm[1] + Sm[2] * Sm[2]) / Sm[0]);
-                if (ps >= eps)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            th2 = fmin(th2, lo);
-        }
-        // element minimum over its N lanes (adi is uniform: no divergent barrier)
-        S[SA + SB + NV + N + k] = th2;
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < N; ++m) th2 = fmin(th2, S[SA + SB + NV + N + m]);
-    }
+        for (int b = 0; b < N; ++b) Ua[v][b] = u[base + mode_off<N>(v, k, b)];
+    double th1, th2;
+    pp_factors<N, NV>(g, S, k, Ua, e0, th1, th2);
     const bool changed = th1 < 1.0 || th2 < 1.0;
     if (active && changed) {
-        // the row again (from L2) scaled: density by theta1, then every
-        // variable by theta2; the means never change
-        const int v1 = th2 < 1.0 ? NV : 1;
+        // the row again (from L2: fewer live registers), scaled
+        double Ub[NV][N];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            if (v >= v1) break;
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int b = 0; b < N; ++b) {
-                if (k == 0 && b == 0) continue;
-                const unsigned idx = base + mode_off<N>(v, k, b);
-                double x = u[idx];
-                if (v == 0) x *= th1;
-                x *= th2;
-                u[idx] = x;
-            }
-        }
+            for (int b = 0; b < N; ++b) Ub[v][b] = u[base + mode_off<N>(v, k, b)];
+        pp_scale_row<N, NV>(k, th1, th2, Ub);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) u[base + mode_off<N>(v, k, b)] = Ub[v][b];
     }
     if (active && k == 0) {
         const long long e = (long long)j * g.nx + i;

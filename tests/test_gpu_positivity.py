@@ -219,3 +219,49 @@ def test_paper_disc_with_positivity_steps_match():
         assert abs(dt_dev.item() - dto) <= 1e-13 * dto
         assert err <= 1e-12
     h.close()
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_fused_positivity_equals_the_separate_pass(order):
+    """With no troubled-cell limiter the positivity scaling runs inside the
+    stage kernels; with the modal-decay indicator at s0 = +inf (it flags
+    nothing) the same scaling runs as its own pass after each stage.  The two
+    must give the same states bit for bit: the fused scaling works on the row
+    values the stage would store."""
+    T = torch()
+    cfg = W.rarefaction(nx=40, ny=3, order=order)
+    prim = W.prim_for(cfg, "rarefaction")
+    hf, uf = dg.dg_init(cfg, prim)
+    hs, us = dg.dg_init(cfg.replace(limiter=dg.LIMITER_MODAL_DECAY, limiter_s0=math.inf), prim)
+    tf = T.zeros(1, dtype=T.float64, device="cuda")
+    ts = T.zeros(1, dtype=T.float64, device="cuda")
+    for k in range(40):
+        dg.dg_rk_step(hf, uf, tf, 0.0, None)
+        dg.dg_rk_step(hs, us, ts, 0.0, None)
+    dg.dg_sync(hf)
+    dg.dg_sync(hs)
+    print(f"[fused positivity] order {order}: t = {tf.item():.6f}, equal states: {T.equal(uf, us)}", flush=True)
+    assert tf.item() == ts.item()
+    assert T.equal(uf, us)
+    hf.close()
+    hs.close()
+
+
+def test_fused_positivity_on_the_paper_disc():
+    """The same identity on the paper's adiabatic disc at order 5 (damping
+    zones, planet), ten steps."""
+    T = torch()
+    cfg = W.paper_disc(nx=40, order=5, q=1e-3).replace(ny=36)
+    prim = W.prim_for(cfg, "paper_disc")
+    hf, uf = dg.dg_init(cfg, prim)
+    hs, us = dg.dg_init(cfg.replace(limiter=dg.LIMITER_MODAL_DECAY, limiter_s0=math.inf), prim)
+    tf = T.zeros(1, dtype=T.float64, device="cuda")
+    ts = T.zeros(1, dtype=T.float64, device="cuda")
+    for k in range(10):
+        dg.dg_rk_step(hf, uf, tf, 0.0, None)
+        dg.dg_rk_step(hs, us, ts, 0.0, None)
+    dg.dg_sync(hf)
+    dg.dg_sync(hs)
+    assert T.equal(uf, us)
+    hf.close()
+    hs.close()
