@@ -73,7 +73,7 @@ def calibrate_copy():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for fn in ("dg_kernels.hip", "dg_internal.h"):
+    for fn in ("dg_kernels.hip", "dg_internal.h", "dg_pp.h"):
         with open(os.path.join(ROOT, "paper_1805_01443_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

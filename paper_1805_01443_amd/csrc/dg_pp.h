@@ -109,26 +109,63 @@ __device__ __forceinline__ void pp_factors(const Geo& g, double* S, int k, const
     th2 = 1.0;
     if (admissible && emin < eps) th1 = (M[0] - eps) / (M[0] - emin);
     if (adi) {
+        // the points whose density-limited value has p < eps, as a bit list
+        unsigned need = 0u;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             if (!admissible || (p < N && !hasA)) continue;
-            // the density-limited point value (the density value again, same bits)
             const double w0 = M[0] + th1 * (point(0, p) - M[0]);
             const double w1 = point(1, p), w2 = point(2, p), w3 = point(NV - 1, p);
             const double pw = gm1 * (w3 - 0.5 * (w1 * w1 + w2 * w2) / w0);
-            if (!(pw < eps)) continue;
-            double lo = 0.0, hi = 1.0;
+            if (pw < eps) need |= 1u << p;
+        }
+        // Each lane works through its own list, two points at a time: two
+        // independent bisections in flight, and a wavefront takes as many
+        // rounds as its longest list needs, not one per point any lane needs.
+        // The values and every step are those of a bisection of one point, so
+        // theta2 (the minimum over the points) keeps its bits.
+        while (__any(need != 0u)) {
+            const int p1 = need ? __builtin_ctz(need) : 0;
+            const bool h1 = need != 0u;
+            need &= need - 1u;
+            const int p2 = need ? __builtin_ctz(need) : p1;
+            const bool h2 = need != 0u;
+            need &= need - 1u;
+            // value of variable v at point q (run-time index), as point() does
+            auto at = [&](int v, int q) __attribute__((always_inline)) {
+                double s2 = 0.0;
+                const bool ga = q < N;
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    const int ix = ga ? (v * N + a) * N + q : SA + (v * N + a) * L + (q - N);
+                    s2 = fma(ga ? pl[a] : pg[a], S[ix], s2);
+                }
+                return s2;
+            };
+            const double a0 = M[0] + th1 * (at(0, p1) - M[0]);
+            const double a1 = at(1, p1), a2 = at(2, p1), a3 = at(NV - 1, p1);
+            const double b0 = M[0] + th1 * (at(0, p2) - M[0]);
+            const double b1 = at(1, p2), b2 = at(2, p2), b3 = at(NV - 1, p2);
+            double lo1 = 0.0, hi1 = 1.0, lo2 = 0.0, hi2 = 1.0;
             for (int it = 0; it < 64; ++it) {
-                const double mid = 0.5 * (lo + hi);
-                const double s0 = M[0] + mid * (w0 - M[0]), s1 = M[1] + mid * (w1 - M[1]);
-                const double s2 = M[2] + mid * (w2 - M[2]), s3 = M[NV - 1] + mid * (w3 - M[NV - 1]);
+                const double m1 = 0.5 * (lo1 + hi1), m2 = 0.5 * (lo2 + hi2);
+                const double s0 = M[0] + m1 * (a0 - M[0]), s1 = M[1] + m1 * (a1 - M[1]);
+                const double s2 = M[2] + m1 * (a2 - M[2]), s3 = M[NV - 1] + m1 * (a3 - M[NV - 1]);
+                const double t0 = M[0] + m2 * (b0 - M[0]), t1 = M[1] + m2 * (b1 - M[1]);
+                const double t2 = M[2] + m2 * (b2 - M[2]), t3 = M[NV - 1] + m2 * (b3 - M[NV - 1]);
                 const double ps = gm1 * (s3 - 0.5 * (s1 * s1 + s2 * s2) / s0);
+                const double pt = gm1 * (t3 - 0.5 * (t1 * t1 + t2 * t2) / t0);
                 if (ps >= eps)
-                    lo = mid;
+                    lo1 = m1;
                 else
-                    hi = mid;
+                    hi1 = m1;
+                if (pt >= eps)
+                    lo2 = m2;
+                else
+                    hi2 = m2;
             }
-            th2 = fmin(th2, lo);
+            if (h1) th2 = fmin(th2, lo1);
+            if (h2) th2 = fmin(th2, lo2);
         }
         // element minimum over its N lanes (adi is uniform: no divergent barrier)
         S[SA + SB + NV + N + k] = th2;
