@@ -1,0 +1,38 @@
+"""Host-side checks of bench.py that need no GPU: the one-GPU refusal and the
+roofline bookkeeping (algorithmic bytes, the counter-calibration record)."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_traffic_record_is_tied_to_the_kernel_sources():
+    """the committed counter record names the source hash it was taken on;
+    bench.py reports its bytes only while that hash is the current one"""
+    with open(os.path.join(ROOT, "profiles", "k_stage_traffic.json")) as f:
+        rec = json.load(f)["disc512_p4_fp64"]
+    assert rec["hbm_bytes_per_launch"] > 0
+    assert 1.9 < rec["fetch_factor"] < 2.1 and 0.9 < rec["write_factor"] < 1.1
+    cur = bench.kernel_source_hash()
+    got = bench.measured_traffic("disc512_p4_fp64")
+    assert got == (rec["hbm_bytes_per_launch"] if rec["kernel_source_sha256_16"] == cur else None)
+
+
+def test_count_model_is_positive_and_grows_with_order():
+    f = [bench.flop_per_element_stage(n, 3) for n in (2, 3, 4, 5)]
+    assert all(a < b for a, b in zip(f, f[1:]))
+    # the sum-factorised volume part dominates at order 5: 2 (7 n^3 nvar - n^3) FLOP
+    assert f[-1] > 2 * (7 * 125 * 3 - 125)
