@@ -8,7 +8,8 @@
 // up to eps; theta2 is the smallest admissible t in [0, 1] of the pressure of
 // mean + t (point - mean), with the density already limited, found by 64
 // bisection steps that keep the admissible end (p is concave along the
-// segment).  eps = min(e0, mean density, mean pressure).  An element whose
+// segment); each step tests rho p >= eps rho, the density on the segment
+// being positive.  eps = min(e0, mean density, mean pressure).  An element whose
 // mean is not admissible keeps theta1 = theta2 = 1.
 #pragma once
 
@@ -153,13 +154,15 @@ __device__ __forceinline__ void pp_factors(const Geo& g, double* S, int k, const
                 const double s2 = M[2] + m1 * (a2 - M[2]), s3 = M[NV - 1] + m1 * (a3 - M[NV - 1]);
                 const double t0 = M[0] + m2 * (b0 - M[0]), t1 = M[1] + m2 * (b1 - M[1]);
                 const double t2 = M[2] + m2 * (b2 - M[2]), t3 = M[NV - 1] + m2 * (b3 - M[NV - 1]);
-                const double ps = gm1 * (s3 - 0.5 * (s1 * s1 + s2 * s2) / s0);
-                const double pt = gm1 * (t3 - 0.5 * (t1 * t1 + t2 * t2) / t0);
-                if (ps >= eps)
+                // rho p >= eps rho (the density on the segment is positive):
+                // no division in the loop
+                const double ps = gm1 * (s3 * s0 - 0.5 * (s1 * s1 + s2 * s2));
+                const double pt = gm1 * (t3 * t0 - 0.5 * (t1 * t1 + t2 * t2));
+                if (ps >= eps * s0)
                     lo1 = m1;
                 else
                     hi1 = m1;
-                if (pt >= eps)
+                if (pt >= eps * t0)
                     lo2 = m2;
                 else
                     hi2 = m2;
