@@ -271,8 +271,8 @@ def main():
         calibrate_copy()
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note "
-                                   "(see DESIGN.md), not an implemented path", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "this library runs on one GPU only; sharding over several GPUs is a "
+                                   "design, not an implemented path", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
 
