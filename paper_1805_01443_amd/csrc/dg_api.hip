@@ -40,6 +40,7 @@ struct dg_handle {
     int dt_blocks = 0;
     int* damp_list = nullptr;
     int ndamp = 0;
+    double* damp_q0 = nullptr;  // damping targets at the Gauss nodes of the listed tiles
     double* tq_part = nullptr;
     int tq_blocks = 0;
     // troubled cells / learned indicator
@@ -339,6 +340,7 @@ void release(dg_handle* h) {
     h->dt_part = nullptr;
     h->bad_part = nullptr;
     (void)hipFree(h->damp_list);
+    (void)hipFree(h->damp_q0);
     (void)hipFree(h->tq_part);
     (void)hipFree(h->eq);
     (void)hipFree(h->du0);
@@ -461,6 +463,7 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
         h->ndamp = (int)list.size();
         if (h->ndamp) {
             DG_ALLOC(h->damp_list, sizeof(int) * list.size());
+            DG_ALLOC(h->damp_q0, sizeof(double) * list.size() * (size_t)h->nvar * h->n * h->n * h->g.ew);
             e = hipMemcpyAsync(h->damp_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, h->s);
             if (e == hipSuccess) e = hipStreamSynchronize(h->s);
             if (e != hipSuccess) {
@@ -517,6 +520,11 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
         }
     }
     (void)hipFree(prim_dev);
+    // damping targets from u0, which is fixed from here on
+    if (h->ndamp) {
+        e = dgk::launch_damp_prep(h->n, h->g, h->u0, h->damp_list, h->ndamp, h->damp_q0, h->s);
+        if (e != hipSuccess) return bail(hip_fail(h, e, "damping targets"));
+    }
     // feature scales: RMS of the initial element means of each variable
     {
         // the means of u0, gathered into [v][e] in the stage workspace
@@ -571,7 +579,7 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
         }
         DG_HIP(h, dgk::launch_rk_combine(u_dev, k, S, &sb->comb[0][0], u_dev, N, h->s), "update");
         if (h->cfg.damping)
-            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
+            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
                    "damping");
         return DG_OK;
     }
@@ -581,7 +589,7 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
         DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
         DG_HIP(h, stage(h, h->ws1, u_dev, u_dev, &sb->st[1]), "stage 2");
         if (h->cfg.damping)
-            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
+            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
                    "damping");
         return DG_OK;
     }
@@ -597,7 +605,7 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2], fuse), "stage 3");
     if (!fuse) DG_HIP(h, limit(h, u_dev, true), "limiter");
     if (h->cfg.damping) {
-        DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->u0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
+        DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
                "damping");
         // the damped state gets the positivity scaling too
         if (h->cfg.positivity)

@@ -114,7 +114,10 @@ hipError_t launch_rk_combine(const double* base, const double* const* k, int nk,
 // nst = 3: SSP(3,3), nst = 2: SSP(2,2), Shu-Osher coefficients in sb->st
 hipError_t launch_step_begin(const Geo& g, StepBlock* sb, const double* dt_part, const unsigned int* bad_part,
                              int nblk, double* t_dev, double dt_fixed, double* dt_used_dev, int nst, hipStream_t s);
-hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const double* eq, const int* list,
+// damping targets of the listed tiles from u0 (once), q0: nlist NV n n EW doubles
+hipError_t launch_damp_prep(int n, const Geo& g, const double* u0, const int* list, int nlist, double* q0,
+                            hipStream_t s);
+hipError_t launch_damp(int n, const Geo& g, double* u, const double* q0, const double* eq, const int* list,
                        int nlist, const StageCoeffs* sc, hipStream_t s);
 hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,
                          double* partials, int nblocks, double* out, hipStream_t s);

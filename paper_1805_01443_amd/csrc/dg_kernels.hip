@@ -1229,20 +1229,92 @@ __device__ __forceinline__ double ramp(const Geo& g, double r, double& td) {
     return 0.0;
 }
 
-// Damping with N lanes per element (same split as k_stage_c): lane k first
-// holds mode row k of u and of u0 and contracts them in y, then Gauss row k
-// (node values, nodal increments, x projection), then mode row k again
-// (y projection and the update).  One listed tile (EW = 64 / N elements) per
-// wave; elements of the tile outside the damping zones get zero increments.
+// Damping targets: rho0, v0x, v0y (and T0 with four variables) of u0 at the
+// Gauss nodes of every listed tile, q0[list index][v][q][r][slot], computed
+// once at set-up by N lanes per element (lane k: mode row k of u0, then
+// Gauss row k), with the arithmetic the damping used when it contracted u0
+// at every step.
 template <int N, int CL>
-__global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const double* __restrict__ u0,
+__global__ void __launch_bounds__(64) k_damp_prep(const Geo g, const double* __restrict__ u0,
+                                                  const int* __restrict__ list, double* __restrict__ q0) {
+    constexpr BasisTab B = make_basis(N);
+    constexpr int NV = NVar<CL>::value;
+    constexpr int EW = 64 / N;
+    constexpr int SLOT = lds_slot(NV * N * N, N);
+    __shared__ double lds[EW * SLOT];
+    constexpr unsigned RS = N * EW * 8;
+    const int lane = threadIdx.x;
+    const int sl = lane / N, k = lane - sl * N;
+    const bool own = EW * N == 64 || sl < EW;
+    const int tile = list[blockIdx.x];
+    const int j = tile / g.tiles_x;
+    const int i0 = (tile - j * g.tiles_x) * EW;
+    const int i = (sl < EW && i0 + sl < g.nx) ? i0 + sl : i0;
+    double* S = lds + (own ? sl : 0) * SLOT;
+    const rsrc_t ru0 = make_rsrc(u0);
+    const unsigned vrow = (tiled_base<N, NV>(g, i, j) + k * EW) * 8u;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double A0[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) A0[b] = ld64(ru0, vrow, (unsigned)(v * N + b) * RS);
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double c0 = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) c0 += A0[b] * B.phi[b][r];
+            S[(v * N + k) * N + r] = c0;
+        }
+    }
+    __syncthreads();
+    double C0[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) C0[v][a] = S[(v * N + a) * N + k];
+    const unsigned qs = (unsigned)(N * EW);  // stride of (v, q) in q0
+    double* qb = q0 + (size_t)blockIdx.x * NV * N * qs + k * EW + (own ? sl : 0);
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double W0[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s0 = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) s0 += B.phi[a][q] * C0[v][a];
+            W0[v] = s0;
+        }
+        const double rho0 = W0[0], ir0 = rcp64(rho0), vx0 = W0[1] * ir0, vy0 = W0[2] * ir0;
+        double P0[NV];
+        P0[0] = rho0;
+        P0[1] = vx0;
+        P0[2] = vy0;
+        if constexpr (NV == 4) {
+            const double gm1 = g.gamma - 1.0;
+            P0[3] = gm1 * (W0[3] - 0.5 * rho0 * (vx0 * vx0 + vy0 * vy0)) * ir0;
+        }
+        if (own) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qb[(v * N + q) * qs] = P0[v];
+        }
+    }
+}
+
+// Damping with N lanes per element (same split as k_stage_c): lane k first
+// holds mode row k of u and contracts it in y, then Gauss row k (node values,
+// nodal increments against the targets of k_damp_prep, x projection), then
+// mode row k again (y projection and the update).  One listed tile (EW = 64 /
+// N elements) per wave; elements of the tile outside the damping zones get
+// zero increments.
+template <int N, int CL>
+__global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const double* __restrict__ q0,
                                                const double* __restrict__ eq, const int* __restrict__ list, int nlist,
                                                const StageCoeffs* __restrict__ scp) {
     constexpr BasisTab B = make_basis(N);
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
-    constexpr int SLOT = lds_slot(2 * NV * NN, N);
+    constexpr int SLOT = lds_slot(NV * NN, N);
     __shared__ double lds[EW * SLOT];
     constexpr unsigned RS = N * EW * 8;  // byte stride of (v * N + b) in a row
     const int lane = threadIdx.x;
@@ -1253,61 +1325,61 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
     const bool active = sl < EW && i0 + sl < g.nx;
     const int i = active ? i0 + sl : i0;  // idle lanes shadow a valid element and store nothing
     // lanes beyond EW * N shadow slot 0's element (same i, j, k) and share its slot
-    double* S = lds + ((EW * N == 64 || sl < EW) ? sl : 0) * SLOT;
+    const bool own = EW * N == 64 || sl < EW;
+    double* S = lds + (own ? sl : 0) * SLOT;
     const double dt = scp->dt;
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
-    const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), req = make_rsrc(eq ? eq : u0);
+    const rsrc_t ru = make_rsrc(u), req = make_rsrc(eq ? eq : u);
     const unsigned vrow = (tiled_base<N, NV>(g, i, j) + k * EW) * 8u;  // mode (k, 0)
 
-    // mode row k: y contraction of u (full state) and u0
+    // the targets of Gauss row k (loaded first, used in the second phase)
+    const unsigned qs = (unsigned)(N * EW);
+    const double* qb = q0 + (size_t)blockIdx.x * NV * N * qs + k * EW + (own ? sl : 0);
+    double Tg[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 0; q < N; ++q) Tg[v][q] = qb[(v * N + q) * qs];
+
+    // mode row k: y contraction of u (full state)
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        double A[N], A0[N];
+        double A[N];
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             const unsigned so = (unsigned)(v * N + b) * RS;
             const double ud = ld64(ru, vrow, so);
             A[b] = eq ? ld64(req, vrow, so) + ud : ud;
-            A0[b] = ld64(ru0, vrow, so);
         }
 #pragma unroll
         for (int r = 0; r < N; ++r) {
-            double c = 0.0, c0 = 0.0;
+            double c = 0.0;
 #pragma unroll
-            for (int b = 0; b < N; ++b) {
-                c += A[b] * B.phi[b][r];
-                c0 += A0[b] * B.phi[b][r];
-            }
+            for (int b = 0; b < N; ++b) c += A[b] * B.phi[b][r];
             S[(v * N + k) * N + r] = c;
-            S[NV * NN + (v * N + k) * N + r] = c0;
         }
     }
     __syncthreads();
 
     // Gauss row k: nodal increments, projected in x
     const double yk = yc + 0.5 * g.dy * pick<N>(B.xi, k);
-    double Cc[NV][N], C0[NV][N], P[NV][N];
+    double Cc[NV][N], P[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int a = 0; a < N; ++a) {
             Cc[v][a] = S[(v * N + a) * N + k];
-            C0[v][a] = S[NV * NN + (v * N + a) * N + k];
             P[v][a] = 0.0;
         }
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-        double W[NV], W0[NV];
+        double W[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double s = 0.0, s0 = 0.0;
+            double s = 0.0;
 #pragma unroll
-            for (int a = 0; a < N; ++a) {
-                s += B.phi[a][q] * Cc[v][a];
-                s0 += B.phi[a][q] * C0[v][a];
-            }
+            for (int a = 0; a < N; ++a) s += B.phi[a][q] * Cc[v][a];
             W[v] = s;
-            W0[v] = s0;
         }
         const double x = xc + 0.5 * g.dx * B.xi[q];
         double td;
@@ -1318,7 +1390,7 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
         if (R > 0.0) {
             const double w = dt * R * rcp64(td + dt * R);
             const double rho = W[0], ir = rcp64(rho), vx = W[1] * ir, vy = W[2] * ir;
-            const double rho0 = W0[0], ir0 = rcp64(rho0), vx0 = W0[1] * ir0, vy0 = W0[2] * ir0;
+            const double rho0 = Tg[0][q], vx0 = Tg[1][q], vy0 = Tg[2][q];
             const double drho = w * (rho0 - rho);
             const double dvx = w * (vx0 - vx), dvy = w * (vy0 - vy);
             const double vx1 = vx + dvx, vy1 = vy + dvy;
@@ -1328,8 +1400,7 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
             if constexpr (NV == 4) {
                 const double gm1 = g.gamma - 1.0;
                 const double T1 = gm1 * (W[3] - 0.5 * rho * (vx * vx + vy * vy)) * ir;
-                const double T0 = gm1 * (W0[3] - 0.5 * rho0 * (vx0 * vx0 + vy0 * vy0)) * ir0;
-                const double dT = w * (T0 - T1);
+                const double dT = w * (Tg[3][q] - T1);  // Tg[3]: the target temperature
                 const double dp = rho * dT + drho * (T1 + dT);
                 const double dke = 0.5 * (drho * (vx1 * vx1 + vy1 * vy1) + rho * (dvx * (vx1 + vx) + dvy * (vy1 + vy)));
                 D[3] = dp / gm1 + dke;
@@ -1572,11 +1643,19 @@ hipError_t launch_step_begin(const Geo& g, StepBlock* sb, const double* dt_part,
     return hipGetLastError();
 }
 
-hipError_t launch_damp(int n, const Geo& g, double* u, const double* u0, const double* eq, const int* list,
+hipError_t launch_damp_prep(int n, const Geo& g, const double* u0, const int* list, int nlist, double* q0,
+                            hipStream_t s) {
+    if (nlist <= 0) return hipSuccess;
+    DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_damp_prep<NT, CT>), dim3(nlist), dim3(64), 0, s,
+                                                                  g, u0, list, q0)));
+    return hipGetLastError();
+}
+
+hipError_t launch_damp(int n, const Geo& g, double* u, const double* q0, const double* eq, const int* list,
                        int nlist, const StageCoeffs* sc, hipStream_t s) {
     if (nlist <= 0) return hipSuccess;
     DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_damp_c<NT, CT>), dim3(nlist), dim3(64), 0, s, g,
-                                                                  u, u0, eq, list, nlist, sc)));
+                                                                  u, q0, eq, list, nlist, sc)));
     return hipGetLastError();
 }
 
