@@ -119,7 +119,7 @@ def cpu_baseline(cfg, prim):
     oc = O.cfg(dataclasses.asdict(cfg))
     u0 = O.project(oc, prim)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    steps = 2
+    steps = 6  # about 10 s on 16 host threads
     t0 = time.perf_counter()
     u, t = u0, 0.0
     for _ in range(steps):
