@@ -30,7 +30,8 @@
  * (or of dg_init / dg_get_nodes when the handle is NULL).  Device-side
  * problems (non-finite or non-positive density means) raise a flag that the
  * next dg_sync() reports as DG_ENONFINITE.  A handle belongs to one stream and
- * is not thread-safe; the library keeps no global mutable state.
+ * is not thread-safe.  Process-wide state: the message of the last failed
+ * handle-less call is kept per host thread.
  */
 #ifndef DG_MI355X_H
 #define DG_MI355X_H

@@ -132,6 +132,70 @@ def test_limited_step_conserves_mass():
     assert abs(un[0, 0].sum() - u[0, 0].sum()) < 1e-13 * u[0, 0].sum()
 
 
+def test_limited_step_limits_after_every_stage():
+    """Sec. 3.1 (iii)(d): the limiter acts inside every Runge-Kutta sub-step.
+    The oracle's limited step equals the SSP(3,3) Shu-Osher stages with the
+    indicator + minmod applied to each stage state (composed here from the
+    separately pinned right-hand side, indicator and minmod), and differs from
+    limiting only the end state of an unlimited step."""
+    n = 3
+    c = _cfg(n=n, nx=14, ny=12, nvar=4, bc=0, x0=0, x1=1, y0=0, y1=1)
+    X, Y = O.nodes(c)
+    # a steep (unresolved) density front, uniform pressure 1
+    rho = 2.0 - np.tanh((np.sqrt((X - 0.45) ** 2 + (Y - 0.55) ** 2) - 0.245) / 0.03)
+    f = [rho, 0.4 * rho, -0.2 * rho, 1.0 / 0.4 + 0.5 * rho * (0.16 + 0.04)]
+    u = O.project(c, S.pack_prim(f, X.shape[0], n * n))
+    s0 = float(np.quantile(O.indicator(c, u), 0.7))
+    dt, t = 4e-3, 0.2
+
+    def lim(w):
+        return O.minmod(c, w, u, O.indicator(c, w) > s0)[0]
+
+    u1 = lim(u + dt * O.rhs(c, t, u))
+    u2 = lim(0.75 * u + 0.25 * (u1 + dt * O.rhs(c, t + dt, u1)))
+    u3 = lim(u / 3.0 + 2.0 / 3.0 * (u2 + dt * O.rhs(c, t + 0.5 * dt, u2)))
+    got, d = O.step_limited(c, u, t, dt, u, s0)
+    assert d == dt
+    assert np.max(np.abs(got - u3)) <= 1e-15 * np.max(np.abs(u3))
+    # the stage limiting changes the result: limiting only at the end differs
+    end_only = lim(O.step(c, u, t, dt)[0])
+    assert np.max(np.abs(end_only - got)) > 1e-6 * np.max(np.abs(got))
+    # and the intermediate stage states were flagged and changed
+    assert (O.indicator(c, u + dt * O.rhs(c, t, u)) > s0).sum() > 0
+    assert O.minmod(c, u + dt * O.rhs(c, t, u), u, O.indicator(c, u + dt * O.rhs(c, t, u)) > s0)[1].any()
+
+
+def test_mlp_features_hand_built_state():
+    """Feature definition u_vm / (|u_v00| + s_v), index v * n^2 + m with the
+    flat mode m = a * n + b (a: degree in x): two hand-built elements."""
+    n = 4
+    c = _cfg(n=n, nx=2, ny=1, nvar=4)
+    u = np.zeros((4, n * n, 2))
+    # element 0: negative density mean (the absolute value enters), distinct
+    # x- and y-slopes so a transposed mode index is seen
+    u[0, 0, 0] = -2.0
+    u[0, 1 * n + 0, 0] = 0.5     # mode (1, 0)
+    u[0, 0 * n + 1, 0] = -0.25   # mode (0, 1)
+    u[3, 0, 0] = 4.0
+    u[3, 3 * n + 2, 0] = 1.5     # mode (3, 2) of the energy
+    # element 1: zero mean, the scale alone normalises
+    u[1, 2 * n + 1, 1] = 0.3     # mode (2, 1) of x-momentum
+    scale = np.array([0.5, 0.25, 1.0, 2.0])
+    f = O.mlp_features(c, u, scale)
+    assert f.shape == (2, 64)
+    assert f[0, 0] == -2.0 / 2.5
+    assert f[0, 0 * 16 + 4] == 0.5 / 2.5      # v = 0, m = 1 * 4 + 0
+    assert f[0, 0 * 16 + 1] == -0.25 / 2.5    # v = 0, m = 0 * 4 + 1
+    assert f[0, 3 * 16 + 0] == 4.0 / 6.0
+    assert f[0, 3 * 16 + 14] == 1.5 / 6.0     # v = 3, m = 3 * 4 + 2
+    assert f[1, 1 * 16 + 9] == 0.3 / 0.25     # v = 1, m = 2 * 4 + 1
+    nz = {(0, 0), (0, 4), (0, 1), (0, 48), (0, 62), (1, 25)}
+    for e in range(2):
+        for k in range(64):
+            if (e, k) not in nz:
+                assert f[e, k] == 0.0, (e, k)
+
+
 # ---------------------------------------------------------------- MLP
 def _params(seed=0):
     rng = np.random.default_rng(seed)

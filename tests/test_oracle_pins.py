@@ -271,6 +271,53 @@ def test_cfl_dt_closed_form_cfg1():
     assert abs(O.dt(c, u) - 0.2 / 5 / (4 * 64)) < 1e-18
 
 
+def _uniform_modes(c, vals):
+    """modes of a state that is constant per variable (the mean mode only)"""
+    u = np.zeros((c.nvar, c.n * c.n, c.nx * c.ny))
+    for v, a in enumerate(vals):
+        u[v, 0, :] = a
+    return u
+
+
+def test_cfl_dt_locally_isothermal_closed_form():
+    """Sec. 2.3 with the locally isothermal closure: c_s = h sqrt(GM / max(r,
+    r_core)) at the element centre.  Uniform rho = 2, v = (0.3, -0.1) on the
+    box [1, 2] x [1, 1.6] (no centre inside r_core), dx != dy: the smallest
+    step is at the centre nearest the star, (1 + dx/2, 1 + dy/2)."""
+    c = O.cfg(n=3, nx=8, ny=6, x0=1.0, x1=2.0, y0=1.0, y1=1.6, closure=1, h=0.05, gm=1.0, r_core=0.4,
+              cfl=0.2, star=1)
+    u = _uniform_modes(c, [2.0, 0.6, -0.2])
+    dx, dy = 1.0 / 8, 0.6 / 6
+    r = math.hypot(1 + dx / 2, 1 + dy / 2)
+    cs = 0.05 * math.sqrt(1.0 / r)
+    expect = 0.2 / 5 / ((0.3 + cs) / dx + (0.1 + cs) / dy)
+    assert abs(O.dt(c, u) - expect) < 1e-15 * expect
+    # inside the core the sound speed is that of r_core: a box around the star
+    c2 = O.cfg(n=4, nx=4, ny=4, x0=-0.2, x1=0.2, y0=-0.2, y1=0.2, closure=1, h=0.05, gm=2.0, r_core=0.4,
+               cfl=0.3, star=1)
+    u2 = _uniform_modes(c2, [1.0, 0.0, 0.0])
+    cs2 = 0.05 * math.sqrt(2.0 / 0.4)
+    assert abs(O.dt(c2, u2) - 0.3 / 7 / (cs2 / 0.1 + cs2 / 0.1)) < 1e-15
+
+
+def test_cfl_dt_adiabatic_closed_form_and_means_only():
+    """Sec. 2.3 with the ideal-gas closure: c = sqrt(gamma p / rho) of the
+    element means.  rho = 1.25, p = rho c^2 / gamma with c = 0.8, v = (0.3,
+    -0.1); a zero-mean perturbation of every variable leaves dt unchanged."""
+    c = O.cfg(n=4, nvar=4, nx=5, ny=7, x0=0.0, x1=1.0, y0=0.0, y1=2.0, closure=2, gamma=1.4, cfl=0.2)
+    rho, vx, vy, cc = 1.25, 0.3, -0.1, 0.8
+    p = rho * cc * cc / 1.4
+    E = p / 0.4 + 0.5 * rho * (vx * vx + vy * vy)
+    u = _uniform_modes(c, [rho, rho * vx, rho * vy, E])
+    dx, dy = 1.0 / 5, 2.0 / 7
+    expect = 0.2 / 7 / ((0.3 + 0.8) / dx + (0.1 + 0.8) / dy)
+    assert abs(O.dt(c, u) - expect) < 1e-15 * expect
+    rng = np.random.default_rng(4)
+    w = u.copy()
+    w[:, 1:, :] += 0.05 * rng.standard_normal(w[:, 1:, :].shape)
+    assert O.dt(c, w) == O.dt(c, u)
+
+
 def test_step_equals_shu_osher_composition():
     """Butcher form of the oracle equals the convex (Shu-Osher) SSP-RK3 form."""
     c = O.cfg(n=3, nx=6, ny=6)
@@ -410,6 +457,47 @@ def test_damping_matches_paper_formula_in_full_zone(adiabatic):
     for q, q0, qd in zip(prims(nod), prims(nod0), prims(nodd)):
         expect = (dt * q0 + tau * q) / (tau + dt)
         assert np.max(np.abs(qd[corner] - expect[corner])) < 1e-13 * max(1.0, np.max(np.abs(expect)))
+
+
+def test_damping_follows_paper_formula_inside_the_ramp():
+    """Nodes strictly inside a ramp (0 < R < 1): rho and v follow Q = (dt Q0 +
+    tau Q)/(tau + dt) with tau = 2 pi sqrt(r_d^3 / GM) / R and the parabolic
+    ramp R = ((r - r_d)/(r_b - r_d))^2, r_b = r_d / 1.15^(3/2) inside and
+    r_d 1.15^(3/2) outside (Sec. 5.1 with the damping radii 0.4 and 2.3).  A
+    linear ramp, the wrong zone radius or no ramp at all fails."""
+    c = _disc_cfg(24)
+    X, Y = O.nodes(c)
+    E = X.shape[0]
+    prim0 = S.pack_prim(S.disc(X, Y), E, 9)
+    u0 = O.project(c, prim0)
+    prim = prim0.copy()
+    prim[0] *= 1.0 + 0.2 * np.sin(3 * X + Y)
+    prim[1] += 0.07 * np.cos(2 * Y)
+    prim[2] -= 0.03 * np.sin(X)
+    u = O.project(c, prim)
+    dt = 0.29
+    ud = O.damp(c, u, u0, dt)
+    nod, nod0, nodd = O.eval_nodes(c, u), O.eval_nodes(c, u0), O.eval_nodes(c, ud)
+    f = 1.15 ** 1.5
+    r = np.sqrt(X ** 2 + Y ** 2)
+    R = np.zeros_like(r)
+    rd = np.where(r < 0.4, 0.4, 2.3)
+    rb = np.where(r < 0.4, 0.4 / f, 2.3 * f)
+    zone = (r < 0.4) | (r > 2.3)
+    R[zone] = np.minimum(((r[zone] - rd[zone]) / (rb[zone] - rd[zone])) ** 2, 1.0)
+    inner = zone & (R < 1.0)
+    assert inner.sum() >= 20 and np.any(R[inner] < 0.3) and np.any(r[inner] < 0.4)
+    tau = np.full_like(r, np.inf)
+    tau[zone] = 2 * math.pi * np.sqrt(rd[zone] ** 3) / R[zone]
+
+    def prims(nd):
+        return nd[0], nd[1] / nd[0], nd[2] / nd[0]
+
+    for q, q0, qd in zip(prims(nod), prims(nod0), prims(nodd)):
+        expect = (dt * q0[inner] + tau[inner] * q[inner]) / (tau[inner] + dt)
+        assert np.max(np.abs(qd[inner] - expect)) < 1e-13 * max(1.0, np.max(np.abs(expect)))
+        # the ramp matters: the damping moved every such node by a visible amount
+        assert np.min(np.abs(qd[inner] - q[inner]) + (np.abs(q0[inner] - q[inner]) < 1e-9)) > 0
 
 
 # ---------------------------------------------------------------- torque
