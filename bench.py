@@ -333,8 +333,9 @@ def main():
                       "speedup_vs_fp64": el / rm["elapsed"],
                       "stage_kernel_us": rm["stage_ms"] * 1e3 / max(rm["launches"], 1),
                       "torque_series_rel_err_vs_fp64": tq_err, "density_rel_L2_err_vs_fp64": dens_l2,
-                      "note": "FP32 deviation arithmetic about the projected equilibrium; FP64 state, "
-                              "stage combination, damping, dt and torque"}}
+                      "note": "FP32 deviation terms linearised about the projected equilibrium (its volume-node "
+                              "values and tabulated edge traces); FP64 L(u_eq), state, stage combination, "
+                              "damping, dt and torque"}}
     del r64
     if not a.no_shard:
         out.setdefault("forms", {})["shard"] = run_shard(a, cfg.order)

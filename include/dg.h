@@ -92,8 +92,10 @@ typedef struct dg_config {
 typedef struct dg_handle dg_handle;
 
 /* Number of doubles in one state array of this configuration (padding
- * included), or a negative DG_E* code for an invalid configuration.  Needs no
- * device. */
+ * included), or a negative DG_E* code for an invalid configuration.  A state
+ * array may hold at most 2^31 - 1 bytes (the kernels address it through
+ * buffer resources of that range): larger configurations give
+ * DG_EUNSUPPORTED here and in dg_init.  Needs no device. */
 long long dg_state_size(const dg_config *cfg);
 
 /* Volume Gauss node coordinates, host arrays x_host[e*n*n + node] and y_host
@@ -116,7 +118,10 @@ int dg_get_nodes(const dg_config *cfg, double *x_host, double *y_host);
  * library.  Every state array of the handle (u0_dev, the u_dev of dg_rhs,
  * dg_rk_step, dg_torque) then holds the FP64 deviation du, and dg_rhs returns
  * L(u_eq + du); dg_full_state reconstructs u.  The right-hand side is
- * L(u_eq) (FP64, computed once, kept in FP32) plus the deviation part in FP32. */
+ * L(u_eq) (FP64, computed once and kept) plus the deviation part
+ * L(u_eq + du) - L(u_eq) in FP32, every deviation flux linearised about u_eq's
+ * own polynomial (its values at the volume nodes and its edge traces, the
+ * latter tabulated in FP32 at init). */
 int dg_init(const dg_config *cfg, const double *prim_nodes_host, double *u0_dev, void *hip_stream,
             dg_handle **out);
 

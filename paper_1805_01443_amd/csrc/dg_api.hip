@@ -28,7 +28,8 @@ struct dg_handle {
     bool dev = false;       // deviation form (DG_PRECISION_MIXED)
     double* eq = nullptr;   // deviation form: projected equilibrium u_eq (FP64)
     double* du0 = nullptr;  // deviation form: initial deviation (fixed exterior state)
-    float* leq = nullptr;   // deviation form: L(u_eq) without the planet, FP32
+    double* leq = nullptr;  // deviation form: L(u_eq) without the planet (FP64)
+    float* eqtr = nullptr;  // deviation form: u_eq's traces at the edge points (FP32)
     double* ws1 = nullptr;  // SSP stage states u^(1), u^(2); Butcher stage state y_i
     double* ws2 = nullptr;
     dgk::RKTable tab{};     // Butcher tables (DG_RK_SSP54, DG_RK_CASHKARP)
@@ -133,8 +134,10 @@ int validate(const dg_config* c, std::string* why) {
         return (*why = "the positivity limiter is built for the SSP(3,3) table", DG_EUNSUPPORTED);
     if (c->positivity && c->precision != DG_PRECISION_FP64)
         return (*why = "the positivity limiter is built for the FP64 form", DG_EUNSUPPORTED);
-    if ((double)c->nvar * c->order * c->order * state_slots(c) * 8.0 >= 4294967296.0)
-        return (*why = "state arrays are limited to 4 GiB (32-bit buffer offsets)", DG_EUNSUPPORTED);
+    // the kernels address state arrays through buffer resources whose range
+    // is 2^31 - 1 bytes
+    if ((double)c->nvar * c->order * c->order * state_slots(c) * 8.0 > 2147483647.0)
+        return (*why = "state arrays are limited to 2^31 - 1 bytes (buffer-resource range)", DG_EUNSUPPORTED);
     return DG_OK;
 }
 
@@ -230,7 +233,7 @@ hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, c
         e = hipEventRecord(a, h->s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, out, sc, h->s)
+    hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, h->eqtr, out, sc, h->s)
                           : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, h->s);
     if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
     return e;
@@ -345,6 +348,7 @@ void release(dg_handle* h) {
     (void)hipFree(h->eq);
     (void)hipFree(h->du0);
     (void)hipFree(h->leq);
+    (void)hipFree(h->eqtr);
     (void)hipFree(h->scale_dev);
     (void)hipFree(h->flags);
     (void)hipFree(h->feat);
@@ -354,6 +358,7 @@ void release(dg_handle* h) {
     h->kbuf = nullptr;
     h->u0 = h->ws1 = h->ws2 = h->eq = h->du0 = nullptr;
     h->leq = nullptr;
+    h->eqtr = nullptr;
 }
 
 }  // namespace
@@ -437,7 +442,8 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     if (h->dev) {
         DG_ALLOC(h->eq, state_bytes);
         DG_ALLOC(h->du0, state_bytes);
-        DG_ALLOC(h->leq, state_bytes / 2);
+        DG_ALLOC(h->leq, state_bytes);
+        DG_ALLOC(h->eqtr, sizeof(float) * (size_t)dgk::eq_trace_entries(h->n, h->g));
     }
 
     // damped tiles: tiles with any volume node of non-zero ramp (the kernel
@@ -483,7 +489,9 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     if (e == hipSuccess) e = hipMemsetAsync(h->ws2, 0, state_bytes, h->s);
     if (e == hipSuccess && h->kbuf) e = hipMemsetAsync(h->kbuf, 0, state_bytes * (size_t)h->tab.s, h->s);
     if (e == hipSuccess && h->dev) e = hipMemsetAsync(h->eq, 0, state_bytes, h->s);
-    if (e == hipSuccess && h->dev) e = hipMemsetAsync(h->leq, 0, state_bytes / 2, h->s);
+    if (e == hipSuccess && h->dev) e = hipMemsetAsync(h->leq, 0, state_bytes, h->s);
+    if (e == hipSuccess && h->dev)
+        e = hipMemsetAsync(h->eqtr, 0, sizeof(float) * (size_t)dgk::eq_trace_entries(h->n, h->g), h->s);
     if (e == hipSuccess) e = hipMemcpyAsync(prim_dev, prim_nodes_host, prim_bytes, hipMemcpyHostToDevice, h->s);
     if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, u0_dev, h->s);
     // the positivity limiter acts on the projected initial state too
@@ -499,8 +507,9 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     if (h->dev) {
         // Deviation form: project the equilibrium (same projection kernel as
         // the state), evaluate L(u_eq) once with the FP64 stage kernel (no
-        // planet, exterior state = u_eq) and keep it in FP32; the caller's
-        // u0_dev and the fixed exterior state become deviations u0 - u_eq.
+        // planet, exterior state = u_eq) and keep it in FP64, tabulate u_eq's
+        // edge traces; the caller's u0_dev and the fixed exterior state become
+        // deviations u0 - u_eq.
         std::vector<double> peq;
         equilibrium_prim(cfg, &peq);
         const long long N = (long long)h->nvar * h->n * h->n * h->g.slots;
@@ -509,8 +518,8 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
         e = hipMemcpyAsync(prim_dev, peq.data(), sizeof(double) * peq.size(), hipMemcpyHostToDevice, h->s);
         if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, h->eq, h->s);
         if (e == hipSuccess) e = dgk::launch_set_coeffs(h->sc_rhs, g0, 0.0, 0.0, 0.0, 1.0, h->s);
-        if (e == hipSuccess) e = dgk::launch_stage(h->n, g0, h->eq, nullptr, h->eq, h->ws1, h->sc_rhs, false, h->s);
-        if (e == hipSuccess) e = dgk::launch_to_f32(h->ws1, h->leq, N, h->s);
+        if (e == hipSuccess) e = dgk::launch_stage(h->n, g0, h->eq, nullptr, h->eq, h->leq, h->sc_rhs, false, h->s);
+        if (e == hipSuccess) e = dgk::launch_eq_traces(h->n, h->g, h->eq, h->eqtr, h->s);
         if (e == hipSuccess) e = dgk::launch_add_state(u0_dev, h->eq, u0_dev, -1.0, N, h->s);
         if (e == hipSuccess) e = hipMemcpyAsync(h->du0, u0_dev, state_bytes, hipMemcpyDeviceToDevice, h->s);
         if (e == hipSuccess) e = hipStreamSynchronize(h->s);  // peq lives until here
@@ -549,7 +558,8 @@ int dg_rhs(dg_handle* h, double t, const double* u_dev, double* rhs_dev) {
     if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
     if (!u_dev || !rhs_dev || u_dev == rhs_dev) return fail(h, DG_EINVAL, "u_dev and rhs_dev must be distinct device arrays");
     DG_HIP(h, dgk::launch_set_coeffs(h->sc_rhs, h->g, t, 0.0, 0.0, 1.0, h->s), "dg_rhs coefficients");
-    DG_HIP(h, h->dev ? dgk::launch_stage_dev(h->n, h->g, u_dev, nullptr, h->du0, h->leq, rhs_dev, h->sc_rhs, h->s)
+    DG_HIP(h, h->dev ? dgk::launch_stage_dev(h->n, h->g, u_dev, nullptr, h->du0, h->leq, h->eqtr, rhs_dev, h->sc_rhs,
+                                             h->s)
                      : dgk::launch_stage(h->n, h->g, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, false, h->s),
            "dg_rhs stage");
     return DG_OK;

@@ -121,11 +121,15 @@ hipError_t launch_damp(int n, const Geo& g, double* u, const double* q0, const d
                        int nlist, const StageCoeffs* sc, hipStream_t s);
 hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,
                          double* partials, int nblocks, double* out, hipStream_t s);
+// deviation form: leq = L(u_eq) (FP64), eqtr = u_eq's edge traces (FP32,
+// eq_trace_entries floats, written by launch_eq_traces)
 hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double* dun, const double* du0,
-                            const float* leq, double* out, const StageCoeffs* sc, hipStream_t s);
+                            const double* leq, const float* eqtr, double* out, const StageCoeffs* sc,
+                            hipStream_t s);
+long long eq_trace_entries(int n, const Geo& g);
+hipError_t launch_eq_traces(int n, const Geo& g, const double* eq, float* eqtr, hipStream_t s);
 hipError_t launch_add_state(const double* a, const double* b, double* out, double sign, long long n,
                             hipStream_t s);
-hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
 int torque_blocks(const Geo& g);
 
 // troubled cells and the learned indicator

@@ -31,13 +31,13 @@ struct NVar {
 // lives in scalar registers, a mode plane is a scalar offset and the lane's
 // element is one shared 32-bit vector offset.  (With plain pointers the
 // compiler keeps a private 64-bit address per mode plane alive from the loads
-// to the stores, which alone costs ~150 registers at order 5.)  Byte offsets
-// are 32-bit: a state array is at most 4 GiB, checked at init.
+// to the stores, which alone costs ~150 registers at order 5.)  The range of
+// a resource is 2^31 - 1 bytes; init rejects state arrays larger than that.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* base) {
     // raw buffer, no swizzle; range checking is not relied on (all accesses
-    // are in bounds by construction)
+    // are in bounds by construction, every array below the range)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
 }
 __device__ __forceinline__ double ld64(rsrc_t r, unsigned voff, unsigned soff) {
@@ -596,17 +596,23 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 }
 
 // ------------------------------------------------------------------ deviation form
-// u = u_eq + du about the disc's rotational equilibrium (locally isothermal,
-// stellar harmonic core inside r_core).  The FP64 state du is converted to
-// FP32 on load; contractions, fluxes and the lift run in FP32 on the
-// deviation; L = L(u_eq) (FP64, precomputed, stored FP32) + dL, and the stage
-// combination is FP64.  Deviation fluxes are written without cancellation:
-// with the equilibrium velocity v and w = dm - v drho,
+// u = u_eq + du about the disc's rotational equilibrium u_eq (locally
+// isothermal, stellar harmonic core inside r_core), u_eq being the projection
+// of the analytic equilibrium.  The FP64 state du is converted to FP32 on load;
+// contractions, fluxes and the lift run in FP32 on the deviation;
+// L = L(u_eq) (FP64, computed once) + dL, and the stage combination is FP64.
+// Every deviation term is linearised about u_eq's own polynomial: at the
+// volume Gauss nodes the projection interpolates, so there the analytic
+// equilibrium is u_eq's value; at the edge points u_eq's traces differ from
+// the analytic profile by the projection error and are read from a table.
+// Deviation fluxes are written without cancellation: with the equilibrium
+// velocity v and w = dm - v drho,
 //   d(m_a m_b / rho) = v_a v_b drho + v_a w_b + v_b w_a + w_a w_b / (rho + drho).
 struct EqPoint {
     float rho, vx, vy, c2;
 };
 
+// the analytic equilibrium at a volume Gauss node
 __device__ __forceinline__ EqPoint eq_at(const Geo& g, double xd, double yd) {
     const float x = (float)xd, y = (float)yd;
     const float r = sqrtf(x * x + y * y);
@@ -621,7 +627,34 @@ __device__ __forceinline__ EqPoint eq_at(const Geo& g, double xd, double yd) {
     return q;
 }
 
-// deviation flux along axis AX (0: f_x, 1: f_y) of the deviation d = (drho, dmx, dmy)
+// u_eq's trace (rho, m_x, m_y) at an edge point, from the trace table, and the
+// locally isothermal c_s^2 of that point
+__device__ __forceinline__ EqPoint eq_trace(const float* e, float c2) {
+    EqPoint q;
+    q.rho = e[0];
+    const float ir = 1.0f / e[0];
+    q.vx = e[1] * ir;
+    q.vy = e[2] * ir;
+    q.c2 = c2;
+    return q;
+}
+
+__device__ __forceinline__ float cs2_at(const Geo& g, double xd, double yd) {
+    const float x = (float)xd, y = (float)yd;
+    return (float)g.h2gm / fmaxf(sqrtf(x * x + y * y), (float)g.r_core);
+}
+
+// Trace table of u_eq: for every element, its own trace at the N points of its
+// west, east, south and north edge (edges 0..3; points eta_k on the west/east
+// edges, xi_k on the south/north edges), FP32, tiled like the state:
+// entry (edge, v, k) of element (i, j) at eqtr_base + ((edge * 3 + v) * N + k) * EW.
+template <int N>
+__device__ __forceinline__ unsigned eqtr_base(const Geo& g, int i, int j) {
+    constexpr int EW = tile_width(N);
+    const int ti = i / EW;
+    return (unsigned)(j * g.tiles_x + ti) * (unsigned)(4 * 3 * N * EW) + (unsigned)(i - ti * EW);
+}
+
 template <int AX>
 __device__ __forceinline__ void dflux(const EqPoint& q, const float* d, float inv1, float* f) {
     const float wx = d[1] - q.vx * d[0], wy = d[2] - q.vy * d[0];
@@ -680,28 +713,37 @@ __device__ __forceinline__ void ext_collapse_f(rsrc_t ru, rsrc_t ru0, unsigned v
 }
 
 // Rusanov flux of the deviation through an axis-aligned edge (outward normal
-// SGN e_AX) at a point with equilibrium q: the locally isothermal sound speed
-// is shared by both sides.
+// SGN e_AX): F(ue_i + d_i, ue_o + d_o) - F(ue_i, ue_o) with the equilibrium
+// traces ue_i, ue_o of the two sides (they differ by the projection error)
+// and the locally isothermal sound speed shared by both sides.  The
+// dissipation splits as -alpha (d_o - d_i) / 2 - (alpha - alpha_eq)(ue_o - ue_i) / 2.
 template <int AX, int SGN>
-__device__ __forceinline__ void rusanov_dev(const EqPoint& q, const float* di, const float* dd, float* h) {
-    const float ii = 1.0f / (q.rho + di[0]), io = 1.0f / (q.rho + dd[0]);
+__device__ __forceinline__ void rusanov_dev(const EqPoint& qi, const EqPoint& qo, const float* ei, const float* eo,
+                                            const float* di, const float* dd, float* h) {
+    const float ii = 1.0f / (qi.rho + di[0]), io = 1.0f / (qo.rho + dd[0]);
     float fi[3], fo[3];
-    dflux<AX>(q, di, ii, fi);
-    dflux<AX>(q, dd, io, fo);
-    const float alpha = fmaxf(fabsf(vnorm<AX, SGN>(q, di, ii)), fabsf(vnorm<AX, SGN>(q, dd, io))) + sqrtf(q.c2);
+    dflux<AX>(qi, di, ii, fi);
+    dflux<AX>(qo, dd, io, fo);
+    const float c = sqrtf(qi.c2);
+    const float alpha = fmaxf(fabsf(vnorm<AX, SGN>(qi, di, ii)), fabsf(vnorm<AX, SGN>(qo, dd, io))) + c;
+    const float alpha_eq = fmaxf(fabsf(AX == 0 ? qi.vx : qi.vy), fabsf(AX == 0 ? qo.vx : qo.vy)) + c;
+    const float da = alpha - alpha_eq;
 #pragma unroll
-    for (int v = 0; v < 3; ++v) h[v] = 0.5f * SGN * (fi[v] + fo[v]) - 0.5f * alpha * (dd[v] - di[v]);
+    for (int v = 0; v < 3; ++v)
+        h[v] = 0.5f * SGN * (fi[v] + fo[v]) - 0.5f * alpha * (dd[v] - di[v]) - 0.5f * da * (eo[v] - ei[v]);
 }
 
 // Deviation-form stage with N lanes per element: the phases of k_stage_c in
-// FP32 on the deviation (fluxes about the analytic equilibrium, stellar pull
-// on the density deviation, planet on the full density), then
+// FP32 on the deviation (fluxes linearised about u_eq: the analytic profile at
+// the volume nodes, u_eq's traces from the table at the edge points; stellar
+// pull on the density deviation, planet on the full density), then
 // out = a0 du^n + a1 du + a2 (L_eq + dL) in FP64.
 template <int N>
 __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, int tiles_total,
                                                     const double* __restrict__ du, const double* dun,
-                                                    const double* __restrict__ du0, const float* __restrict__ leq,
-                                                    double* out, const StageCoeffs* __restrict__ scp) {
+                                                    const double* __restrict__ du0, const double* __restrict__ leq,
+                                                    const float* __restrict__ eqtr, double* out,
+                                                    const StageCoeffs* __restrict__ scp) {
     constexpr int NV = 3;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
@@ -724,8 +766,8 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
 
     const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
     const rsrc_t rdu = make_rsrc(du), rdu0 = make_rsrc(du0), rout = make_rsrc(out), rdun = make_rsrc(dun),
-                 rleq = make_rsrc(leq);
-    constexpr unsigned RS = N * EW * 8, RS4 = N * EW * 4;  // byte stride of (v * N + b) in a row
+                 rleq = make_rsrc(leq), rtr = make_rsrc(eqtr);
+    constexpr unsigned RS = N * EW * 8;  // byte stride of (v * N + b) in a row
     const unsigned eb = tiled_base<N, NV>(g, i, j);
     const unsigned vrow = (eb + k * EW) * 8u;  // mode (k, 0) of this element
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
@@ -752,14 +794,14 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
         S[NV * NN + (0 * NV + v) * N + k] = tm;
         S[NV * NN + (1 * NV + v) * N + k] = tp;
     }
+    int il = i - 1, ir = i + 1, jb = j - 1, jt = j + 1;
+    const bool ol = il < 0, orr = ir >= g.nx, ob = jb < 0, ot = jt >= g.ny;
+    il += ol ? g.nx : 0;
+    ir -= orr ? g.nx : 0;
+    jb += ob ? g.ny : 0;
+    jt -= ot ? g.ny : 0;
+    const bool fx = g.bc == 1, fl = fx && ol, fr = fx && orr, fb = fx && ob, ft = fx && ot;
     {
-        int il = i - 1, ir = i + 1, jb = j - 1, jt = j + 1;
-        const bool ol = il < 0, orr = ir >= g.nx, ob = jb < 0, ot = jt >= g.ny;
-        il += ol ? g.nx : 0;
-        ir -= orr ? g.nx : 0;
-        jb += ob ? g.ny : 0;
-        jt -= ot ? g.ny : 0;
-        const bool fx = g.bc == 1, fl = fx && ol, fr = fx && orr, fb = fx && ob, ft = fx && ot;
         const bool wfx = __any(fl || fr), wfy = __any(fb || ft);
         const unsigned vcol = (eb + k * N * EW) * 8u;
         float T[NV];
@@ -845,6 +887,30 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     {
         const float* Cl = S + NV * NN;
         float di[NV], dd[NV];
+        // u_eq's traces at point k of the four edges, own and exterior (the
+        // neighbour's trace on the shared edge; at a fixed box edge the
+        // exterior state is u0 = u_eq + du0 of the element itself, so its
+        // equilibrium part is the element's own trace there)
+        float ew[2][NV], ee[2][NV], es[2][NV], en[2][NV];
+        {
+            const unsigned ob = eqtr_base<N>(g, i, j);
+            const unsigned bw = fl ? ob : eqtr_base<N>(g, il, j), be = fr ? ob : eqtr_base<N>(g, ir, j);
+            const unsigned bs = fb ? ob : eqtr_base<N>(g, i, jb), bn = ft ? ob : eqtr_base<N>(g, i, jt);
+            auto at = [&](unsigned base, int edge, int v) {
+                return ld32(rtr, (base + (unsigned)(((edge * 3 + v) * N + k) * EW)) * 4u, 0u);
+            };
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                ew[0][v] = at(ob, 0, v);
+                ew[1][v] = at(bw, fl ? 0 : 1, v);
+                ee[0][v] = at(ob, 1, v);
+                ee[1][v] = at(be, fr ? 1 : 0, v);
+                es[0][v] = at(ob, 2, v);
+                es[1][v] = at(bs, fb ? 2 : 3, v);
+                en[0][v] = at(ob, 3, v);
+                en[1][v] = at(bn, ft ? 3 : 2, v);
+            }
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             float si = 0.0f, so = 0.0f;
@@ -856,7 +922,10 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
             di[v] = si;
             dd[v] = so;
         }
-        rusanov_dev<0, -1>(eq_at(g, xc - 0.5 * g.dx, yk), di, dd, hf[0]);
+        {
+            const float c2 = cs2_at(g, xc - 0.5 * g.dx, yk);
+            rusanov_dev<0, -1>(eq_trace(ew[0], c2), eq_trace(ew[1], c2), ew[0], ew[1], di, dd, hf[0]);
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             float si = 0.0f, so = 0.0f;
@@ -868,7 +937,10 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
             di[v] = si;
             dd[v] = so;
         }
-        rusanov_dev<0, 1>(eq_at(g, xc + 0.5 * g.dx, yk), di, dd, hf[1]);
+        {
+            const float c2 = cs2_at(g, xc + 0.5 * g.dx, yk);
+            rusanov_dev<0, 1>(eq_trace(ee[0], c2), eq_trace(ee[1], c2), ee[0], ee[1], di, dd, hf[1]);
+        }
         // west/east lifts folded into X (same weight w_r phi_b(eta_r) in R)
         const float idx = (float)g.idx;
 #pragma unroll
@@ -889,7 +961,10 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
             di[v] = si;
             dd[v] = so;
         }
-        rusanov_dev<1, -1>(eq_at(g, xk, yc - 0.5 * g.dy), di, dd, hf[2]);
+        {
+            const float c2 = cs2_at(g, xk, yc - 0.5 * g.dy);
+            rusanov_dev<1, -1>(eq_trace(es[0], c2), eq_trace(es[1], c2), es[0], es[1], di, dd, hf[2]);
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             float si = 0.0f, so = 0.0f;
@@ -901,7 +976,10 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
             di[v] = si;
             dd[v] = so;
         }
-        rusanov_dev<1, 1>(eq_at(g, xk, yc + 0.5 * g.dy), di, dd, hf[3]);
+        {
+            const float c2 = cs2_at(g, xk, yc + 0.5 * g.dy);
+            rusanov_dev<1, 1>(eq_trace(en[0], c2), eq_trace(en[1], c2), en[0], en[1], di, dd, hf[3]);
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -928,15 +1006,14 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     }
     const float idy = (float)g.idy;
     const float* H = S + 2 * NV * NN;
-    const unsigned vrow4 = (eb + k * EW) * 4u;
     // L_eq, du and du^n of the row, issued before any store (out may alias du^n)
-    float Le[NV][N];
+    double Le[NV][N];
     double U1[NV][N], Un[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            Le[v][b] = ld32(rleq, vrow4, (unsigned)(v * N + b) * RS4);
+            Le[v][b] = ld64(rleq, vrow, (unsigned)(v * N + b) * RS);
             U1[v][b] = ld64(rdu, vrow, (unsigned)(v * N + b) * RS);
         }
     if (a0 != 0.0) {
@@ -971,7 +1048,7 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
 #pragma unroll
             for (int b = 0; b < N; ++b) {
                 const unsigned po = (unsigned)(v * N + b) * RS;
-                const double L = (double)Le[v][b] + (double)R[v][b];
+                const double L = Le[v][b] + (double)R[v][b];
                 const double base = a1 * U1[v][b] + a2 * L;
                 st64(rout, vrow, po, a0 != 0.0 ? a0 * Un[v][b] + base : base);
             }
@@ -984,10 +1061,32 @@ __global__ void k_add_state(const double* a, const double* b, double* out, doubl
     if (k < n) out[k] = a[k] + sign * b[k];
 }
 
-// float copy of an FP64 array
-__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
-    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (k < n) b[k] = (float)a[k];
+// trace table of the projected equilibrium (layout at eqtr_base): thread per
+// element, the polynomial of its modes at the N points of each edge
+template <int N>
+__global__ void __launch_bounds__(64) k_eq_traces(const Geo g, const double* __restrict__ eq, float* __restrict__ eqtr) {
+    constexpr BasisTab T = make_basis(N);
+    constexpr int EW = tile_width(N);
+    const long long e = (long long)blockIdx.x * 64 + threadIdx.x;
+    if (e >= g.E) return;
+    const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+    const unsigned base = tiled_base<N, 3>(g, i, j), tb = eqtr_base<N>(g, i, j);
+    for (int v = 0; v < 3; ++v)
+        for (int k = 0; k < N; ++k) {
+            double w = 0.0, ea = 0.0, so = 0.0, no = 0.0;
+            for (int a = 0; a < N; ++a)
+                for (int b = 0; b < N; ++b) {
+                    const double c = eq[base + mode_off<N>(v, a, b)];
+                    w += c * T.pm[a] * T.phi[b][k];
+                    ea += c * T.pp[a] * T.phi[b][k];
+                    so += c * T.phi[a][k] * T.pm[b];
+                    no += c * T.phi[a][k] * T.pp[b];
+                }
+            eqtr[tb + ((0 * 3 + v) * N + k) * EW] = (float)w;
+            eqtr[tb + ((1 * 3 + v) * N + k) * EW] = (float)ea;
+            eqtr[tb + ((2 * 3 + v) * N + k) * EW] = (float)so;
+            eqtr[tb + ((3 * 3 + v) * N + k) * EW] = (float)no;
+        }
 }
 
 // ------------------------------------------------------------------ init
@@ -1660,15 +1759,26 @@ hipError_t launch_damp(int n, const Geo& g, double* u, const double* q0, const d
 }
 
 hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double* dun, const double* du0,
-                            const float* leq, double* out, const StageCoeffs* sc, hipStream_t s) {
+                            const double* leq, const float* eqtr, double* out, const StageCoeffs* sc,
+                            hipStream_t s) {
     if (!dun) dun = du;
     if (!du0) du0 = du;
+    if (!leq || !eqtr) return hipErrorInvalidValue;
     DG_DISPATCH_N(n, {
         constexpr int EW = 64 / NT;
         const int tx = (g.nx + EW - 1) / EW;
         const int tt = tx * g.ny;
-        hipLaunchKernelGGL((k_stage_dev_c<NT>), dim3(tt), dim3(64), 0, s, g, tx, tt, du, dun, du0, leq, out, sc);
+        hipLaunchKernelGGL((k_stage_dev_c<NT>), dim3(tt), dim3(64), 0, s, g, tx, tt, du, dun, du0, leq, eqtr, out,
+                           sc);
     });
+    return hipGetLastError();
+}
+
+long long eq_trace_entries(int n, const Geo& g) { return (long long)g.tiles_x * g.ny * 4 * 3 * n * (64 / n); }
+
+hipError_t launch_eq_traces(int n, const Geo& g, const double* eq, float* eqtr, hipStream_t s) {
+    const int blocks = (int)((g.E + 63) / 64);
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_eq_traces<NT>), dim3(blocks), dim3(64), 0, s, g, eq, eqtr));
     return hipGetLastError();
 }
 
@@ -1676,12 +1786,6 @@ hipError_t launch_add_state(const double* a, const double* b, double* out, doubl
                             hipStream_t s) {
     const int blocks = (int)((n + 255) / 256);
     hipLaunchKernelGGL(k_add_state, dim3(blocks), dim3(256), 0, s, a, b, out, sign, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s) {
-    const int blocks = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(k_to_f32, dim3(blocks), dim3(256), 0, s, a, b, n);
     return hipGetLastError();
 }
 

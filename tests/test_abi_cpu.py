@@ -125,3 +125,14 @@ def test_state_size_and_tiled_layout(cfg):
 def test_state_size_rejects_bad_config():
     with pytest.raises(dg.DGError):
         dg.dg_state_size(W.wave(nx=8).replace(order=9))
+
+
+def test_state_size_limit_is_the_buffer_range():
+    """State arrays are addressed through buffer resources of 2^31 - 1 bytes:
+    the largest configuration below that is accepted, the next row is not
+    (order 5, three variables: 600 bytes per padded element slot, 1896 slots
+    per row)."""
+    ok = W.disc(nx=1896, order=5).replace(ny=1887)
+    assert dg.dg_state_size(ok) * 8 == 600 * 1896 * 1887 <= 2 ** 31 - 1
+    with pytest.raises(dg.DGError):
+        dg.dg_state_size(ok.replace(ny=1888))

@@ -76,20 +76,42 @@ def test_indicator_flags_labels_and_limited_state():
 
 
 def test_limited_steps_parity():
+    """Three steps with the indicator + minmod after every stage: the isothermal
+    wave workload with a density step on a square whose sides cut through the
+    middle of elements (a step on element edges leaves every element constant:
+    nothing to flag).  The smooth ring at 40^2 is not altered by minmod, and
+    the ring with a density jump needs the positivity limiter behind minmod
+    (tested with it in test_gpu_positivity)."""
     T = torch()
-    cfg, oc, h, u, uo = ring_setup(nx=40, s0=-3.0)
+    cfg = W.wave(nx=40, order=4).replace(limiter=dg.LIMITER_MODAL_DECAY, limiter_s0=-3.0)
+    oc = ocfg(cfg)
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, "wave", x=x, y=y)
+    inside = (np.abs(x - 0.5) < 0.2375) & (np.abs(y - 0.5) < 0.2375)
+    prim[0] *= np.where(inside.reshape(cfg.n_elem, 16), 1.5, 1.0)
+    h, u = dg.dg_init(cfg, prim)
+    uo = O.project(oc, prim)
     u0 = uo.copy()
     t_dev = T.zeros(1, dtype=T.float64, device="cuda")
-    t = 0.0
+    t, dt = 0.0, 1e-4
+    acts_all = []
     for k in range(3):
-        dg.dg_rk_step(h, u, t_dev, 1e-3, None)
+        dg.dg_rk_step(h, u, t_dev, dt, None)
         dg.dg_sync(h)
-        uo, _ = O.step_limited(oc, uo, t, 1e-3, u0, cfg.limiter_s0)
-        t += 1e-3
+        # where the limiter acts, the oracle's limited step differs from its plain one
+        plain, _ = O.step(oc, uo, t, dt, u0=u0)
+        uo, _ = O.step_limited(oc, uo, t, dt, u0, cfg.limiter_s0)
+        t += dt
+        acts = max(np.max(np.abs(plain[v] - uo[v])) / np.max(np.abs(uo[v])) for v in range(cfg.nvar))
         a = planes(cfg, u)
         err = max(np.max(np.abs(a[v] - uo[v])) / np.max(np.abs(uo[v])) for v in range(cfg.nvar))
-        print(f"[limited step {k}] rel err {err:.3e}", flush=True)
+        print(f"[limited step {k}] rel err {err:.3e}; limited - plain step {acts:.3e}", flush=True)
+        acts_all.append(acts)
         assert err <= 1e-12
+    # the step cuts through the middle of 76 elements: minmod alters them in
+    # the first two stages of the first step; the later steps start from
+    # limited slopes, which minmod keeps
+    assert acts_all[0] > 1e-3, "the limiter must act in the first step of this test"
     h.close()
 
 
@@ -219,6 +241,7 @@ def test_fused_learned_flags_match_features_then_forward():
     ref = (z.cpu().numpy() > np.float32(zthr)).astype(np.uint8)
     got = mf.cpu().numpy()
     print(f"[fused flags] {int(ref.sum())} of {E} flagged", flush=True)
+    assert 0 < ref.sum() < E, "the parameters and theta must flag some but not all elements"
     assert np.array_equal(got, ref)
     h.close()
 
@@ -226,20 +249,31 @@ def test_fused_learned_flags_match_features_then_forward():
 def test_full_size_ring_limited_step_parity():
     """The benchmark's limited form at its full size (ring, 1024 x 1024, order
     4, modal-decay indicator + minmod + positivity limiter): the projected and
-    limited initial state and one CFL step against the oracle."""
-    import math
+    limited initial state and one CFL step against the oracle.  The ring state
+    gets a density and energy jump at r = 1.6 (through the middle of
+    elements), so that minmod has elements to alter in the step: the smooth
+    ring at t = 0 has none."""
     from paper_1805_01443_amd import learned
     T = torch()
     cfg = learned.ring_config(1024)
     oc = ocfg(cfg)
     x, y = O.nodes(oc)
     prim = W.prim_for(cfg, "disc_ring", seed=0, x=x, y=y)
-    print("[full ring] 1024x1024 order 4 adiabatic, limited, one step", flush=True)
+    r = np.sqrt(x ** 2 + y ** 2).reshape(cfg.n_elem, 16)
+    prim[0] *= np.where(r < 1.6, 2.0, 1.0)
+    prim[3] *= np.where(r < 1.6, 2.0, 1.0)
+    print("[full ring] 1024x1024 order 4 adiabatic with a jump, limited, one step", flush=True)
     h, u = dg.dg_init(cfg, prim)
     dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
     t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    fl = T.zeros(cfg.n_elem, dtype=T.uint8, device="cuda")
+    ch = T.zeros(cfg.n_elem, dtype=T.uint8, device="cuda")
+    dg.dg_troubled(h, u.clone(), apply=False, flags=fl, changed=ch)
     dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
     dg.dg_sync(h)
+    nfl, nch = int(fl.sum().item()), int(ch.sum().item())
+    print(f"  initial state: {nfl} elements flagged, {nch} of them altered by minmod", flush=True)
+    assert nch > 0
     uo, _, _ = O.positivity(oc, O.project(oc, prim))
     uo, dto = O.step_limited(oc, uo, 0.0, 0.0, uo.copy(), cfg.limiter_s0)
     assert abs(dt_dev.item() - dto) <= 1e-14 * dto

@@ -1,17 +1,17 @@
 """GPU tests of the mixed-precision deviation form (u = u_eq + du, FP32
 deviation arithmetic, FP64 state / stage accumulation / torque).
 
-Pin: at du = 0 without planet the right-hand side equals the FP32 rounding of
-the FP64 L(u_eq) bitwise (every deviation term is exactly zero).  Beyond that
-the form is not bit-identical by design, and its error is not FP32 rounding
-alone: the deviation fluxes and the Rusanov dissipation are linearised about
-the analytic equilibrium at each point, while L(u_eq) holds the projected
-equilibrium; the differences are (deviation) x (projection error of the
-equilibrium), largest at the kink of the profile at r = r_core and where the
-1e-4 density noise makes the density residual small.  Measured at 44^2, order 3:
-1.7e-4 of max|L_rho| on the annulus, 5e-5 over the box; the bound below is 1e-3
-(documented, parity unpinned beyond it).  The 5-step test checks the state
-against the FP64 GPU path on the annulus at 1e-5 (the state changes by dt L)."""
+Pin: at du = 0 without planet the right-hand side equals the FP64 L(u_eq)
+bitwise (every deviation term is exactly zero).  Beyond that the form is not
+bit-identical by design: L = L(u_eq) (FP64) + [L(u_eq + du) - L(u_eq)], the
+bracket evaluated in FP32 and linearised about u_eq's own polynomial (its
+values at the volume nodes, where the projection interpolates the analytic
+profile, and its tabulated edge traces).  So the error is FP32 rounding of the
+deviation terms: one right-hand side is checked against the FP64 oracle to
+1e-5 of max|L_v| over the whole box (FP32 epsilon 6e-8 times the sums of
+up to 2n terms and the 1/dx of the lift), the first step's CFL dt (from the
+FP64 means of u_eq + du0) to 1e-13, and five steps against the FP64 GPU path
+to 1e-5 of max|u_v| and to 1e-4 of the evolved deviation itself."""
 import dataclasses
 
 import numpy as np
@@ -22,8 +22,10 @@ from paper_1805_01443_amd import configs as W
 from paper_1805_01443_amd import dg
 
 pytestmark = pytest.mark.gpu
-BOUND = 1e-5      # state after steps, torque
-BOUND_RHS = 1e-3  # one right-hand side against the FP64 oracle
+BOUND = 1e-5      # state after steps (of max|u_v|), torque (of the sum of |terms|)
+BOUND_RHS = 1e-5  # one right-hand side against the FP64 oracle (of max|L_v|)
+BOUND_DEV = 1e-4  # state after steps, of the evolved deviation u - u_eq
+BOUND_DT1 = 1e-13 # first CFL step: FP64 means on both sides
 
 
 def torch():
@@ -57,17 +59,7 @@ def radii(cfg):
     return np.hypot(cfg.x0 + (i + 0.5) * dx, cfg.y0 + (j + 0.5) * dy)
 
 
-def annulus(cfg):
-    """the undamped disc away from the core kink of the equilibrium at
-    r = r_core: there the deviation form linearises about the analytic
-    equilibrium while the state holds its projection, which differs by the
-    projection error of the kinked profile (second order in it times the
-    deviation); elsewhere the error is FP32 rounding"""
-    r = radii(cfg)
-    return (r > 0.55) & (r < 2.2)
-
-
-def test_zero_deviation_gives_fp32_of_equilibrium_rhs_bitwise():
+def test_zero_deviation_gives_the_equilibrium_rhs_bitwise():
     T = torch()
     cfg = W.disc(nx=40, order=5, q=0.0).replace(bc=dg.BC_PERIODIC, precision=dg.PRECISION_MIXED, sigma0=1.3)
     prim = W.prim_for(cfg, "disc_eq")
@@ -83,7 +75,7 @@ def test_zero_deviation_gives_fp32_of_equilibrium_rhs_bitwise():
     r64 = T.zeros_like(du0)
     dg.dg_rhs(h64, 0.0, ueq, r64)
     T.cuda.synchronize()
-    assert T.equal(rm, r64.float().double())
+    assert T.equal(rm, r64)
     hm.close()
     h64.close()
 
@@ -116,13 +108,11 @@ def test_mixed_rhs_error_against_oracle(order):
     uo = O.project(oc, prim)
     ro = O.rhs(oc, 0.37, uo, u0=uo)
     rg = planes(cfg, r)
-    err_all = relerr(rg, ro)
-    err = relerr(rg, ro, annulus(cfg))
+    err = relerr(rg, ro)
     worst = int(np.argmax(np.max(np.abs(rg - ro), axis=(0, 1))))
-    print(f"[mixed rhs] order {order}: rel err vs FP64 oracle, annulus {err}, whole box {err_all} "
-          f"(largest at r = {radii(cfg)[worst]:.3f})", flush=True)
+    print(f"[mixed rhs] order {order}: rel err vs FP64 oracle {err} (largest at r = {radii(cfg)[worst]:.3f})",
+          flush=True)
     assert max(err) <= BOUND_RHS
-    assert max(err_all) <= BOUND_RHS
     hm.close()
 
 
@@ -138,21 +128,23 @@ def test_mixed_steps_and_torque_against_fp64_gpu():
     dt64 = T.zeros(1, dtype=T.float64, device="cuda")
     gm = T.zeros(1, dtype=T.float64, device="cuda")
     g64 = T.zeros(1, dtype=T.float64, device="cuda")
+    dts = []
     for _ in range(5):
         dg.dg_rk_step(hm, du, tm, 0.0, dtm)
         dg.dg_rk_step(h64, u, t64, 0.0, dt64)
+        dts.append((dtm.item(), dt64.item()))
     dg.dg_torque(hm, du, gm, t_dev=tm)
     dg.dg_torque(h64, u, g64, t_dev=t64)
     dg.dg_sync(hm)
     dg.dg_sync(h64)
-    # the CFL minimum sits at the core, where the states differ most
-    assert abs(dtm.item() - dt64.item()) <= BOUND * dt64.item()
+    dt_err = [abs(a - b) / b for a, b in dts]
+    print(f"[mixed 5 steps] dt rel err per step {dt_err}", flush=True)
+    assert dt_err[0] <= BOUND_DT1
+    assert max(dt_err) <= BOUND
     full = T.empty_like(du)
     dg.dg_full_state(hm, du, full)
     T.cuda.synchronize()
-    e_all = relerr(planes(cfg, full), planes(cfg, u))
-    e = relerr(planes(cfg, full), planes(cfg, u), annulus(cfg))
-    print(f"[mixed 5 steps] whole-box state rel err {e_all}", flush=True)
+    e = relerr(planes(cfg, full), planes(cfg, u))
     # deviation from the equilibrium: error relative to the evolved deviation itself
     dev64 = u - (full - du)
     ed = (full - u).abs().max().item() / dev64.abs().max().item()
@@ -160,6 +152,7 @@ def test_mixed_steps_and_torque_against_fp64_gpu():
     print(f"[mixed 5 steps] state rel err {e}, rel to deviation {ed:.3e}, "
           f"torque {gm.item():.12e} vs {g64.item():.12e}", flush=True)
     assert max(e) <= BOUND
+    assert ed <= BOUND_DEV
     assert abs(gm.item() - g64.item()) <= BOUND * sabs
     hm.close()
     h64.close()
