@@ -153,6 +153,22 @@ int dg_rk_step(dg_handle *h, double *u_dev, double *t_dev, double dt_fixed, doub
  * give identical bits. */
 int dg_torque(dg_handle *h, double t, const double *t_dev, const double *u_dev, double *torque_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the torque of
+ * dg_torque, same kernels, same bits, without a handle.  cfg describes the
+ * state (FP64 form only: DG_PRECISION_MIXED gives DG_EUNSUPPORTED); u_dev,
+ * t_dev (may be NULL: then t) and torque_dev are device memory as in
+ * dg_torque; the work is queued on hip_stream (NULL = default stream).  The
+ * per-block partial sums live in a static device array of 131072 doubles
+ * (1 MiB per GPU, held until the process ends): grids needing more partials
+ * (more than 4 * 131072 tiles of 64 / order elements) give DG_EUNSUPPORTED.
+ * Nothing is allocated and no state is kept between calls except that array:
+ * calls that overlap on one GPU (other streams, other host threads) race on
+ * it, so the caller serialises them.  Errors as for the handle-less calls
+ * (dg_last_error(NULL)). */
+int dg_torque_noalloc(const dg_config *cfg, double t, const double *t_dev, const double *u_dev, double *torque_dev,
+                      void *hip_stream);
+
 /* ---- troubled cells (limiter DG_LIMITER_MODAL_DECAY or DG_LIMITER_LEARNED) ----
  *
  * The limiter is the minmod slope limiter of the Cockburn-Shu RKDG scheme the

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -361,6 +362,34 @@ void release(dg_handle* h) {
     h->eqtr = nullptr;
 }
 
+// Scratch of dg_torque_noalloc: the torque's per-block partial sums, one
+// copy per GPU in a static device array (no allocation at any call).  Host
+// code uses the device address from hipGetSymbolAddress, never the array's
+// name (a host-side stand-in).
+constexpr int kNoAllocPartials = 1 << 17;
+__device__ __align__(256) double scratch[kNoAllocPartials];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's scratch address, looked up once per device
+hipError_t scratch_of_current_device(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -631,6 +660,29 @@ int dg_torque(dg_handle* h, double t, const double* t_dev, const double* u_dev, 
     if (!u_dev || !torque_dev) return fail(h, DG_EINVAL, "u_dev and torque_dev are required");
     DG_HIP(h, dgk::launch_torque(h->n, h->g, t, t_dev, u_dev, h->eq, h->tq_part, h->tq_blocks, torque_dev, h->s),
            "torque");
+    return DG_OK;
+}
+
+int dg_torque_noalloc(const dg_config* cfg, double t, const double* t_dev, const double* u_dev, double* torque_dev,
+                      void* hip_stream) {
+    std::string why;
+    const int rc = validate(cfg, &why);
+    if (rc != DG_OK) return fail(nullptr, rc, why);
+    if (cfg->precision != DG_PRECISION_FP64)
+        return fail(nullptr, DG_EUNSUPPORTED, "dg_torque_noalloc takes full FP64 states (precision DG_PRECISION_FP64)");
+    Geo g;
+    make_geo(cfg, &g);
+    const int nb = dgk::torque_blocks(g);
+    if (nb > kNoAllocPartials)
+        return fail(nullptr, DG_EUNSUPPORTED,
+                    "dg_torque_noalloc: the grid needs " + std::to_string(nb) + " partial sums, the static scratch holds " +
+                        std::to_string(kNoAllocPartials) + " (at most 4 * 131072 tiles of 64 / order elements)");
+    if (!u_dev || !torque_dev) return fail(nullptr, DG_EINVAL, "u_dev and torque_dev are required");
+    double* part = nullptr;
+    hipError_t e = scratch_of_current_device(&part);
+    if (e != hipSuccess) return fail(nullptr, DG_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+    e = dgk::launch_torque(cfg->order, g, t, t_dev, u_dev, nullptr, part, nb, torque_dev, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(nullptr, DG_EHIP, std::string("torque: ") + hipGetErrorString(e));
     return DG_OK;
 }
 

@@ -132,6 +132,7 @@ def lib():
         L.dg_rhs.argtypes = [vp, C.c_double, vp, vp]
         L.dg_rk_step.argtypes = [vp, vp, vp, C.c_double, vp]
         L.dg_torque.argtypes = [vp, C.c_double, vp, vp, vp]
+        L.dg_torque_noalloc.argtypes = [cp, C.c_double, vp, vp, vp, vp]
         L.dg_sync.argtypes = [vp]
         L.dg_free.argtypes = [vp]
         L.dg_profile_begin.argtypes = [vp]
@@ -149,7 +150,7 @@ def lib():
         for name in ("dg_get_nodes", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
                      "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled", "dg_positivity",
                      "dg_mlp_feature_scales", "dg_mlp_features", "dg_mlp_params", "dg_mlp_forward",
-                     "dg_mlp_train_step", "dg_capture"):
+                     "dg_mlp_train_step", "dg_capture", "dg_torque_noalloc"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -158,7 +159,7 @@ def lib():
 EXPORTS = ("dg_get_nodes", "dg_state_size", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
            "dg_last_error", "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled", "dg_positivity",
            "dg_mlp_feature_scales", "dg_mlp_features", "dg_mlp_params", "dg_mlp_forward", "dg_mlp_train_step",
-           "dg_capture")
+           "dg_capture", "dg_torque_noalloc")
 MLP_NPARAM = 3169
 
 
@@ -264,6 +265,15 @@ def dg_rk_step(h: Handle, u, t_dev, dt_fixed: float = 0.0, dt_used=None):
 
 def dg_torque(h: Handle, u, out, t: float = 0.0, t_dev=None):
     _check(lib().dg_torque(h.ptr, float(t), _ptr(t_dev), _ptr(u), _ptr(out)), h.ptr)
+
+
+def dg_torque_noalloc(cfg: Config, u, out, t: float = 0.0, t_dev=None, stream=None):
+    """dg_torque without a handle and without allocating: partial sums in the
+    library's static device scratch (FP64 states; calls on one GPU must not
+    overlap).  stream: a hipStream_t value (default: torch's current stream)."""
+    c = cfg.to_c()
+    s = _stream() if stream is None else C.c_void_p(stream)
+    _check(lib().dg_torque_noalloc(C.byref(c), float(t), _ptr(t_dev), _ptr(u), _ptr(out), s))
 
 
 def dg_profile_begin(h: Handle):

@@ -136,3 +136,21 @@ def test_state_size_limit_is_the_buffer_range():
     assert dg.dg_state_size(ok) * 8 == 600 * 1896 * 1887 <= 2 ** 31 - 1
     with pytest.raises(dg.DGError):
         dg.dg_state_size(ok.replace(ny=1888))
+
+
+def test_noalloc_torque_rejects_what_it_cannot_hold_without_a_device():
+    """dg_torque_noalloc keeps its partial sums in a static array of 131072
+    doubles: a grid needing more is refused before any device call, and so is
+    the deviation form (its states are not full states)."""
+    # order 2: 32 elements per tile, 128 tiles per row: 134400 partial sums
+    cfg = W.disc(nx=4096, order=2).replace(ny=4200)
+    assert dg.dg_state_size(cfg) > 0
+    with pytest.raises(dg.DGError) as ex:
+        dg.dg_torque_noalloc(cfg, None, None, stream=0)
+    assert ex.value.code == dg.DG_EUNSUPPORTED
+    with pytest.raises(dg.DGError) as ex:
+        dg.dg_torque_noalloc(W.disc_mixed(nx=16, order=3), None, None, stream=0)
+    assert ex.value.code == dg.DG_EUNSUPPORTED
+    with pytest.raises(dg.DGError) as ex:
+        dg.dg_torque_noalloc(W.disc(nx=16, order=3), None, None, stream=0)
+    assert ex.value.code == dg.DG_EINVAL
