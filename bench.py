@@ -41,8 +41,14 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--no-limited", action="store_true", help="skip the modal vs learned limiter comparison")
     ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU-share (1024 x 128 strip) run")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 1024^2 order sweep")
     ap.add_argument("--ring-nx", type=int, default=1024)
     ap.add_argument("--ring-steps", type=int, default=200)
+    ap.add_argument("--mixed-nx", type=int, default=1024)
+    ap.add_argument("--mixed-steps", type=int, default=2000)
+    ap.add_argument("--sweep-steps", type=int, default=20)
+    ap.add_argument("--cpu-child", nargs=3, metavar=("NX", "ORDER", "STEPS"), default=None,
+                    help=argparse.SUPPRESS)
     ap.add_argument("--seed", type=int, default=None,
                     help="seeded disc: Sigma0 and 1e-4 density noise from the seed, q = 3e-5")
     ap.add_argument("--sweep", action="store_true",
@@ -110,16 +116,31 @@ def fp64_model(cfg, avg_launch_s):
             "frac": ach / FP64_PEAK_TFLOPS, "note": "FLOP from the count model, not from counters"}
 
 
-def cpu_baseline(cfg, prim):
-    """The oracle as it stands, one full step (CFL dt, three stages, damping)
-    plus the torque, on all host cores."""
-    import numpy as np  # noqa: F401
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(nx, order, steps):
+    """The oracle as it stands on the disc at nx^2 and this order: `steps`
+    full steps (CFL dt, three SSP-RK3 stages, damping) plus the torque after
+    each, plain C FP64 with OpenMP over the elements; DOF-stage updates per
+    second and the seconds taken."""
     import oracle as O
+    from paper_1805_01443_amd import configs as W
     O.build()
+    cfg = W.disc(nx=nx, order=order)
     oc = O.cfg(dataclasses.asdict(cfg))
+    # the oracle's own node coordinates: this leg loads no HIP library
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, "disc", x=x, y=y)
     u0 = O.project(oc, prim)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    steps = 6  # about 10 s on 16 host threads
     t0 = time.perf_counter()
     u, t = u0, 0.0
     for _ in range(steps):
@@ -127,11 +148,35 @@ def cpu_baseline(cfg, prim):
         t += dt
         O.torque(oc, t, u)
     el = time.perf_counter() - t0
-    dofs = cfg.nx * cfg.ny * cfg.order ** 2
-    return {"value": dofs * 3 * steps / el, "unit": "DOF-stage/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} full steps (CFL dt, 3 SSP-RK3 stages, damping) + torque each, of the same "
-                      f"{cfg.nx}x{cfg.ny} order-{cfg.order} disc, plain C FP64, OpenMP over elements "
-                      f"({threads} threads), {el:.1f} s"}
+    return cfg.nx * cfg.ny * order ** 2 * 3 * steps / el, el
+
+
+def cpu_baseline(nx, order):
+    """The oracle on the host cores, before the GPU is touched: all threads on
+    six steps of the benchmark disc (about 10 s on 16 threads), and one thread
+    (a child process with OMP_NUM_THREADS=1) on two steps of the same disc at
+    128^2 (same work per element; the rate is per DOF-stage)."""
+    import subprocess
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    steps = 6
+    v, el = oracle_rate(nx, order, steps)
+    out = {"value": v, "unit": "DOF-stage/s", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} full steps (CFL dt, 3 SSP-RK3 stages, damping) + torque each, of the same "
+                     f"{nx}x{nx} order-{order} disc, plain C FP64, OpenMP over elements ({threads} threads), "
+                     f"{el:.1f} s",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", "128", str(order), "2"],
+                       env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode == 0 and r.stdout.strip():
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        out["one_thread"] = {"value": one["value"], "unit": "DOF-stage/s", "cores": 1,
+                             "sample": f"2 full steps + torque of the same disc at 128x128, order {order}, "
+                                       f"OMP_NUM_THREADS=1, {one['seconds']:.1f} s"}
+        out["threads_speedup"] = v / one["value"]
+    else:
+        out["one_thread"] = {"error": (r.stderr or "")[-400:]}
+    return out
 
 
 def run_disc(cfg, prim, steps, warmup, profile):
@@ -167,10 +212,24 @@ def run_disc(cfg, prim, steps, warmup, profile):
     return res
 
 
+NCAP = 10  # captured steps before the timed ones (limited forms)
+
+
 def run_limited(a):
     """The ring workload (order 4, adiabatic, 1024^2 by default) with the plain
     modal-decay indicator and with the learned indicator, both followed by
-    minmod: step rate of each and the density difference after the timed steps."""
+    minmod and the positivity limiter: step rate of each and the density
+    difference after the timed steps, on two states.
+      smooth: the ring from t = 0.  At 1024^2 the plain sensor flags no element
+              for t < 1 (31 500 steps): this times the indicators' cost alone.
+      jump:   the same ring with density and energy doubled inside r = 1.6, an
+              edge through the middle of elements that both pipelines must
+              limit from the first step.
+    Each run first takes NCAP untimed steps that capture the plain indicator's
+    flags and labels and the network's flags on the run's own last-stage states
+    (the learned run's miss and false-alarm rates against the labels), then the
+    timed steps."""
+    import numpy as np
     import torch
 
     from paper_1805_01443_amd import configs as W
@@ -180,40 +239,68 @@ def run_limited(a):
         params, theta, s0, src = learned.init_params(0), 0.5, learned.default_s0(4), "untrained (He init)"
     else:
         params, theta, s0, src = lp["params"], lp["theta"], lp["s0"], "trained, " + learned.PARAMS_FILE.split(os.sep)[-1]
-    out, rho = {}, {}
-    for name, lim in (("modal", dg.LIMITER_MODAL_DECAY), ("learned", dg.LIMITER_LEARNED)):
-        cfg = learned.ring_config(a.ring_nx, limiter=lim, theta=theta, s0=s0)
-        prim = W.prim_for(cfg, "disc_ring", seed=0)
-        h, u = dg.dg_init(cfg, prim)
-        if lim == dg.LIMITER_LEARNED:
-            dg.dg_mlp_params(h, set_params=params)
-        t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-        for _ in range(a.warmup):
-            dg.dg_rk_step(h, u, t_dev, 0.0, None)
-        dg.dg_sync(h)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(a.ring_steps):
-            dg.dg_rk_step(h, u, t_dev, 0.0, None)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        dg.dg_sync(h)
-        fl = torch.zeros(cfg.n_elem, dtype=torch.uint8, device="cuda")
-        dg.dg_troubled(h, u, apply=False, flags=fl)
-        dofs = cfg.n_elem * cfg.order ** 2
-        out[name] = {"value": dofs * 3 * a.ring_steps / el, "unit": "DOF-stage/s",
-                     "ms_per_step": el * 1e3 / a.ring_steps, "sensor_flagged_at_end": int(fl.sum().item())}
-        rho[name] = dg.to_planes(cfg, u)[0].clone()
-        h.close()
-    out["learned_speedup_vs_modal"] = out["modal"]["ms_per_step"] / out["learned"]["ms_per_step"]
-    out["density_rel_L2_diff"] = float(((rho["learned"] - rho["modal"]) ** 2).sum().sqrt()
-                                       / (rho["modal"] ** 2).sum().sqrt())
-    out["workload"] = f"ring{a.ring_nx}_p3_adiabatic_fp64_seed0"
-    out["steps"] = a.ring_steps
-    out["network"] = src
-    out["theta"] = theta
-    out["s0"] = s0
-    return out
+    res = {"workload": f"ring{a.ring_nx}_p3_adiabatic_fp64_seed0", "network": src, "theta": theta, "s0": s0}
+    for state in ("smooth", "jump"):
+        steps = a.ring_steps if state == "smooth" else max(a.ring_steps // 2, 1)
+        out, rho = {}, {}
+        for name, lim in (("modal", dg.LIMITER_MODAL_DECAY), ("learned", dg.LIMITER_LEARNED)):
+            cfg = learned.ring_config(a.ring_nx, limiter=lim, theta=theta, s0=s0)
+            prim = W.prim_for(cfg, "disc_ring", seed=0)
+            if state == "jump":
+                x, y = dg.dg_get_nodes(cfg)
+                inside = np.sqrt(x ** 2 + y ** 2) < 1.6
+                prim[0] = np.where(inside, 2.0 * prim[0], prim[0])
+                prim[3] = np.where(inside, 2.0 * prim[3], prim[3])
+            h, u = dg.dg_init(cfg, prim)
+            if lim == dg.LIMITER_LEARNED:
+                dg.dg_mlp_params(h, set_params=params)
+            t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+            # the first NCAP steps (untimed): the plain indicator's flags and
+            # labels (flagged and altered by minmod) on each step's last-stage
+            # state before limiting, and with the learned limiter the
+            # network's flags on the same states
+            E = cfg.n_elem
+            fl = torch.zeros(E, dtype=torch.uint8, device="cuda")
+            lab = torch.zeros(E, dtype=torch.uint8, device="cuda")
+            mf = torch.zeros(E, dtype=torch.uint8, device="cuda")
+            conf = {"labels": 0, "flagged": 0, "mlp_flags": 0, "miss": 0, "false_alarm": 0, "elements": 0}
+            for _ in range(NCAP):
+                dg.dg_capture(h, flags=fl, labels=lab, mlp_flags=mf if lim == dg.LIMITER_LEARNED else None)
+                dg.dg_rk_step(h, u, t_dev, 0.0, None)
+                torch.cuda.synchronize()
+                conf["labels"] += int(lab.sum().item())
+                conf["flagged"] += int(fl.sum().item())
+                conf["elements"] += E
+                if lim == dg.LIMITER_LEARNED:
+                    conf["mlp_flags"] += int(mf.sum().item())
+                    conf["miss"] += int(((lab == 1) & (mf == 0)).sum().item())
+                    conf["false_alarm"] += int(((lab == 0) & (mf == 1)).sum().item())
+            dg.dg_sync(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                dg.dg_rk_step(h, u, t_dev, 0.0, None)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            dg.dg_sync(h)
+            dofs = cfg.n_elem * cfg.order ** 2
+            rec = {"value": dofs * 3 * steps / el, "unit": "DOF-stage/s", "ms_per_step": el * 1e3 / steps,
+                   "plain_flagged_per_step": conf["flagged"] / NCAP, "plain_labels_per_step": conf["labels"] / NCAP}
+            if lim == dg.LIMITER_LEARNED:
+                rec["mlp_flagged_per_step"] = conf["mlp_flags"] / NCAP
+                rec["miss_rate"] = conf["miss"] / conf["labels"] if conf["labels"] else None
+                neg = conf["elements"] - conf["labels"]
+                rec["false_alarm_rate"] = conf["false_alarm"] / neg if neg else None
+            rho[name] = dg.to_planes(cfg, u)[0].clone()
+            out[name] = rec
+            h.close()
+        out["learned_speedup_vs_modal"] = out["modal"]["ms_per_step"] / out["learned"]["ms_per_step"]
+        out["density_rel_L2_diff"] = float(((rho["learned"] - rho["modal"]) ** 2).sum().sqrt()
+                                           / (rho["modal"] ** 2).sum().sqrt())
+        out["timed_steps"] = steps
+        out["captured_steps_before_timing"] = NCAP
+        res[state] = out
+    return res
 
 
 def run_shard(a, order):
@@ -247,22 +334,59 @@ def disc_workload(a, order):
     return cfg, W.prim_for(cfg, "disc", seed=a.seed), W.sigma0_of(a.seed)
 
 
-def sweep(a):
-    """FP64 throughput per order at the chosen resolution."""
+def sweep(a, nx, steps, seed):
+    """FP64 throughput per order on the seeded disc at nx^2 (orders 2..5)."""
+    from paper_1805_01443_amd import configs as W
     rows = []
     for order in (2, 3, 4, 5):
-        cfg, prim, _ = disc_workload(a, order)
-        r = run_disc(cfg, prim, a.steps, a.warmup, profile=True)
+        cfg = W.disc_sweep(nx=nx, order=order)
+        r = run_disc(cfg, W.prim_for(cfg, "disc", seed=seed), steps, a.warmup, profile=True)
         state_bytes = cfg.nvar * order ** 2 * cfg.n_elem * 8
         avg = r["stage_ms"] / 1e3 / max(r["launches"], 1)
         ach = state_bytes * 8.0 / 3.0 / avg / 1e9
         rows.append({"order": order, "p": order - 1, "dofs": cfg.n_elem * order ** 2,
-                     "dof_stage_per_s": cfg.n_elem * order ** 2 * 3 * a.steps / r["elapsed"],
-                     "ms_per_step": r["elapsed"] * 1e3 / a.steps, "stage_kernel_us": avg * 1e6,
+                     "dof_stage_per_s": cfg.n_elem * order ** 2 * 3 * steps / r["elapsed"],
+                     "ms_per_step": r["elapsed"] * 1e3 / steps, "stage_kernel_us": avg * 1e6,
                      "hbm_GBps_alg": ach, "hbm_frac": ach / HBM_PEAK_GBPS,
                      "fp64_model": fp64_model(cfg, avg)})
         del r
-    print(json.dumps({"sweep": rows, "nx": a.nx, "steps": a.steps, "seed": a.seed}), flush=True)
+    return {"workload": f"disc{nx}_seed{seed}_orders2to5_fp64", "steps": steps, "rows": rows}
+
+
+def run_mixed(a):
+    """The mixed-precision deviation form against the FP64 path on the seeded
+    1024^2 order-5 disc (q = 3e-5), --mixed-steps steps each with the torque
+    every step: speeds, the torque series' largest difference relative to its
+    largest value, and the relative L2 difference of the final density modes
+    (Parseval: the orthonormal modes' L2 norm is the density's L2 norm over
+    |K|).  The deviation's own error: the final difference relative to the
+    largest deviation of the FP64 state from the equilibrium."""
+    from paper_1805_01443_amd import configs as W
+    from paper_1805_01443_amd import dg
+    cfg = W.disc_sweep(nx=a.mixed_nx, order=5)
+    prim = W.prim_for(cfg, "disc", seed=0)
+    r64 = run_disc(cfg, prim, a.mixed_steps, a.warmup, profile=True)
+    cm = W.disc_mixed(nx=a.mixed_nx, order=5, seed=0)
+    rm = run_disc(cm, prim, a.mixed_steps, a.warmup, profile=True)
+    g64, gm = r64["torques"], rm["torques"]
+    rho64 = dg.to_planes(cfg, r64["full"])[0]
+    rhom = dg.to_planes(cm, rm["full"])[0]
+    dens_l2 = float(((rhom - rho64) ** 2).sum().sqrt() / (rho64 ** 2).sum().sqrt())
+    tq_err = float((gm - g64).abs().max() / g64.abs().max())
+    dofs = W.dofs(cfg)
+    return {"workload": f"disc{a.mixed_nx}_p4_seed0_mixed_vs_fp64", "steps": a.mixed_steps,
+            "fp64": {"value": dofs * 3 * a.mixed_steps / r64["elapsed"], "unit": "DOF-stage/s",
+                     "ms_per_step": r64["elapsed"] * 1e3 / a.mixed_steps,
+                     "stage_kernel_us": r64["stage_ms"] * 1e3 / max(r64["launches"], 1)},
+            "mixed": {"value": dofs * 3 * a.mixed_steps / rm["elapsed"], "unit": "DOF-stage/s",
+                      "ms_per_step": rm["elapsed"] * 1e3 / a.mixed_steps,
+                      "stage_kernel_us": rm["stage_ms"] * 1e3 / max(rm["launches"], 1)},
+            "speedup_vs_fp64": r64["elapsed"] / rm["elapsed"],
+            "torque_series_rel_err_vs_fp64": tq_err, "density_rel_L2_err_vs_fp64": dens_l2,
+            "t_end": rm["t_end"],
+            "note": "FP32 deviation terms linearised about the projected equilibrium (its volume-node "
+                    "values and tabulated edge traces); FP64 L(u_eq), state, stage combination, "
+                    "damping, dt and torque"}
 
 
 def main():
@@ -270,18 +394,26 @@ def main():
     if a.calibrate_copy:
         calibrate_copy()
         return
+    if a.cpu_child:
+        nx, order, steps = (int(v) for v in a.cpu_child)
+        v, el = oracle_rate(nx, order, steps)
+        print(json.dumps({"value": v, "seconds": el}), flush=True)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU only; sharding over several GPUs is a "
                                    "design, not an implemented path", "n_gpus": a.gpus}))
         sys.exit(2)
+    # torch first (its HIP runtime is the one the library then binds to), then
+    # the oracle's timings, before the GPU is initialised
     import torch
 
+    cpu = None if a.no_cpu_baseline else cpu_baseline(a.nx, a.order)
+
     from paper_1805_01443_amd import configs as W
-    from paper_1805_01443_amd import dg
 
     torch.cuda.set_device(0)
     if a.sweep:
-        sweep(a)
+        print(json.dumps(sweep(a, a.nx, a.steps, 0 if a.seed is None else a.seed)), flush=True)
         return
     cfg, prim, sigma0 = disc_workload(a, a.order)
     r64 = run_disc(cfg, prim, a.steps, a.warmup, profile=True)
@@ -319,31 +451,23 @@ def main():
                      "alg_bytes_per_launch": alg_bytes_per_launch},
         "fp64_model": fp64_model(cfg, avg_launch_s),
     }
-    if not a.no_mixed:
-        # the same workload in the mixed-precision deviation form
-        cm = cfg.replace(precision=dg.PRECISION_MIXED, sigma0=sigma0)
-        rm = run_disc(cm, prim, a.steps, a.warmup, profile=True)
-        g64, gm = r64["torques"], rm["torques"]
-        rho64 = dg.to_planes(cfg, r64["full"])[0]
-        rhom = dg.to_planes(cm, rm["full"])[0]
-        dens_l2 = float(((rhom - rho64) ** 2).sum().sqrt() / (rho64 ** 2).sum().sqrt())
-        tq_err = float((gm - g64).abs().max() / g64.abs().max())
-        out["forms"] = {
-            "mixed": {"value": dofs * 3 * a.steps / rm["elapsed"], "unit": "DOF-stage/s",
-                      "speedup_vs_fp64": el / rm["elapsed"],
-                      "stage_kernel_us": rm["stage_ms"] * 1e3 / max(rm["launches"], 1),
-                      "torque_series_rel_err_vs_fp64": tq_err, "density_rel_L2_err_vs_fp64": dens_l2,
-                      "note": "FP32 deviation terms linearised about the projected equilibrium (its volume-node "
-                              "values and tabulated edge traces); FP64 L(u_eq), state, stage combination, "
-                              "damping, dt and torque"}}
     del r64
+    forms = {}
+    if not a.no_sweep:
+        forms["sweep1024"] = sweep(a, 1024, a.sweep_steps, 0)
+    if not a.no_mixed:
+        forms["mixed"] = run_mixed(a)
     if not a.no_shard:
-        out.setdefault("forms", {})["shard"] = run_shard(a, cfg.order)
+        forms["shard"] = run_shard(a, cfg.order)
     if not a.no_limited:
-        out.setdefault("forms", {})["limited"] = run_limited(a)
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, prim)
-        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+        forms["limited"] = run_limited(a)
+    if forms:
+        out["forms"] = forms
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+        out["cpu_baseline"]["gpu_over_cpu"] = value / cpu["value"]
+        if "value" in cpu.get("one_thread", {}):
+            out["cpu_baseline"]["gpu_over_one_thread"] = value / cpu["one_thread"]["value"]
     print(json.dumps(out), flush=True)
 
 

@@ -36,3 +36,14 @@ def test_count_model_is_positive_and_grows_with_order():
     assert all(a < b for a, b in zip(f, f[1:]))
     # the sum-factorised volume part dominates at order 5: 2 (7 n^3 nvar - n^3) FLOP
     assert f[-1] > 2 * (7 * 125 * 3 - 125)
+
+
+def test_one_thread_oracle_child_reports_a_rate():
+    """the single-thread oracle timing runs as a child process (OMP_NUM_THREADS=1)
+    and prints one JSON line with its DOF-stage rate"""
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-child", "8", "3", "1"],
+                       capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stderr[-2000:]
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    assert rec["value"] > 0 and rec["seconds"] > 0
