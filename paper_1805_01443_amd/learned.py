@@ -10,7 +10,10 @@ library's own forward/backward/Adam kernels (``dg_mlp_train_step``).  Then, in
 DAgger iterations, the learned limiter itself runs the training seeds and the
 states it visits (where its misses let oscillations grow) are labelled by the
 plain indicator and added to the data before retraining.  The flag threshold
-is chosen on a validation seed for a miss rate <= 1 %, and on a test seed the
+is chosen on a validation seed for a miss rate <= 1 %.  Besides the ring runs,
+every seed contributes a short run from its jump state (density and pressure
+multiplied inside a seeded radius: a discontinuity the smooth ring does not
+produce at these times), whose first steps are all captured.  On a test seed the
 learned limiter runs the same workload while its flags are compared with the
 plain labels on the same states (miss and false-alarm rates); torque, density,
 residual oscillation and step time are compared with the plain indicator, with
@@ -31,6 +34,7 @@ import numpy as np
 
 from . import configs as W
 from . import dg
+from . import synth
 
 
 def default_s0(order: int) -> float:
@@ -77,15 +81,28 @@ def init_params(seed=0):
     return p
 
 
-def collect(seed, nx, steps, every, cap, torch, s0=None, log=print, positivity=1, params=None, theta=0.5):
+def ring_prim(cfg, seed, jump=None):
+    """Initial data of the ring workload; jump: None, or (r_j, f) to multiply
+    density and pressure by f inside r < r_j."""
+    prim = W.prim_for(cfg, "disc_ring", seed=seed)
+    if jump is None:
+        return prim
+    x, y = dg.dg_get_nodes(cfg)
+    return synth.apply_jump(prim, x, y, *jump)
+
+
+def collect(seed, nx, steps, every, cap, torch, s0=None, log=print, positivity=1, params=None, theta=0.5,
+            jump=False, cap_first=0):
     """Run the plain pipeline (or, with ``params``, the learned limiter with
     that network: the states it visits, labelled by the plain indicator);
     returns (features int16 [N, 64], labels float [N], per-capture positive
-    counts, steps run).  A run whose state turns non-finite stops there and
-    keeps the samples captured before."""
+    counts, steps run).  With ``jump`` the ring starts with the seed's density
+    and pressure jump (synth.ring_jump); the first ``cap_first`` steps are
+    captured, then every ``every``-th.  A run whose state turns non-finite
+    stops there and keeps the samples captured before."""
     lim = dg.LIMITER_MODAL_DECAY if params is None else dg.LIMITER_LEARNED
     cfg = ring_config(nx, limiter=lim, theta=theta, s0=s0, positivity=positivity)
-    prim = W.prim_for(cfg, "disc_ring", seed=seed)
+    prim = ring_prim(cfg, seed, synth.ring_jump(seed) if jump else None)
     h, u = dg.dg_init(cfg, prim)
     if params is not None:
         dg.dg_mlp_params(h, set_params=params)
@@ -98,7 +115,7 @@ def collect(seed, nx, steps, every, cap, torch, s0=None, log=print, positivity=1
     xs, ys, npos = [], [], []
     done = 0
     for k in range(steps):
-        cap_now = (k + 1) % every == 0
+        cap_now = k < cap_first or (k + 1) % every == 0
         if cap_now:
             dg.dg_capture(h, feat=feat, flags=lab)
         dg.dg_rk_step(h, u, t_dev, 0.0, None)
@@ -123,7 +140,8 @@ def collect(seed, nx, steps, every, cap, torch, s0=None, log=print, positivity=1
         dg.dg_sync(h)
     except dg.DGError:
         pass
-    log(f"[collect] seed {seed} ({'learned' if params is not None else 'plain'}): {done} steps, "
+    log(f"[collect] seed {seed}{' jump' if jump else ''} ({'learned' if params is not None else 'plain'}): "
+        f"{done} steps, "
         f"t_end {t_dev.item():.4f}, positives per capture "
         f"{npos[:3]}...{npos[-3:]} (total {sum(npos)})")
     h.close()
@@ -351,6 +369,43 @@ def evaluate_run(seed, nx, steps, every, params, theta, torch, s0=None, log=prin
     return out
 
 
+def evaluate_jump(seed, nx, steps, params, theta, torch, s0=None, log=print, positivity=1):
+    """The seed's jump state (synth.ring_jump): the network's flags against
+    the plain labels on every step's last-stage state, on the plain run's
+    states (open loop) and on the learned limiter's own (closed loop)."""
+    out = {"jump": list(synth.ring_jump(seed)), "steps": steps}
+    for name, lim in (("open_loop", dg.LIMITER_MODAL_DECAY), ("closed_loop", dg.LIMITER_LEARNED)):
+        cfg = ring_config(nx, limiter=lim, theta=theta, s0=s0, positivity=positivity)
+        prim = ring_prim(cfg, seed, synth.ring_jump(seed))
+        h, u = dg.dg_init(cfg, prim)
+        dg.dg_mlp_params(h, set_params=params)
+        E = cfg.n_elem
+        feat = torch.zeros((E, 64), dtype=torch.int16, device="cuda")
+        lab = torch.zeros(E, dtype=torch.uint8, device="cuda")
+        z = torch.zeros(E, dtype=torch.float32, device="cuda")
+        thf = np.float32(theta)
+        zthr = float(np.log(thf / (np.float32(1.0) - thf)))
+        t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        tp = fn = fp = tn = 0
+        for _ in range(steps):
+            dg.dg_capture(h, feat=feat, flags=lab)
+            dg.dg_rk_step(h, u, t_dev, 0.0, None)
+            dg.dg_mlp_forward(h, feat, E, z)
+            y = lab.bool()
+            m = z > zthr
+            tp += int((y & m).sum())
+            fn += int((y & ~m).sum())
+            fp += int((~y & m).sum())
+            tn += int((~y & ~m).sum())
+        dg.dg_sync(h)
+        h.close()
+        out[name] = {"miss_rate": fn / max(tp + fn, 1), "false_alarm_rate": fp / max(fp + tn, 1),
+                     "label_positives": tp + fn, "mlp_flags": tp + fp}
+        log(f"[eval jump] {name}: miss {out[name]['miss_rate']:.4f}, false alarm {out[name]['false_alarm_rate']:.5f}, "
+            f"{tp + fn} positives over {steps} steps")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--nx", type=int, default=1024)
@@ -369,6 +424,8 @@ def main(argv=None):
     ap.add_argument("--no-positivity", action="store_true", help="without the positivity-preserving limiter")
     ap.add_argument("--dagger", type=int, default=2,
                     help="iterations of data from the learned limiter's own runs, labelled by the plain indicator")
+    ap.add_argument("--jump-steps", type=int, default=0,
+                    help="steps of a run from each seed's jump state (0: none), its first 20 captured")
     a = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
@@ -379,11 +436,23 @@ def main(argv=None):
     t_start = time.time()
     pos = 0 if a.no_positivity else 1
     Xs, Ys = [], []
+
+    def runs(seed, params=None, theta=0.5):
+        """the seed's ring run and, with --jump-steps, its jump run"""
+        X, Y, _, _ = collect(seed, a.nx, a.steps, a.every, a.cap, torch, a.s0, log, pos, params=params, theta=theta)
+        xs, ys = [X], [Y]
+        if a.jump_steps > 0:
+            X, Y, _, _ = collect(seed, a.nx, a.jump_steps, a.every, a.cap, torch, a.s0, log, pos, params=params,
+                                 theta=theta, jump=True, cap_first=min(20, a.jump_steps))
+            xs.append(X)
+            ys.append(Y)
+        return torch.cat(xs), torch.cat(ys)
+
     for s in a.train_seeds:
-        X, Y, _, _ = collect(s, a.nx, a.steps, a.every, a.cap, torch, a.s0, log, pos)
+        X, Y = runs(s)
         Xs.append(X)
         Ys.append(Y)
-    Xv, Yv, _, _ = collect(a.val_seed, a.nx, a.steps, a.every, a.cap, torch, a.s0, log, pos)
+    Xv, Yv = runs(a.val_seed)
     Xvs, Yvs = [Xv], [Yv]
     # a handle is needed to own the network; any configuration with the limiter works
     cfg = ring_config(64)
@@ -399,12 +468,10 @@ def main(argv=None):
     for rnd in range(1, a.dagger + 1):
         params = dg.dg_mlp_params(h, get=True)
         for s in a.train_seeds:
-            X, Y, _, _ = collect(s, a.nx, a.steps, a.every, a.cap, torch, a.s0, log, pos, params=params,
-                                 theta=theta)
+            X, Y = runs(s, params, theta)
             Xs.append(X)
             Ys.append(Y)
-        Xv, Yv, _, _ = collect(a.val_seed, a.nx, a.steps, a.every, a.cap, torch, a.s0, log, pos, params=params,
-                               theta=theta)
+        Xv, Yv = runs(a.val_seed, params, theta)
         Xvs.append(Xv)
         Yvs.append(Yv)
         X, Y = augment_positives(torch.cat(Xs), torch.cat(Ys), torch)
@@ -426,7 +493,9 @@ def main(argv=None):
     h.close()
     s0 = default_s0(4) if a.s0 is None else a.s0
     ev = evaluate_run(a.test_seed, a.nx, a.steps, a.every, params, theta, torch, s0, log, pos)
-    res = {"nx": a.nx, "order": 4, "steps": a.steps, "s0": s0, "positivity": pos, "every": a.every,
+    if a.jump_steps > 0:
+        ev["jump"] = evaluate_jump(a.test_seed, a.nx, min(20, a.jump_steps), params, theta, torch, s0, log, pos)
+    res = {"nx": a.nx, "jump_steps": a.jump_steps, "order": 4, "steps": a.steps, "s0": s0, "positivity": pos, "every": a.every,
            "dagger_iterations": a.dagger, "train_seeds": a.train_seeds, "val_samples": int(Xv.shape[0]),
            "val_positives": int(Yv.sum().item()),
            "val_seed": a.val_seed, "test_seed": a.test_seed, "train_samples": int(X.shape[0]),
@@ -439,8 +508,8 @@ def main(argv=None):
         json.dump(res, f, indent=1)
     if a.params_out:
         save_params(a.params_out, params, theta, s0,
-                    {k: res[k] for k in ("nx", "steps", "positivity", "every", "train_seeds", "val_seed", "test_seed",
-                                         "train_samples", "train_positives", "epochs", "val_miss")})
+                    {k: res[k] for k in ("nx", "steps", "jump_steps", "positivity", "every", "train_seeds", "val_seed",
+                                         "test_seed", "train_samples", "train_positives", "epochs", "val_miss")})
 
 
 if __name__ == "__main__":

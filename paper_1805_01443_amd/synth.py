@@ -20,6 +20,9 @@ Set-ups:
   Keplerian outside, the reading of its Omega^2(r) definition).
 * ``disc_ring``       the adiabatic disc (gamma = 1.4, p = c_s^2 Sigma) with an
   axisymmetric Gaussian over-pressure ring p *= 1 + 4 exp(-(r-r_ring)^2/(2 s^2)).
+* ``apply_jump``      that state with density and pressure multiplied by a seeded
+  factor inside a seeded radius (``ring_jump``): a discontinuity through the
+  middle of elements, for the troubled-cell indicators.
 
 Random numbers come from SplitMix64 (Steele, Lea & Flood 2014): the 64-bit
 state is ``seed * 0x9E3779B97F4A7C15 + (index + 1) * 0x9E3779B97F4A7C15`` and one
@@ -181,6 +184,25 @@ def double_rarefaction(x, y, speed=2.0, rho=1.0, p=0.4, split=0.5, band=0.02):
 def ring_radius(seed):
     """r_ring ~ U[1.4, 1.9] from the seed (index 2**62 + 1 is reserved for it)."""
     return 1.4 + 0.5 * float(uniform01(seed, (np.uint64(1) << np.uint64(62)) + np.uint64(1)))
+
+
+def ring_jump(seed):
+    """A density and pressure jump for the ring workload: factor f ~ U[1.5, 3]
+    inside r < r_j, r_j ~ U[1.2, 2.0] (indices 2**62 + 2 and + 3 of the seed)."""
+    base = np.uint64(1) << np.uint64(62)
+    r_j = 1.2 + 0.8 * float(uniform01(seed, base + np.uint64(2)))
+    f = 1.5 + 1.5 * float(uniform01(seed, base + np.uint64(3)))
+    return r_j, f
+
+
+def apply_jump(prim, x, y, r_j, f):
+    """prim [var][E][n^2] of an adiabatic state (rho, vx, vy, p) with density
+    and pressure multiplied by f at the nodes inside r < r_j (velocity kept)."""
+    inside = np.sqrt(np.asarray(x) ** 2 + np.asarray(y) ** 2) < r_j
+    out = prim.copy()
+    out[0] = np.where(inside, f * prim[0], prim[0])
+    out[3] = np.where(inside, f * prim[3], prim[3])
+    return out
 
 
 def pack_prim(fields, n_elem, n_nodes):
