@@ -146,15 +146,11 @@ __device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const do
 }
 
 // ------------------------------------------------------------------ stage kernel, N lanes per element
-// LDS entries per element slot: at least `need`, rounded up to N modulo m
-// (16 for doubles, 32 for floats) so that lane (s, k) reading entry k of slot
-// s (s * SLOT + k) hits consecutive banks across a wavefront, and
-// element-uniform reads of the slots of one lane group fall in distinct banks.
-constexpr int lds_slot(int need, int n, int m = 16) {
-    int s = need;
-    while (s % m != n % m) ++s;
-    return s;
-}
+// Slot size in LDS for the N-lanes kernels: the lanes of one index k run over
+// the element slots (lane k * EW + s), and an odd slot stride puts the slots
+// read or written by 16 consecutive lanes on 16 different bank pairs (banks for
+// floats).
+constexpr int lds_slot_odd(int need) { return need | 1; }
 
 // Lane-dependent entry t[k] of a compile-time table (k < N): a select chain on
 // immediates.
@@ -167,8 +163,8 @@ __device__ __forceinline__ double pick(const double (&t)[kMaxOrder], int k) {
 }
 
 // out = a0 u^n + a1 u + a2 L(u, t), with the N lanes of an element sharing
-// its tensor-product contractions.  Lane (s, k): element slot s = lane / N of
-// the wave (EW = 64 / N consecutive elements of one row), index k = lane % N.
+// its tensor-product contractions.  Lane (s, k) = lane k * EW + s: element
+// slot s of the wave (EW = 64 / N consecutive elements of one row), index k.
 // Transposes between the lanes of an element go through LDS, single values
 // per lane through lane permutes:
 //   phase 1, k = mode row a: own row u[v][a][.] -> C[v][a][r] = sum_b u[v][a][b]
@@ -201,27 +197,31 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     constexpr BasisTab B = make_basis(N);
     // C, later X then Y; south/north fluxes; with the positivity scaling
     // fused, its rows and minima after that
-    constexpr int SLOT = lds_slot(PP && pp_slot<N, NV>() > NV * NN + 2 * NV * N ? pp_slot<N, NV>()
-                                                                               : NV * NN + 2 * NV * N,
-                                  N);
+    constexpr int SLOT = lds_slot_odd(PP && pp_slot<N, NV>() > NV * NN + 2 * NV * N ? pp_slot<N, NV>()
+                                                                                   : NV * NN + 2 * NV * N);
     __shared__ double lds[EW * SLOT];
 
+    // Lane k * EW + s holds index k of element slot s: the lanes of one k
+    // address consecutive doubles of the tile (a row of the EW elements is one
+    // contiguous run), so every row load and store is contiguous in lane
+    // order.  Lanes beyond N * EW shadow slot 0's element (same i, j and k):
+    // they compute and store exactly the values of lane (0, k) and share slot 0.
     const int lane = threadIdx.x;
-    const int sl = lane / N, k = lane - sl * N;
-    // Lanes beyond EW * N shadow slot 0's element (same i, j and k), so they
-    // compute and store exactly the values of lanes (0, k): they share slot 0.
-    const bool own = EW * N == 64 || sl < EW;
+    const bool own = lane < N * EW;
+    const int k = own ? lane / EW : lane - N * EW;
+    const int sl = own ? lane - k * EW : EW;
     const int tile = remap_tile(blockIdx.x, tiles_total);
     const int j = tile / tiles_x;
     const int i0 = (tile - j * tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
     const int i = active ? i0 + sl : i0;  // idle lanes shadow a valid element and store nothing
-    double* S = lds + (own ? sl : 0) * SLOT;
-    const int l0 = (own ? sl : 0) * N;  // lane of index 0 of the element
+    const int e0 = own ? sl : 0;          // the element's lanes are e0 + a * EW
+    double* S = lds + e0 * SLOT;
+    const int me = e0 + k * EW;           // this lane, or the slot-0 lane an idle lane shadows
     // The x neighbours inside the wave hand over their x collapses by lane
     // permute; only the first slot (west) and the last slot or the end of the
     // row (east) read the neighbour's column from memory.
-    const bool gw = l0 == 0, ge = l0 == (EW - 1) * N || i + 1 >= g.nx;
+    const bool gw = e0 == 0, ge = e0 == EW - 1 || i + 1 >= g.nx;
 
     const double a0 = scp->a0, a1 = scp->a1, a2 = scp->a2, xp = scp->xp, yp = scp->yp;
     const rsrc_t ru = make_rsrc(u), ru0 = make_rsrc(u0), rout = make_rsrc(out), run = make_rsrc(un);
@@ -318,8 +318,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         // ce +- co: east / west side of column Xo, ne +- no: of column Xn.
         // A neighbour in the wave hands over the side of its own column that
         // faces this element.
-        const double from_w = __shfl(ce + co, lane >= N ? lane - N : lane);
-        const double from_e = __shfl(ce - co, lane + N < 64 ? lane + N : lane);
+        const double from_w = __shfl(ce + co, me >= 1 ? me - 1 : me);
+        const double from_e = __shfl(ce - co, me + 1 < 64 ? me + 1 : me);
         Tl[v] = gw ? ne + no : from_w;
         Tr[v] = ge ? (gwe ? ce - co : ne - no) : from_e;
         // box edges: the element's own initial row/column (or the ghost) on the
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
         for (int a = 0; a < N; ++a) Cc[v][a] = S[(v * N + a) * N + k];
     // edge traces at point k and their fluxes (outward normals); a collapse of
-    // row a is held by lane l0 + a
+    // row a is held by lane e0 + a * EW
     double* H = S + NV * NN;  // south / north fluxes [edge][v][point]
     double X[NV][N], Y[NV][N];
     {
@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 si += B.pm[a] * Cc[v][a];
-                so += phk[a] * __shfl(Tl[v], l0 + a);
+                so += phk[a] * __shfl(Tl[v], e0 + a * EW);
             }
             Ui[v] = si;
             Uo[v] = so;
@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 si += B.pp[a] * Cc[v][a];
-                so += phk[a] * __shfl(Tr[v], l0 + a);
+                so += phk[a] * __shfl(Tr[v], e0 + a * EW);
             }
             Ui[v] = si;
             Uo[v] = so;
@@ -415,8 +415,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             double si = 0.0, so = 0.0;
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                si += phk[a] * __shfl(Tm[v], l0 + a);
-                so += phk[a] * __shfl(Tb[v], l0 + a);
+                si += phk[a] * __shfl(Tm[v], e0 + a * EW);
+                so += phk[a] * __shfl(Tb[v], e0 + a * EW);
             }
             Ui[v] = si;
             Uo[v] = so;
@@ -429,8 +429,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             double si = 0.0, so = 0.0;
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                si += phk[a] * __shfl(Tp[v], l0 + a);
-                so += phk[a] * __shfl(Tt[v], l0 + a);
+                si += phk[a] * __shfl(Tp[v], e0 + a * EW);
+                so += phk[a] * __shfl(Tt[v], e0 + a * EW);
             }
             Ui[v] = si;
             Uo[v] = so;
@@ -750,13 +750,15 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     constexpr BasisTab B = make_basis(N);
     constexpr int P1 = NV * NN + 6 * NV * N;
     constexpr int P2 = 2 * NV * NN + 2 * NV * N;
-    constexpr int SLOT = lds_slot(P1 > P2 ? P1 : P2, N, 32);
+    constexpr int SLOT = lds_slot_odd(P1 > P2 ? P1 : P2);
     __shared__ float lds[EW * SLOT];
 
     const int lane = threadIdx.x;
-    const int sl = lane / N, k = lane - sl * N;
-    // lanes beyond EW * N shadow slot 0's element and share its slot
-    const bool own = EW * N == 64 || sl < EW;
+    // lane k * EW + s: index k of element slot s (rows contiguous in lane
+    // order); lanes beyond N * EW shadow slot 0's element
+    const bool own = lane < N * EW;
+    const int k = own ? lane / EW : lane - N * EW;
+    const int sl = own ? lane - k * EW : EW;
     const int tile = remap_tile(blockIdx.x, tiles_total);
     const int j = tile / tiles_x;
     const int i0 = (tile - j * tiles_x) * EW;
@@ -1339,12 +1341,15 @@ __global__ void __launch_bounds__(64) k_damp_prep(const Geo g, const double* __r
     constexpr BasisTab B = make_basis(N);
     constexpr int NV = NVar<CL>::value;
     constexpr int EW = 64 / N;
-    constexpr int SLOT = lds_slot(NV * N * N, N);
+    constexpr int SLOT = lds_slot_odd(NV * N * N);
     __shared__ double lds[EW * SLOT];
     constexpr unsigned RS = N * EW * 8;
     const int lane = threadIdx.x;
-    const int sl = lane / N, k = lane - sl * N;
-    const bool own = EW * N == 64 || sl < EW;
+    // lane k * EW + s: index k of element slot s (rows contiguous in lane
+    // order); lanes beyond N * EW shadow slot 0's element
+    const bool own = lane < N * EW;
+    const int k = own ? lane / EW : lane - N * EW;
+    const int sl = own ? lane - k * EW : EW;
     const int tile = list[blockIdx.x];
     const int j = tile / g.tiles_x;
     const int i0 = (tile - j * g.tiles_x) * EW;
@@ -1413,18 +1418,20 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
-    constexpr int SLOT = lds_slot(NV * NN, N);
+    constexpr int SLOT = lds_slot_odd(NV * NN);
     __shared__ double lds[EW * SLOT];
     constexpr unsigned RS = N * EW * 8;  // byte stride of (v * N + b) in a row
     const int lane = threadIdx.x;
-    const int sl = lane / N, k = lane - sl * N;
+    // lane k * EW + s: index k of element slot s (rows contiguous in lane
+    // order); lanes beyond N * EW shadow slot 0's element
+    const bool own = lane < N * EW;
+    const int k = own ? lane / EW : lane - N * EW;
+    const int sl = own ? lane - k * EW : EW;
     const int tile = list[blockIdx.x];
     const int j = tile / g.tiles_x;
     const int i0 = (tile - j * g.tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
     const int i = active ? i0 + sl : i0;  // idle lanes shadow a valid element and store nothing
-    // lanes beyond EW * N shadow slot 0's element (same i, j, k) and share its slot
-    const bool own = EW * N == 64 || sl < EW;
     double* S = lds + (own ? sl : 0) * SLOT;
     const double dt = scp->dt;
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
@@ -1567,19 +1574,23 @@ __global__ void __launch_bounds__(64 * kTorqueWaves) k_torque(const Geo g, doubl
                                                               double* __restrict__ partials) {
     constexpr BasisTab T = make_basis(N);
     constexpr int EW = 64 / N;
-    __shared__ double lds[kTorqueWaves][EW * N * N];
+    constexpr int TS = (N * N) | 1;  // slot stride: odd, the slots of one k on distinct banks
+    __shared__ double lds[kTorqueWaves][EW * TS];
     __shared__ double pxy[2];
     __shared__ double red[kTorqueWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int sl = lane / N, k = lane - sl * N;
-    const bool own = EW * N == 64 || sl < EW;  // idle lanes shadow slot 0 and add nothing
+    // lane k * EW + s: index k of element slot s (rows contiguous in lane
+    // order); lanes beyond N * EW shadow slot 0's element and add nothing
+    const bool own = lane < N * EW;
+    const int k = own ? lane / EW : lane - N * EW;
+    const int sl = own ? lane - k * EW : EW;
     const int tile = blockIdx.x * kTorqueWaves + wv;
     const bool live = tile < g.tiles_x * g.ny;  // the last block may hold fewer tiles
     const int j = live ? tile / g.tiles_x : 0;
     const int i0 = live ? (tile - j * g.tiles_x) * EW : 0;
     const bool active = live && sl < EW && i0 + sl < g.nx;
     const int i = active ? i0 + sl : i0;
-    double* S = lds[wv] + (own ? sl : 0) * (N * N);
+    double* S = lds[wv] + (own ? sl : 0) * TS;
     if (threadIdx.x == 0) {
         const double tt = t_dev ? *t_dev : t;
         planet_at(g, tt, pxy[0], pxy[1]);

@@ -36,19 +36,22 @@ __device__ __forceinline__ double nb_mean(const Geo& g, const double* __restrict
 }
 
 // ------------------------------------------------------------------ positivity
-// Positivity scaling (Sec. 2.4) with N lanes per element (lane (s, k), EW =
-// 64 / N elements per wavefront, one wavefront per block): lane k loads mode
+// Positivity scaling (Sec. 2.4) with N lanes per element (lane (s, k) = lane
+// k * EW + s, EW = 64 / N elements per wavefront, one wavefront per block): lane k loads mode
 // row k of every variable; the factors come from pp_factors (dg_pp.h); each
 // lane of a changed element scales and stores its row.
 template <int N, int NV>
 __global__ void __launch_bounds__(64) k_pp_c(const Geo g, double* u, double e0, unsigned char* changed_out,
                                              double* theta_out) {
     constexpr int EW = 64 / N;
-    constexpr int SLOT = pp_slot<N, NV>();
+    constexpr int SLOT = pp_slot<N, NV>() | 1;  // odd: the slots of one k on distinct banks
     __shared__ double lds[EW * SLOT];
     const int lane = threadIdx.x;
-    const int sl = lane / N, k = lane - sl * N;
-    const bool own = EW * N == 64 || sl < EW;  // idle lanes shadow slot 0's element
+    // lane k * EW + s: index k of element slot s (rows contiguous in lane
+    // order); lanes beyond N * EW shadow slot 0's element
+    const bool own = lane < N * EW;
+    const int k = own ? lane / EW : lane - N * EW;
+    const int sl = own ? lane - k * EW : EW;
     const int tile = blockIdx.x;
     const int j = tile / g.tiles_x;
     const int i0 = (tile - j * g.tiles_x) * EW;
