@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     const unsigned vb = (tiled_base<N, NV>(g, i, jb) + k * EW) * 8u, vt = (tiled_base<N, NV>(g, i, jt) + k * EW) * 8u;
     const unsigned vl = (tiled_base<N, NV>(g, il, j) + k * N * EW) * 8u;
     const unsigned vr = (tiled_base<N, NV>(g, ir, j) + k * N * EW) * 8u;
-    double Ua[NV][N], Xb[NV][N], Xt[NV][N], Xo[NV][N], Xn[NV][N];
+    double Ua[NV][N], Xb[NV][N], Xt[NV][N], Xn[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -263,24 +263,26 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             Xb[v][m] = ld64(ru, vb, srow);
             Xt[v][m] = ld64(ru, vt, srow);
         }
-    // x columns: Xo the own column k (its x collapses go to the x neighbours
-    // in the wave), Xn the neighbour's column k where that neighbour is
-    // outside the wave (west for the first slot, east for the last slot or
-    // the row end); a lane with both neighbours outside (a row ending after
-    // the first slot) takes the east one as Xo.  Lanes without such a
-    // neighbour read their own column twice (cached lines, values unused).
-    // No branch: these loads stay in flight with the others.
+    // x neighbours outside the wave (west of the first slot, east of the last
+    // slot or of the row end): their column k, loaded by those lanes only (a
+    // lane with both neighbours outside, a row ending at the first slot, reads
+    // the east one further below).  The neighbours inside the wave hand over
+    // their edge traces in phase 2.
     const bool gwe = gw && ge;
-    const unsigned vo = gwe ? vr : vcol, vn = gw ? vl : (ge ? vr : vcol);
+    if (gw || ge) {
+        const unsigned vn = gw ? vl : vr;
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int m = 0; m < N; ++m) {
-            const unsigned scol = (unsigned)(v * NN + m) * CS;
-            Xo[v][m] = ld64(ru, vo, scol);
-            Xn[v][m] = ld64(ru, vn, scol);
-        }
-    // row k's collapses: own south / north, exterior south / north / west / east
+            for (int m = 0; m < N; ++m) Xn[v][m] = ld64(ru, vn, (unsigned)(v * NN + m) * CS);
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < N; ++m) Xn[v][m] = 0.0;
+    }
+    // row k's collapses: own south / north, exterior south / north, and (on
+    // the boundary lanes) the x collapses of the neighbour's column
     double Tm[NV], Tp[NV], Tb[NV], Tt[NV], Tl[NV], Tr[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -293,21 +295,18 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         }
         // the exterior collapses take the neighbour's far side.  phi_m(-1) =
         // (-1)^m phi_m(1): even and odd partial sums give either side.
-        double ue = 0.0, uo = 0.0, be = 0.0, bo = 0.0, te = 0.0, to = 0.0, ce = 0.0, co = 0.0, ne = 0.0,
-               no = 0.0;
+        double ue = 0.0, uo = 0.0, be = 0.0, bo = 0.0, te = 0.0, to = 0.0, ne = 0.0, no = 0.0;
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             if (m % 2 == 0) {
                 ue += B.pp[m] * Ua[v][m];
                 be += B.pp[m] * Xb[v][m];
                 te += B.pp[m] * Xt[v][m];
-                ce += B.pp[m] * Xo[v][m];
                 ne += B.pp[m] * Xn[v][m];
             } else {
                 uo += B.pp[m] * Ua[v][m];
                 bo += B.pp[m] * Xb[v][m];
                 to += B.pp[m] * Xt[v][m];
-                co += B.pp[m] * Xo[v][m];
                 no += B.pp[m] * Xn[v][m];
             }
         }
@@ -315,13 +314,26 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         Tp[v] = ue + uo;
         Tb[v] = be + bo;
         Tt[v] = te - to;
-        // ce +- co: east / west side of column Xo, ne +- no: of column Xn.
-        // A neighbour in the wave hands over the side of its own column that
-        // faces this element.
-        const double from_w = __shfl(ce + co, me >= 1 ? me - 1 : me);
-        const double from_e = __shfl(ce - co, me + 1 < 64 ? me + 1 : me);
-        Tl[v] = gw ? ne + no : from_w;
-        Tr[v] = ge ? (gwe ? ce - co : ne - no) : from_e;
+        // ne +- no: the east / west side of the loaded neighbour column
+        Tl[v] = ne + no;
+        Tr[v] = ne - no;
+    }
+    if (__any(gwe)) {  // the east neighbour's column of a lane that also reads the west one
+        if (gwe) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double e = 0.0, o = 0.0;
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const double w = B.pp[m] * ld64(ru, vr, (unsigned)(v * NN + m) * CS);
+                    if (m % 2 == 0) e += w; else o += w;
+                }
+                Tr[v] = e - o;
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
         // box edges: the element's own initial row/column (or the ghost) on the
         // near side
         if (wfy) {
@@ -372,31 +384,29 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     double X[NV][N], Y[NV][N];
     {
         double Ui[NV], Uo[NV], hw[NV], he[NV], hs[NV];
-        // west / east: own traces from C, exterior from the x collapses
+        // west / east: own traces from C; the exterior is the x neighbour's own
+        // trace at eta_k (lane permute) inside the wave, and the contraction of
+        // the loaded column's collapses at the first and last slot
+        double Ei[NV], Wx[NV], Ex[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double si = 0.0, so = 0.0;
+            double w = 0.0, e = 0.0, tl = 0.0, tr = 0.0;
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                si += B.pm[a] * Cc[v][a];
-                so += phk[a] * __shfl(Tl[v], e0 + a * EW);
+                w += B.pm[a] * Cc[v][a];
+                e += B.pp[a] * Cc[v][a];
+                tl += phk[a] * __shfl(Tl[v], e0 + a * EW);
+                tr += phk[a] * __shfl(Tr[v], e0 + a * EW);
             }
-            Ui[v] = si;
-            Uo[v] = so;
+            const double from_w = __shfl(e, me >= 1 ? me - 1 : me);
+            const double from_e = __shfl(w, me + 1 < 64 ? me + 1 : me);
+            Ui[v] = w;
+            Ei[v] = e;
+            Wx[v] = gw ? tl : from_w;
+            Ex[v] = ge ? tr : from_e;
         }
-        rusanov<CL, 0, -1>(g, Ui, Uo, xc - 0.5 * g.dx, yk, hw);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double si = 0.0, so = 0.0;
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                si += B.pp[a] * Cc[v][a];
-                so += phk[a] * __shfl(Tr[v], e0 + a * EW);
-            }
-            Ui[v] = si;
-            Uo[v] = so;
-        }
-        rusanov<CL, 0, 1>(g, Ui, Uo, xc + 0.5 * g.dx, yk, he);
+        rusanov<CL, 0, -1>(g, Ui, Wx, xc - 0.5 * g.dx, yk, hw);
+        rusanov<CL, 0, 1>(g, Ei, Ex, xc + 0.5 * g.dx, yk, he);
         // west/east lifts of row r enter R[a][b] with the same weight
         // w_r phi_b(eta_r) as X[r][a]: X[r][a] = -(1/dx)(phi_a(-1) h_W + phi_a(1) h_E)
 #pragma unroll
