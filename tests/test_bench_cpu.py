@@ -25,7 +25,13 @@ def test_traffic_record_is_tied_to_the_kernel_sources():
     with open(os.path.join(ROOT, "profiles", "k_stage_traffic.json")) as f:
         rec = json.load(f)["disc512_p4_fp64"]
     assert rec["hbm_bytes_per_launch"] > 0
-    assert 1.9 < rec["fetch_factor"] < 2.1 and 0.9 < rec["write_factor"] < 1.1
+    # FETCH_SIZE prices 128-byte read requests as 64 bytes, and the request
+    # counters see 5/6 of a plain copy's reads: the copy-calibrated factor is
+    # about 2.4 for reads and 1 for writes.  The read bytes from FETCH_SIZE and
+    # from the request-size counters, each calibrated on the copy, must agree.
+    assert 1.0 < rec["fetch_factor"] < 3.0 and 0.9 < rec["write_factor"] < 1.1
+    assert abs(rec["direct_read_bytes_per_launch"] / rec["read_bytes_per_launch"] - 1) < 0.01
+    assert rec["hbm_bytes_per_launch"] == rec["read_bytes_per_launch"] + rec["written_bytes_per_launch"]
     cur = bench.kernel_source_hash()
     got = bench.measured_traffic("disc512_p4_fp64")
     assert got == (rec["hbm_bytes_per_launch"] if rec["kernel_source_sha256_16"] == cur else None)
