@@ -389,6 +389,11 @@ def run_mixed(a):
                     "damping, dt and torque"}
 
 
+def progress(msg):
+    """One line per finished leg on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     if a.calibrate_copy:
@@ -408,6 +413,8 @@ def main():
     import torch
 
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.nx, a.order)
+    if cpu is not None:
+        progress("oracle baseline done")
 
     from paper_1805_01443_amd import configs as W
 
@@ -417,6 +424,7 @@ def main():
         return
     cfg, prim, sigma0 = disc_workload(a, a.order)
     r64 = run_disc(cfg, prim, a.steps, a.warmup, profile=True)
+    progress(f"timed steps done: {cfg.nx}^2 order {cfg.order}")
     el = r64["elapsed"]
     dofs = W.dofs(cfg)
     value = dofs * 3 * a.steps / el
@@ -455,12 +463,16 @@ def main():
     forms = {}
     if not a.no_sweep:
         forms["sweep1024"] = sweep(a, 1024, a.sweep_steps, 0)
+        progress("order sweep done")
     if not a.no_mixed:
         forms["mixed"] = run_mixed(a)
+        progress("mixed form done")
     if not a.no_shard:
         forms["shard"] = run_shard(a, cfg.order)
+        progress("strip done")
     if not a.no_limited:
         forms["limited"] = run_limited(a)
+        progress("limited forms done")
     if forms:
         out["forms"] = forms
     if cpu is not None:
