@@ -153,15 +153,28 @@ int dg_rk_step(dg_handle *h, double *u_dev, double *t_dev, double dt_fixed, doub
  * give identical bits. */
 int dg_torque(dg_handle *h, double t, const double *t_dev, const double *u_dev, double *torque_dev);
 
+/* The torque of eq. (5) of the state entering the step (u^n at t^n, as
+ * dg_torque(h, 0, t_dev, u_dev, torque_dev) before the step gives it), then one
+ * step of dg_rk_step (Algorithm 1): the same torque bits and the same state.
+ * Sec. 5.2 records the torque every step; here the first stage kernel forms it
+ * from the node densities and planet offsets it evaluates anyway (one partial
+ * per tile, summed in the same fixed order as dg_torque), which saves the
+ * torque kernel's read of the density.  The deviation form, and the positivity
+ * limiter without a troubled-cell limiter (its scaling fused into the stage
+ * kernels), run the two calls one after the other.  After the last step, dg_torque gives the torque of the
+ * final state.  torque_dev: device double.  Errors as for dg_rk_step. */
+int dg_rk_step_torque(dg_handle *h, double *u_dev, double *t_dev, double dt_fixed, double *dt_used_dev,
+                      double *torque_dev);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): the torque of
  * dg_torque, same kernels, same bits, without a handle.  cfg describes the
  * state (FP64 form only: DG_PRECISION_MIXED gives DG_EUNSUPPORTED); u_dev,
  * t_dev (may be NULL: then t) and torque_dev are device memory as in
  * dg_torque; the work is queued on hip_stream (NULL = default stream).  The
- * per-block partial sums live in a static device array of 131072 doubles
- * (1 MiB per GPU, held until the process ends): grids needing more partials
- * (more than 4 * 131072 tiles of 64 / order elements) give DG_EUNSUPPORTED.
+ * per-tile partial sums live in a static device array of 524288 doubles
+ * (4 MiB per GPU, held until the process ends): grids of more than 524288
+ * tiles of 64 / order elements of a row give DG_EUNSUPPORTED.
  * Nothing is allocated and no state is kept between calls except that array:
  * calls that overlap on one GPU (other streams, other host threads) race on
  * it, so the caller serialises them.  Errors as for the handle-less calls

@@ -43,8 +43,7 @@ struct dg_handle {
     int* damp_list = nullptr;
     int ndamp = 0;
     double* damp_q0 = nullptr;  // damping targets at the Gauss nodes of the listed tiles
-    double* tq_part = nullptr;
-    int tq_blocks = 0;
+    double* tq_part = nullptr;  // torque partials, one per tile
     // troubled cells / learned indicator
     double* scale_dev = nullptr;     // feature scales (nvar)
     double scale_host[4] = {0, 0, 0, 0};
@@ -223,7 +222,7 @@ void drop_events(dg_handle* h) {
 // launch one stage kernel, bracketed by events while profiling; pp: with the
 // positivity scaling fused (FP64 path)
 hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, const StageCoeffs* sc,
-                 bool pp = false) {
+                 bool pp = false, double* tq_part = nullptr) {
     hipEvent_t a = nullptr, b = nullptr;
     if (h->prof) {
         hipError_t e = hipEventCreate(&a);
@@ -235,7 +234,7 @@ hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, c
         if (e != hipSuccess) return e;
     }
     hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, h->eqtr, out, sc, h->s)
-                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, h->s);
+                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, tq_part, h->s);
     if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
     return e;
 }
@@ -346,6 +345,7 @@ void release(dg_handle* h) {
     (void)hipFree(h->damp_list);
     (void)hipFree(h->damp_q0);
     (void)hipFree(h->tq_part);
+    h->tq_part = nullptr;
     (void)hipFree(h->eq);
     (void)hipFree(h->du0);
     (void)hipFree(h->leq);
@@ -362,11 +362,11 @@ void release(dg_handle* h) {
     h->eqtr = nullptr;
 }
 
-// Scratch of dg_torque_noalloc: the torque's per-block partial sums, one
-// copy per GPU in a static device array (no allocation at any call).  Host
-// code uses the device address from hipGetSymbolAddress, never the array's
-// name (a host-side stand-in).
-constexpr int kNoAllocPartials = 1 << 17;
+// Scratch of dg_torque_noalloc: the torque's per-tile partial sums (4 MiB),
+// one copy per GPU in a static device array (no allocation at any call).
+// Host code uses the device address from hipGetSymbolAddress, never the
+// array's name (a host-side stand-in).
+constexpr int kNoAllocPartials = 1 << 19;
 __device__ __align__(256) double scratch[kNoAllocPartials];
 
 constexpr int kMaxDevices = 64;
@@ -460,8 +460,7 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     h->dt_blocks = dgk::dt_blocks(h->g);
     DG_ALLOC(h->dt_part, sizeof(double) * (size_t)h->dt_blocks);
     DG_ALLOC(h->bad_part, sizeof(unsigned int) * (size_t)h->dt_blocks);
-    h->tq_blocks = dgk::torque_blocks(h->g);
-    DG_ALLOC(h->tq_part, sizeof(double) * (size_t)h->tq_blocks);
+    DG_ALLOC(h->tq_part, sizeof(double) * (size_t)dgk::torque_partials(h->g));
     DG_ALLOC(prim_dev, prim_bytes);
     DG_ALLOC(h->scale_dev, sizeof(double) * 4);
     DG_ALLOC(h->flags, (size_t)h->E);
@@ -547,7 +546,7 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
         e = hipMemcpyAsync(prim_dev, peq.data(), sizeof(double) * peq.size(), hipMemcpyHostToDevice, h->s);
         if (e == hipSuccess) e = dgk::launch_project(h->n, h->nvar, h->g, prim_dev, h->eq, h->s);
         if (e == hipSuccess) e = dgk::launch_set_coeffs(h->sc_rhs, g0, 0.0, 0.0, 0.0, 1.0, h->s);
-        if (e == hipSuccess) e = dgk::launch_stage(h->n, g0, h->eq, nullptr, h->eq, h->leq, h->sc_rhs, false, h->s);
+        if (e == hipSuccess) e = dgk::launch_stage(h->n, g0, h->eq, nullptr, h->eq, h->leq, h->sc_rhs, false, nullptr, h->s);
         if (e == hipSuccess) e = dgk::launch_eq_traces(h->n, h->g, h->eq, h->eqtr, h->s);
         if (e == hipSuccess) e = dgk::launch_add_state(u0_dev, h->eq, u0_dev, -1.0, N, h->s);
         if (e == hipSuccess) e = hipMemcpyAsync(h->du0, u0_dev, state_bytes, hipMemcpyDeviceToDevice, h->s);
@@ -589,16 +588,19 @@ int dg_rhs(dg_handle* h, double t, const double* u_dev, double* rhs_dev) {
     DG_HIP(h, dgk::launch_set_coeffs(h->sc_rhs, h->g, t, 0.0, 0.0, 1.0, h->s), "dg_rhs coefficients");
     DG_HIP(h, h->dev ? dgk::launch_stage_dev(h->n, h->g, u_dev, nullptr, h->du0, h->leq, h->eqtr, rhs_dev, h->sc_rhs,
                                              h->s)
-                     : dgk::launch_stage(h->n, h->g, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, false, h->s),
+                     : dgk::launch_stage(h->n, h->g, u_dev, nullptr, h->u0, rhs_dev, h->sc_rhs, false, nullptr, h->s),
            "dg_rhs stage");
     return DG_OK;
 }
 
-int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, double* dt_used_dev) {
+// One step (Algorithm 1); with tq (FP64 form) the first stage, whose input is
+// u^n at t^n, also forms the torque partials of u^n (h->tq_part).
+static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, double* dt_used_dev, bool tq) {
     if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
     if (!u_dev || !t_dev) return fail(h, DG_EINVAL, "u_dev and t_dev are required");
     if (!(dt_fixed == dt_fixed)) return fail(h, DG_EINVAL, "dt_fixed is NaN");
     StepBlock* sb = h->sb;
+    double* tqp = tq ? h->tq_part : nullptr;
     DG_HIP(h, dgk::launch_dt(h->n, h->g, u_dev, h->eq, h->dt_part, h->bad_part, h->s), "CFL reduction");
     if (h->tab.s > 0) {
         // Butcher form: k_i = L(y_i), y_1 = u^n, y_i = u^n + dt sum_{j<i} a_ij k_j,
@@ -611,7 +613,8 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
                                                          dt_fixed, dt_used_dev, h->s), "step begin");
         for (int i = 0; i < S; ++i) {
             const double* y = i == 0 ? u_dev : h->ws1;
-            DG_HIP(h, stage(h, y, nullptr, h->kbuf + (size_t)i * (size_t)N, &sb->st[i]), "stage");
+            DG_HIP(h, stage(h, y, nullptr, h->kbuf + (size_t)i * (size_t)N, &sb->st[i], false, i == 0 ? tqp : nullptr),
+                   "stage");
             if (i + 1 < S) {
                 DG_HIP(h, dgk::launch_rk_combine(u_dev, k, i + 1, &sb->comb[i + 1][0], h->ws1, N, h->s), "stage state");
             }
@@ -625,7 +628,7 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     if (h->cfg.rk == DG_RK_SSP22) {
         DG_HIP(h, dgk::launch_step_begin(h->g, sb, h->dt_part, h->bad_part, h->dt_blocks, t_dev, dt_fixed,
                                                    dt_used_dev, 2, h->s), "step begin");
-        DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0]), "stage 1");
+        DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0], false, tqp), "stage 1");
         DG_HIP(h, stage(h, h->ws1, u_dev, u_dev, &sb->st[1]), "stage 2");
         if (h->cfg.damping)
             DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
@@ -637,7 +640,7 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     // the positivity scaling alone (no troubled-cell limiter before it) runs
     // inside the stage kernels
     const bool fuse = h->cfg.positivity && h->cfg.limiter == DG_LIMITER_NONE && !h->dev;
-    DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0], fuse), "stage 1");
+    DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0], fuse, tqp), "stage 1");
     if (!fuse) DG_HIP(h, limit(h, h->ws1, false), "limiter");
     DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1], fuse), "stage 2");
     if (!fuse) DG_HIP(h, limit(h, h->ws2, false), "limiter");
@@ -655,11 +658,31 @@ int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, doub
     return DG_OK;
 }
 
+int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, double* dt_used_dev) {
+    return rk_step(h, u_dev, t_dev, dt_fixed, dt_used_dev, false);
+}
+
+int dg_rk_step_torque(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, double* dt_used_dev,
+                      double* torque_dev) {
+    if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
+    if (!u_dev || !t_dev || !torque_dev) return fail(h, DG_EINVAL, "u_dev, t_dev and torque_dev are required");
+    // the deviation form's stage kernel has no torque terms, and the stage
+    // kernels with the positivity scaling fused do not take them (registers):
+    // there the two calls run one after the other
+    if (h->dev || (h->cfg.positivity && h->cfg.limiter == DG_LIMITER_NONE)) {
+        const int rc = dg_torque(h, 0.0, t_dev, u_dev, torque_dev);
+        return rc != DG_OK ? rc : rk_step(h, u_dev, t_dev, dt_fixed, dt_used_dev, false);
+    }
+    const int rc = rk_step(h, u_dev, t_dev, dt_fixed, dt_used_dev, true);
+    if (rc != DG_OK) return rc;
+    DG_HIP(h, dgk::launch_torque_final(h->g, h->tq_part, torque_dev, h->s), "torque sum");
+    return DG_OK;
+}
+
 int dg_torque(dg_handle* h, double t, const double* t_dev, const double* u_dev, double* torque_dev) {
     if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
     if (!u_dev || !torque_dev) return fail(h, DG_EINVAL, "u_dev and torque_dev are required");
-    DG_HIP(h, dgk::launch_torque(h->n, h->g, t, t_dev, u_dev, h->eq, h->tq_part, h->tq_blocks, torque_dev, h->s),
-           "torque");
+    DG_HIP(h, dgk::launch_torque(h->n, h->g, t, t_dev, u_dev, h->eq, h->tq_part, torque_dev, h->s), "torque");
     return DG_OK;
 }
 
@@ -672,16 +695,16 @@ int dg_torque_noalloc(const dg_config* cfg, double t, const double* t_dev, const
         return fail(nullptr, DG_EUNSUPPORTED, "dg_torque_noalloc takes full FP64 states (precision DG_PRECISION_FP64)");
     Geo g;
     make_geo(cfg, &g);
-    const int nb = dgk::torque_blocks(g);
+    const int nb = dgk::torque_partials(g);
     if (nb > kNoAllocPartials)
         return fail(nullptr, DG_EUNSUPPORTED,
                     "dg_torque_noalloc: the grid needs " + std::to_string(nb) + " partial sums, the static scratch holds " +
-                        std::to_string(kNoAllocPartials) + " (at most 4 * 131072 tiles of 64 / order elements)");
+                        std::to_string(kNoAllocPartials) + " (one per tile of 64 / order elements)");
     if (!u_dev || !torque_dev) return fail(nullptr, DG_EINVAL, "u_dev and torque_dev are required");
     double* part = nullptr;
     hipError_t e = scratch_of_current_device(&part);
     if (e != hipSuccess) return fail(nullptr, DG_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
-    e = dgk::launch_torque(cfg->order, g, t, t_dev, u_dev, nullptr, part, nb, torque_dev, (hipStream_t)hip_stream);
+    e = dgk::launch_torque(cfg->order, g, t, t_dev, u_dev, nullptr, part, torque_dev, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(nullptr, DG_EHIP, std::string("torque: ") + hipGetErrorString(e));
     return DG_OK;
 }

@@ -93,9 +93,12 @@ struct StepBlock {
 // launchers (all asynchronous on `s`)
 hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim_dev, double* u_dev,
                           hipStream_t s);
-// pp: the positivity scaling fused into the stage (after the combination)
+// pp: the positivity scaling fused into the stage (after the combination);
+// tq_part (optional, not with pp; a stage whose input u is the state at the
+// stage time): also the torque of eq. (5) on u, one partial per tile
+// (torque_partials doubles), for launch_torque_final
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0,
-                        double* out, const StageCoeffs* sc, bool pp, hipStream_t s);
+                        double* out, const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s);
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
 // CFL step per element; per-block minimum into dt_part[block] and a per-block
@@ -119,8 +122,12 @@ hipError_t launch_damp_prep(int n, const Geo& g, const double* u0, const int* li
                             hipStream_t s);
 hipError_t launch_damp(int n, const Geo& g, double* u, const double* q0, const double* eq, const int* list,
                        int nlist, const StageCoeffs* sc, hipStream_t s);
+// torque of eq. (5): one partial per tile into partials (torque_partials
+// doubles), then their sum in a fixed order into *out
 hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,
-                         double* partials, int nblocks, double* out, hipStream_t s);
+                         double* partials, double* out, hipStream_t s);
+// the fixed-order sum alone, of partials a stage kernel wrote
+hipError_t launch_torque_final(const Geo& g, const double* partials, double* out, hipStream_t s);
 // deviation form: leq = L(u_eq) (FP64), eqtr = u_eq's edge traces (FP32,
 // eq_trace_entries floats, written by launch_eq_traces)
 hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double* dun, const double* du0,
@@ -130,7 +137,7 @@ long long eq_trace_entries(int n, const Geo& g);
 hipError_t launch_eq_traces(int n, const Geo& g, const double* eq, float* eqtr, hipStream_t s);
 hipError_t launch_add_state(const double* a, const double* b, double* out, double sign, long long n,
                             hipStream_t s);
-int torque_blocks(const Geo& g);
+int torque_partials(const Geo& g);
 
 // troubled cells and the learned indicator
 // means of every variable into out[v * E + e] (contiguous), from a state array

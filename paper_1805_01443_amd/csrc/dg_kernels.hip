@@ -162,6 +162,24 @@ __device__ __forceinline__ double pick(const double (&t)[kMaxOrder], int k) {
     return r;
 }
 
+// ---- torque of eq. (5), per element: node (xi_q, eta_r) carries the mass
+// rho w_q w_r dx dy / 4 (w: Gauss weights on [-1, 1]); G = 1, per unit planet
+// mass.  Lane k of an element takes the nodes (xi_q, eta_k), q < N, in the
+// order q = 0 .. N - 1, from the node density rho, the planet offsets
+// (dx, dy) = (x - xp, y - yp) and id3 = ((dx^2 + dy^2 + eps^2)^(-1/2))^3.  The
+// first stage kernel and the torque kernel add the same doubles in the same
+// order, so their tile sums agree to the last bit.
+__device__ __forceinline__ double torque_term(double rho, double wnode, double xp, double yp, double dx, double dy,
+                                              double id3) {
+    const double kk = (rho * wnode) * id3;
+    return xp * (kk * dy) - yp * (kk * dx);
+}
+// sum over the wavefront by a fixed xor butterfly (every lane gets the sum)
+__device__ __forceinline__ double wave_sum(double s) {
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    return s;
+}
+
 // out = a0 u^n + a1 u + a2 L(u, t), with the N lanes of an element sharing
 // its tensor-product contractions.  Lane (s, k) = lane k * EW + s: element
 // slot s of the wave (EW = 64 / N consecutive elements of one row), index k.
@@ -186,11 +204,14 @@ __device__ __forceinline__ double pick(const double (&t)[kMaxOrder], int k) {
 //            slot at C plus two flux rows); stage combination of row a.
 // Every integral is the same Gauss sum as in eq. (3); the density volume term
 // is taken by quadrature (exact for its polynomial integrand).
-template <int N, int CL, bool PP>
+// TQ (a stage whose input is u^n at its own time, the first one): also the
+// torque of eq. (5) on u, from the node densities and planet offsets phase 2
+// evaluates anyway, as the tile's partial tq_part[tile].
+template <int N, int CL, bool PP, bool TQ>
 __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int tiles_total,
                                                 const double* __restrict__ u, const double* un,
                                                 const double* __restrict__ u0, double* out,
-                                                const StageCoeffs* __restrict__ scp) {
+                                                const StageCoeffs* __restrict__ scp, double* tq_part) {
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
@@ -449,6 +470,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
         for (int v = 0; v < NV; ++v) H[(1 * NV + v) * N + k] = hs[v];
     }
+    const double wk = pick<N>(B.wh, k) * g.dx * g.dy;  // torque: node mass factor of Gauss row k
+    double tqs = 0.0;
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         double W[NV];
@@ -478,12 +501,14 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             gx = kk * x;
             gy = kk * y;
         }
-        if (g.q > 0.0) {
+        if (TQ || g.q > 0.0) {
             const double dx = x - xp, dy = y - yp;
             const double id = rsq64(dx * dx + dy * dy + g.eps2);
-            const double kk = g.q * id * id * id;
+            const double id3 = id * id * id;
+            const double kk = g.q * id3;
             gx += kk * dx;
             gy += kk * dy;
+            if constexpr (TQ) tqs += torque_term(W[0], wk * B.wh[q], xp, yp, dx, dy, id3);
         }
         double fx[NV], fy[NV], sy[NV];
         fx[0] = W[1];
@@ -510,6 +535,10 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
                 Y[v][a] += B.wphi[a][q] * fyy;
             }
         }
+    }
+    if constexpr (TQ) {
+        const double t = wave_sum(active ? tqs : 0.0);
+        if (lane == 0) tq_part[tile] = t;
     }
     __syncthreads();  // every lane has read C
 #pragma unroll
@@ -1573,21 +1602,21 @@ __device__ __forceinline__ double block_sum(double s, double* red) {
 }
 
 // N lanes per element, one tile (EW = 64 / N elements of a row) per
-// wavefront, four tiles per block: lane k contracts the density row k in y
-// (LDS), then evaluates the nodes (xi_k, eta_r), r < N, and their torque
-// terms; one partial per block, in a fixed lane and wavefront order, so the
-// sum is bitwise reproducible.
+// wavefront, four tiles per block, with the arithmetic of the stage kernel's
+// phases 1 and 2: lane k contracts the density row k in y (LDS), then takes
+// the nodes (xi_q, eta_k), q < N; one partial per tile (the wavefront's sum by
+// a fixed butterfly), so the sum is bitwise reproducible and equal to the one
+// the first stage kernel forms on the same state.
 template <int N>
 __global__ void __launch_bounds__(64 * kTorqueWaves) k_torque(const Geo g, double t, const double* t_dev,
                                                               const double* __restrict__ u,
                                                               const double* __restrict__ eq,
                                                               double* __restrict__ partials) {
-    constexpr BasisTab T = make_basis(N);
+    constexpr BasisTab B = make_basis(N);
     constexpr int EW = 64 / N;
     constexpr int TS = (N * N) | 1;  // slot stride: odd, the slots of one k on distinct banks
     __shared__ double lds[kTorqueWaves][EW * TS];
     __shared__ double pxy[2];
-    __shared__ double red[kTorqueWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // lane k * EW + s: index k of element slot s (rows contiguous in lane
     // order); lanes beyond N * EW shadow slot 0's element and add nothing
@@ -1613,37 +1642,37 @@ __global__ void __launch_bounds__(64 * kTorqueWaves) k_torque(const Geo g, doubl
         const unsigned idx = base + mode_off<N>(0, k, b);
         row[b] = eq ? eq[idx] + u[idx] : u[idx];
     }
+    if (own) {
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-        double c = 0.0;
+        for (int r = 0; r < N; ++r) {
+            double c = 0.0;
 #pragma unroll
-        for (int b = 0; b < N; ++b) c = fma(row[b], T.phi[b][r], c);
-        S[k * N + r] = c;
+            for (int b = 0; b < N; ++b) c += row[b] * B.phi[b][r];
+            S[k * N + r] = c;
+        }
     }
     __syncthreads();
     const double xp = pxy[0], yp = pxy[1];
-    double phk[N];  // phi_a(xi_k)
+    double Cc[N];
 #pragma unroll
-    for (int a = 0; a < N; ++a) phk[a] = pick<N>(T.phi[a], k);
-    const double x = g.x0 + (i + 0.5) * g.dx + 0.5 * g.dx * pick<N>(T.xi, k);
-    const double wk = pick<N>(T.wh, k) * g.dx * g.dy;
-    const double yc = g.y0 + (j + 0.5) * g.dy;
+    for (int a = 0; a < N; ++a) Cc[a] = S[a * N + k];
+    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+    const double y = yc + 0.5 * g.dy * pick<N>(B.xi, k);
+    const double wk = pick<N>(B.wh, k) * g.dx * g.dy;
     double s = 0.0;
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
+    for (int q = 0; q < N; ++q) {
         double rho = 0.0;
 #pragma unroll
-        for (int a = 0; a < N; ++a) rho = fma(phk[a], S[a * N + r], rho);
-        const double y = yc + 0.5 * g.dy * T.xi[r];
-        const double m = rho * (wk * T.wh[r]);
+        for (int a = 0; a < N; ++a) rho += B.phi[a][q] * Cc[a];
+        const double x = xc + 0.5 * g.dx * B.xi[q];
         const double dx = x - xp, dy = y - yp;
         const double id = rsq64(dx * dx + dy * dy + g.eps2);
-        const double kk = m * (id * id * id);
-        s += xp * (kk * dy) - yp * (kk * dx);
+        const double id3 = id * id * id;
+        s += torque_term(rho, wk * B.wh[q], xp, yp, dx, dy, id3);
     }
-    if (!active) s = 0.0;
-    const double b = block_sum<kTorqueWaves>(s, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = b;
+    s = wave_sum(active ? s : 0.0);
+    if (lane == 0 && live) partials[tile] = s;
 }
 
 // one block: thread p adds the partials p, p + 1024, ... in order, then the
@@ -1686,20 +1715,29 @@ hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim, dou
 }
 
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0, double* out,
-                        const StageCoeffs* sc, bool pp, hipStream_t s) {
+                        const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s) {
     // arrays that a launch does not read still get a valid base (buffer
     // resources are never built on a null pointer)
     if (!un) un = u;
     if (!u0) u0 = u;
+    // with the positivity scaling fused the torque terms take the order-5
+    // adiabatic kernel past 256 registers (one wave per SIMD): not offered
+    if (pp && tq_part) return hipErrorInvalidValue;
+#define DG_STAGE(PPV, TQV)                                                                                      \
+    hipLaunchKernelGGL((k_stage_c<NT, CT, PPV, TQV>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, sc, \
+                       tq_part)
     DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, {
         constexpr int EW = 64 / NT;
         const int tx = (g.nx + EW - 1) / EW;
         const int tt = tx * g.ny;
         if (pp)
-            hipLaunchKernelGGL((k_stage_c<NT, CT, true>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, sc);
+            DG_STAGE(true, false);
+        else if (tq_part)
+            DG_STAGE(false, true);
         else
-            hipLaunchKernelGGL((k_stage_c<NT, CT, false>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, sc);
+            DG_STAGE(false, false);
     }));
+#undef DG_STAGE
     return hipGetLastError();
 }
 
@@ -1811,13 +1849,20 @@ hipError_t launch_add_state(const double* a, const double* b, double* out, doubl
 }
 
 // one partial per block of four tiles
-int torque_blocks(const Geo& g) { return (g.tiles_x * g.ny + kTorqueWaves - 1) / kTorqueWaves; }
+int torque_partials(const Geo& g) { return g.tiles_x * g.ny; }
 
 hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,
-                         double* partials, int nblocks, double* out, hipStream_t s) {
+                         double* partials, double* out, hipStream_t s) {
+    const int np = torque_partials(g);
+    const int nblocks = (np + kTorqueWaves - 1) / kTorqueWaves;
     DG_DISPATCH_N(n, hipLaunchKernelGGL((k_torque<NT>), dim3(nblocks), dim3(64 * kTorqueWaves), 0, s, g, t, t_dev, u,
                                          eq, partials));
-    hipLaunchKernelGGL(k_torque_final, dim3(1), dim3(kTorqueFinal), 0, s, partials, nblocks, out);
+    hipLaunchKernelGGL(k_torque_final, dim3(1), dim3(kTorqueFinal), 0, s, partials, np, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_torque_final(const Geo& g, const double* partials, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_torque_final, dim3(1), dim3(kTorqueFinal), 0, s, partials, torque_partials(g), out);
     return hipGetLastError();
 }
 

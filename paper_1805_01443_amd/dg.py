@@ -131,6 +131,7 @@ def lib():
         L.dg_full_state.argtypes = [vp, vp, vp]
         L.dg_rhs.argtypes = [vp, C.c_double, vp, vp]
         L.dg_rk_step.argtypes = [vp, vp, vp, C.c_double, vp]
+        L.dg_rk_step_torque.argtypes = [vp, vp, vp, C.c_double, vp, vp]
         L.dg_torque.argtypes = [vp, C.c_double, vp, vp, vp]
         L.dg_torque_noalloc.argtypes = [cp, C.c_double, vp, vp, vp, vp]
         L.dg_sync.argtypes = [vp]
@@ -147,7 +148,8 @@ def lib():
         L.dg_capture.argtypes = [vp, vp, vp, vp, vp]
         L.dg_last_error.argtypes = [vp]
         L.dg_last_error.restype = C.c_char_p
-        for name in ("dg_get_nodes", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
+        for name in ("dg_get_nodes", "dg_init", "dg_rhs", "dg_rk_step", "dg_rk_step_torque", "dg_torque",
+                     "dg_sync", "dg_free",
                      "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled", "dg_positivity",
                      "dg_mlp_feature_scales", "dg_mlp_features", "dg_mlp_params", "dg_mlp_forward",
                      "dg_mlp_train_step", "dg_capture", "dg_torque_noalloc"):
@@ -156,7 +158,8 @@ def lib():
     return _lib
 
 
-EXPORTS = ("dg_get_nodes", "dg_state_size", "dg_init", "dg_rhs", "dg_rk_step", "dg_torque", "dg_sync", "dg_free",
+EXPORTS = ("dg_get_nodes", "dg_state_size", "dg_init", "dg_rhs", "dg_rk_step", "dg_rk_step_torque", "dg_torque",
+           "dg_sync", "dg_free",
            "dg_last_error", "dg_profile_begin", "dg_profile_end", "dg_full_state", "dg_troubled", "dg_positivity",
            "dg_mlp_feature_scales", "dg_mlp_features", "dg_mlp_params", "dg_mlp_forward", "dg_mlp_train_step",
            "dg_capture", "dg_torque_noalloc")
@@ -261,6 +264,12 @@ def dg_rhs(h: Handle, t: float, u, rhs):
 
 def dg_rk_step(h: Handle, u, t_dev, dt_fixed: float = 0.0, dt_used=None):
     _check(lib().dg_rk_step(h.ptr, _ptr(u), _ptr(t_dev), float(dt_fixed), _ptr(dt_used)), h.ptr)
+
+
+def dg_rk_step_torque(h: Handle, u, t_dev, out, dt_fixed: float = 0.0, dt_used=None):
+    """The torque of the state entering the step (u^n at t^n) into the device
+    double out, then dg_rk_step (same bits as dg_torque before dg_rk_step)."""
+    _check(lib().dg_rk_step_torque(h.ptr, _ptr(u), _ptr(t_dev), float(dt_fixed), _ptr(dt_used), _ptr(out)), h.ptr)
 
 
 def dg_torque(h: Handle, u, out, t: float = 0.0, t_dev=None):

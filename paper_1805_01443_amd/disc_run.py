@@ -55,8 +55,7 @@ def run(nx, order, orbits, rk=dg.RK_SSP33, chunk=2000, every=50, log=print, work
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(chunk):
-            dg.dg_rk_step(h, u, t_dev, 0.0, dt_dev)
-            dg.dg_torque(h, u, tq[k:k + 1], t_dev=t_dev)
+            dg.dg_rk_step_torque(h, u, t_dev, tq[k:k + 1], 0.0, dt_dev)
         torch.cuda.synchronize()
         el += time.perf_counter() - t0
         dg.dg_sync(h)

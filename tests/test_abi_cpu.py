@@ -85,6 +85,7 @@ def test_null_handle_calls_fail_cleanly():
     L = dg.lib()
     assert L.dg_rhs(None, 0.0, None, None) == dg.DG_EINVAL
     assert L.dg_rk_step(None, None, None, 0.0, None) == dg.DG_EINVAL
+    assert L.dg_rk_step_torque(None, None, None, 0.0, None, None) == dg.DG_EINVAL
     assert L.dg_torque(None, 0.0, None, None, None) == dg.DG_EINVAL
     assert L.dg_sync(None) == dg.DG_EINVAL
     assert L.dg_free(None) == dg.DG_OK
@@ -139,10 +140,10 @@ def test_state_size_limit_is_the_buffer_range():
 
 
 def test_noalloc_torque_rejects_what_it_cannot_hold_without_a_device():
-    """dg_torque_noalloc keeps its partial sums in a static array of 131072
-    doubles: a grid needing more is refused before any device call, and so is
-    the deviation form (its states are not full states)."""
-    # order 2: 32 elements per tile, 128 tiles per row: 134400 partial sums
+    """dg_torque_noalloc keeps its partial sums, one per tile, in a static
+    array of 524288 doubles: a grid needing more is refused before any device
+    call, and so is the deviation form (its states are not full states)."""
+    # order 2: 32 elements per tile, 128 tiles per row: 537600 partial sums
     cfg = W.disc(nx=4096, order=2).replace(ny=4200)
     assert dg.dg_state_size(cfg) > 0
     with pytest.raises(dg.DGError) as ex:
