@@ -39,7 +39,7 @@ class _Cfg(C.Structure):
         ("q", C.c_double), ("eps", C.c_double), ("rp", C.c_double), ("phi0", C.c_double),
         ("damping", C.c_int), ("rd_in", C.c_double), ("rd_out", C.c_double),
         ("cfl", C.c_double), ("rk", C.c_int), ("positivity", C.c_int),
-        ("pp_eps", C.c_double),
+        ("pp_eps", C.c_double), ("flux", C.c_int),
     ]
 
 
@@ -62,6 +62,7 @@ def lib():
         _lib.or_project.argtypes = [cp, P, P]
         _lib.or_eval_nodes.argtypes = [cp, P, P]
         _lib.or_rhs.argtypes = [cp, C.c_double, P, P, P]
+        _lib.or_num_flux.argtypes = [cp, P, P, C.c_double, C.c_double, C.c_double, C.c_double, P]
         _lib.or_dt.argtypes = [cp, P]
         _lib.or_dt.restype = C.c_double
         _lib.or_rk_butcher.argtypes = [C.c_int, P, P, P, _RHS_FN, C.c_void_p, C.c_long, P,
@@ -97,7 +98,7 @@ def lib():
 _DEFAULTS = dict(n=3, nvar=3, nx=8, ny=8, x0=0.0, x1=1.0, y0=0.0, y1=1.0, closure=0, cs=1.0,
                  h=0.05, gamma=1.4, bc=0, star=0, gm=1.0, r_core=0.4, q=0.0, eps=0.03,
                  rp=1.0, phi0=0.0, damping=0, rd_in=0.4, rd_out=2.3, cfl=0.2, rk=0,
-                 positivity=0, pp_eps=0.0)
+                 positivity=0, pp_eps=0.0, flux=0)
 
 
 def cfg(fields=None, **kw):
@@ -178,6 +179,14 @@ def rhs(c, t, u, u0=None):
     keep = _f64(u0) if u0 is not None else None
     lib().or_rhs(C.byref(c), float(t), _p(u), _p(keep) if keep is not None else u0p, _p(out))
     return out
+
+
+def num_flux(c, Ui, Uo, nx, ny, x=0.0, y=0.0):
+    """the configured edge flux h(U_in, U_out) for outward normal (nx, ny)"""
+    Ui, Uo = _f64(Ui), _f64(Uo)
+    h = np.zeros(c.nvar)
+    lib().or_num_flux(C.byref(c), _p(Ui), _p(Uo), float(nx), float(ny), float(x), float(y), _p(h))
+    return h
 
 
 def dt(c, u):

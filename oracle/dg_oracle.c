@@ -279,6 +279,70 @@ static void rusanov(const or_cfg *c, const double *Ui, const double *Uo, double 
     for (int v = 0; v < c->nvar; ++v) h[v] = 0.5 * (Fi[v] + Fo[v]) - 0.5 * alpha * (Uo[v] - Ui[v]);
 }
 
+/* HLLC flux for the adiabatic closure (Toro, Spruce & Speares 1994; Toro,
+ * Riemann Solvers and Numerical Methods for Fluid Dynamics, Sec. 10.4), left
+ * state = the element's own trace, right state = the exterior, n = the
+ * element's outward normal; normal velocities q = v.n.  Wave speeds as
+ * estimated by Davis (1988):
+ *   S_L = min(q_L - c_L, q_R - c_R),  S_R = max(q_L + c_L, q_R + c_R);
+ * contact speed from the momentum jump conditions across the two outer waves:
+ *   S* = (p_R - p_L + rho_L q_L (S_L - q_L) - rho_R q_R (S_R - q_R))
+ *        / (rho_L (S_L - q_L) - rho_R (S_R - q_R));
+ * star state of side K (density, momentum with the normal velocity replaced by
+ * S*, energy):
+ *   U*_K = rho_K (S_K - q_K) / (S_K - S*)
+ *          [1, v_K + (S* - q_K) n, E_K / rho_K + (S* - q_K) (S* + p_K / (rho_K (S_K - q_K)))];
+ * flux: F_L if S_L >= 0; F_L + S_L (U*_L - U_L) if S_L < 0 <= S*;
+ * F_R + S_R (U*_R - U_R) if S* < 0 < S_R; F_R if S_R <= 0. */
+static void hllc(const or_cfg *c, const double *UL, const double *UR, double nx, double ny, double x, double y,
+                 double *h)
+{
+    double pl, cl, pr, cr, FL[OR_MAXV], FR[OR_MAXV];
+    closure(c, UL, x, y, &pl, &cl);
+    closure(c, UR, x, y, &pr, &cr);
+    flux_n(c, UL, pl, nx, ny, FL);
+    flux_n(c, UR, pr, nx, ny, FR);
+    double rl = UL[0], rr = UR[0];
+    double ql = (UL[1] * nx + UL[2] * ny) / rl, qr = (UR[1] * nx + UR[2] * ny) / rr;
+    double sl = fmin(ql - cl, qr - cr), sr = fmax(ql + cl, qr + cr);
+    double ss = (pr - pl + rl * ql * (sl - ql) - rr * qr * (sr - qr)) / (rl * (sl - ql) - rr * (sr - qr));
+    if (sl >= 0.0) {
+        for (int v = 0; v < 4; ++v) h[v] = FL[v];
+        return;
+    }
+    if (sr <= 0.0) {
+        for (int v = 0; v < 4; ++v) h[v] = FR[v];
+        return;
+    }
+    /* the side whose star state the edge sees */
+    const int left = ss >= 0.0;
+    const double *U = left ? UL : UR, *F = left ? FL : FR;
+    double sk = left ? sl : sr, qk = left ? ql : qr, pk = left ? pl : pr, rk = U[0];
+    double f = rk * (sk - qk) / (sk - ss);
+    double us[4];
+    us[0] = f;
+    us[1] = f * (U[1] / rk + (ss - qk) * nx);
+    us[2] = f * (U[2] / rk + (ss - qk) * ny);
+    us[3] = f * (U[3] / rk + (ss - qk) * (ss + pk / (rk * (sk - qk))));
+    for (int v = 0; v < 4; ++v) h[v] = F[v] + sk * (us[v] - U[v]);
+}
+
+/* the configured numerical flux of eq. (3) */
+static void num_flux(const or_cfg *c, const double *Ui, const double *Uo, double nx, double ny, double x, double y,
+                     double *h)
+{
+    if (c->flux == 1 && c->closure == 2)
+        hllc(c, Ui, Uo, nx, ny, x, y, h);
+    else
+        rusanov(c, Ui, Uo, nx, ny, x, y, h);
+}
+
+void or_num_flux(const or_cfg *c, const double *Ui, const double *Uo, double nx, double ny, double x, double y,
+                 double *h)
+{
+    num_flux(c, Ui, Uo, nx, ny, x, y, h);
+}
+
 /* ------------------------------------------------------------------ */
 /* initial projection (Sec. 3.1 (i))                                     */
 /* ------------------------------------------------------------------ */
@@ -400,7 +464,7 @@ void or_rhs(const or_cfg *c, double t, const double *u, const double *u0, double
                     eval_point(c, u, en, xin, etan, Uo);
                 }
                 double x = xc + 0.5 * dx * xi, y = yc + 0.5 * dy * eta;
-                rusanov(c, Ui, Uo, nx, ny, x, y, h);
+                num_flux(c, Ui, Uo, nx, ny, x, y, h);
                 for (int a = 0; a < n; ++a)
                     for (int b = 0; b < n; ++b) {
                         double vv = or_phi(a, xi) * or_phi(b, eta);

@@ -47,7 +47,14 @@ typedef struct {
     int rk;           /* Appendix A table: 0 SSP(3,3), 1 SSP(2,2), 2 SSP(5,4), 3 Cash-Karp */
     int positivity;   /* 1: positivity-preserving limiter after every stage (Sec. 2.4) */
     double pp_eps;    /* floor of the limiter's eps (<= 0: 1e-13) */
+    int flux;         /* edge flux: 0 Rusanov, 1 HLLC (adiabatic closure only) */
 } or_cfg;
+
+/* The numerical flux of eq. (3) through an edge point (x, y) with unit
+ * outward normal (nx, ny): h(U_in, U_out) of the configured type (c->flux).
+ * Exported for its pins. */
+void or_num_flux(const or_cfg *c, const double *Ui, const double *Uo, double nx, double ny, double x, double y,
+                 double *h);
 
 /* Sec. 2.2, eq. (3): Gauss-Legendre nodes (ascending) and weights on [-1,1]. */
 int or_gauss_legendre(int n, double *x, double *w);
