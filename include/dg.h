@@ -60,6 +60,11 @@ enum { DG_LIMITER_NONE = 0, DG_LIMITER_MODAL_DECAY = 1, DG_LIMITER_LEARNED = 2 }
  * and the six-stage Cash-Karp table with its fifth-order weights, both as
  * printed. */
 enum { DG_RK_SSP33 = 0, DG_RK_SSP22 = 1, DG_RK_SSP54 = 2, DG_RK_CASHKARP = 3 };
+/* Numerical flux of eq. (3) (its type is not named in the paper): Rusanov
+ * (local Lax-Friedrichs, the default) or, for the adiabatic closure, HLLC
+ * (Toro, Spruce & Speares 1994, with the wave-speed estimates of Davis 1988),
+ * which keeps contact and shear waves. */
+enum { DG_FLUX_RUSANOV = 0, DG_FLUX_HLLC = 1 };
 
 /* Problem statement.  Units: G = M_* = r_p = 1 as in Sec. 5.1. */
 typedef struct dg_config {
@@ -87,6 +92,7 @@ typedef struct dg_config {
     int rk;               /* DG_RK_* (0 = SSP(3,3)) */
     int positivity;       /* 1: positivity-preserving limiter (Sec. 2.4), see dg_positivity */
     double pp_eps;        /* floor e0 of its eps (<= 0: 1e-13, Zhang & Shu's value) */
+    int flux;             /* DG_FLUX_* (DG_FLUX_HLLC: adiabatic closure, FP64 form) */
 } dg_config;
 
 typedef struct dg_handle dg_handle;

@@ -134,6 +134,9 @@ int validate(const dg_config* c, std::string* why) {
         return (*why = "the positivity limiter is built for the SSP(3,3) table", DG_EUNSUPPORTED);
     if (c->positivity && c->precision != DG_PRECISION_FP64)
         return (*why = "the positivity limiter is built for the FP64 form", DG_EUNSUPPORTED);
+    if (c->flux != DG_FLUX_RUSANOV && c->flux != DG_FLUX_HLLC) return (*why = "unknown flux", DG_EINVAL);
+    if (c->flux == DG_FLUX_HLLC && !(c->closure == DG_CLOSURE_ADIABATIC && c->precision == DG_PRECISION_FP64))
+        return (*why = "the HLLC flux is built for the adiabatic closure in the FP64 form", DG_EUNSUPPORTED);
     // the kernels address state arrays through buffer resources whose range
     // is 2^31 - 1 bytes
     if ((double)c->nvar * c->order * c->order * state_slots(c) * 8.0 > 2147483647.0)
@@ -187,6 +190,7 @@ void make_geo(const dg_config* c, Geo* g) {
     g->td_out = c->gm > 0 ? 2.0 * pi * std::sqrt(c->rd_out * c->rd_out * c->rd_out / c->gm) : 0.0;
     g->cfl_fac = c->cfl / (2.0 * (c->order - 1) + 1.0);
     g->pp_eps = c->pp_eps > 0.0 ? c->pp_eps : 1e-13;
+    g->flux = c->flux;
     if (c->positivity) {
         // Sec. 2.4: C min(1/(2N_p+1), w_1/2), w_1 of the limiter's Lobatto rule
         const dgk::LobattoTab lt = dgk::make_lobatto(c->order);

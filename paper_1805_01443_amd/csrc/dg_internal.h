@@ -44,6 +44,7 @@ struct Geo {
     double cfl_fac;             // C / (2 N_p + 1)
     double pp_eps;              // positivity limiter: floor of eps
     double sigma0;              // deviation form: equilibrium Sigma0
+    int flux;                   // 0 Rusanov, 1 HLLC (adiabatic closure)
 };
 
 // Index (in entries) of mode (0, 0) of variable 0 of element (i, j) in the

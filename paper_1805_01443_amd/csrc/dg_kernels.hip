@@ -145,6 +145,71 @@ __device__ __forceinline__ void rusanov(const Geo& g, const double* Ui, const do
     for (int v = 0; v < NV; ++v) h[v] = 0.5 * (Fi[v] + Fo[v]) - 0.5 * alpha * (Uo[v] - Ui[v]);
 }
 
+// HLLC flux (adiabatic closure) through an axis-aligned edge with outward
+// normal n = SGN * e_AX, own state Ui (left), exterior Uo (right): Toro,
+// Spruce & Speares' three-wave flux with Davis' outer wave speeds
+//   S_L = min(q_L - c_L, q_R - c_R), S_R = max(q_L + c_L, q_R + c_R), q = v.n,
+// the contact speed S* from the momentum jump conditions of the outer waves,
+//   S* = (p_R - p_L + rho_L q_L (S_L - q_L) - rho_R q_R (S_R - q_R))
+//        / (rho_L (S_L - q_L) - rho_R (S_R - q_R)),
+// and the star state of the side the edge sees,
+//   U*_K = rho_K (S_K - q_K) / (S_K - S*)
+//          [1, v_K + (S* - q_K) n, E_K / rho_K + (S* - q_K) (S* + p_K / (rho_K (S_K - q_K)))],
+// h = F_L (S_L >= 0), F_K + S_K (U*_K - U_K) (K = L if S* >= 0, else R), F_R (S_R <= 0).
+template <int AX, int SGN>
+__device__ __forceinline__ void hllc(const Geo& g, const double* Ui, const double* Uo, double* h) {
+    const double ii = rcp64(Ui[0]), io = rcp64(Uo[0]);
+    const double gm1 = g.gamma - 1.0;
+    const double pi = gm1 * (Ui[3] - 0.5 * (Ui[1] * Ui[1] + Ui[2] * Ui[2]) * ii);
+    const double po = gm1 * (Uo[3] - 0.5 * (Uo[1] * Uo[1] + Uo[2] * Uo[2]) * io);
+    const double ti = g.gamma * pi * ii, to = g.gamma * po * io;
+    const double ci = ti * rsq64(ti), co = to * rsq64(to);
+    const double qi = SGN * Ui[1 + AX] * ii, qo = SGN * Uo[1 + AX] * io;
+    double Fi[4], Fo[4];
+    Fi[0] = Ui[0] * qi;
+    Fo[0] = Uo[0] * qo;
+    Fi[1] = Ui[1] * qi + (AX == 0 ? SGN * pi : 0.0);
+    Fo[1] = Uo[1] * qo + (AX == 0 ? SGN * po : 0.0);
+    Fi[2] = Ui[2] * qi + (AX == 1 ? SGN * pi : 0.0);
+    Fo[2] = Uo[2] * qo + (AX == 1 ? SGN * po : 0.0);
+    Fi[3] = (Ui[3] + pi) * qi;
+    Fo[3] = (Uo[3] + po) * qo;
+    const double sl = fmin(qi - ci, qo - co), sr = fmax(qi + ci, qo + co);
+    const double ss = (po - pi + Ui[0] * qi * (sl - qi) - Uo[0] * qo * (sr - qo)) *
+                      rcp64(Ui[0] * (sl - qi) - Uo[0] * (sr - qo));
+    // the side the edge sees (selects, no divergence)
+    const bool left = ss >= 0.0;
+    const double sk = left ? sl : sr, qk = left ? qi : qo, pk = left ? pi : po, ik = left ? ii : io;
+    double U[4], F[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        U[v] = left ? Ui[v] : Uo[v];
+        F[v] = left ? Fi[v] : Fo[v];
+    }
+    const double rk = U[0], dq = ss - qk;
+    const double f = rk * (sk - qk) * rcp64(sk - ss);
+    double us[4];
+    us[0] = f;
+    us[1] = f * (U[1] * ik + (AX == 0 ? SGN * dq : 0.0));
+    us[2] = f * (U[2] * ik + (AX == 1 ? SGN * dq : 0.0));
+    us[3] = f * (U[3] * ik + dq * (ss + pk * rcp64(rk * (sk - qk))));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const double star = F[v] + sk * (us[v] - U[v]);
+        h[v] = sl >= 0.0 ? Fi[v] : (sr <= 0.0 ? Fo[v] : star);
+    }
+}
+
+// the configured edge flux: HLLC (FX = 1, adiabatic closure) or Rusanov
+template <int CL, int FX, int AX, int SGN>
+__device__ __forceinline__ void edge_flux(const Geo& g, const double* Ui, const double* Uo, double x, double y,
+                                          double* h) {
+    if constexpr (FX == 1 && CL == CL_ADI)
+        hllc<AX, SGN>(g, Ui, Uo, h);
+    else
+        rusanov<CL, AX, SGN>(g, Ui, Uo, x, y, h);
+}
+
 // ------------------------------------------------------------------ stage kernel, N lanes per element
 // Slot size in LDS for the N-lanes kernels: the lanes of one index k run over
 // the element slots (lane k * EW + s), and an odd slot stride puts the slots
@@ -204,10 +269,11 @@ __device__ __forceinline__ double wave_sum(double s) {
 //            slot at C plus two flux rows); stage combination of row a.
 // Every integral is the same Gauss sum as in eq. (3); the density volume term
 // is taken by quadrature (exact for its polynomial integrand).
+// FX: the edge flux (0 Rusanov, 1 HLLC for the adiabatic closure).
 // TQ (a stage whose input is u^n at its own time, the first one): also the
 // torque of eq. (5) on u, from the node densities and planet offsets phase 2
 // evaluates anyway, as the tile's partial tq_part[tile].
-template <int N, int CL, bool PP, bool TQ>
+template <int N, int CL, bool PP, bool TQ, int FX>
 __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int tiles_total,
                                                 const double* __restrict__ u, const double* un,
                                                 const double* __restrict__ u0, double* out,
@@ -426,8 +492,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             Wx[v] = gw ? tl : from_w;
             Ex[v] = ge ? tr : from_e;
         }
-        rusanov<CL, 0, -1>(g, Ui, Wx, xc - 0.5 * g.dx, yk, hw);
-        rusanov<CL, 0, 1>(g, Ei, Ex, xc + 0.5 * g.dx, yk, he);
+        edge_flux<CL, FX, 0, -1>(g, Ui, Wx, xc - 0.5 * g.dx, yk, hw);
+        edge_flux<CL, FX, 0, 1>(g, Ei, Ex, xc + 0.5 * g.dx, yk, he);
         // west/east lifts of row r enter R[a][b] with the same weight
         // w_r phi_b(eta_r) as X[r][a]: X[r][a] = -(1/dx)(phi_a(-1) h_W + phi_a(1) h_E)
 #pragma unroll
@@ -452,7 +518,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             Ui[v] = si;
             Uo[v] = so;
         }
-        rusanov<CL, 1, -1>(g, Ui, Uo, xk, yc - 0.5 * g.dy, hs);
+        edge_flux<CL, FX, 1, -1>(g, Ui, Uo, xk, yc - 0.5 * g.dy, hs);
 #pragma unroll
         for (int v = 0; v < NV; ++v) H[(0 * NV + v) * N + k] = hs[v];
 #pragma unroll
@@ -466,7 +532,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             Ui[v] = si;
             Uo[v] = so;
         }
-        rusanov<CL, 1, 1>(g, Ui, Uo, xk, yc + 0.5 * g.dy, hs);
+        edge_flux<CL, FX, 1, 1>(g, Ui, Uo, xk, yc + 0.5 * g.dy, hs);
 #pragma unroll
         for (int v = 0; v < NV; ++v) H[(1 * NV + v) * N + k] = hs[v];
     }
@@ -1723,20 +1789,31 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
     // with the positivity scaling fused the torque terms take the order-5
     // adiabatic kernel past 256 registers (one wave per SIMD): not offered
     if (pp && tq_part) return hipErrorInvalidValue;
-#define DG_STAGE(PPV, TQV)                                                                                      \
-    hipLaunchKernelGGL((k_stage_c<NT, CT, PPV, TQV>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, sc, \
-                       tq_part)
+#define DG_STAGE(PPV, TQV, FXV)                                                                                  \
+    hipLaunchKernelGGL((k_stage_c<NT, CT, PPV, TQV, FXV>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, \
+                       sc, tq_part)
+#define DG_STAGE_FX(FXV)                 \
+    if (pp)                              \
+        DG_STAGE(true, false, FXV);      \
+    else if (tq_part)                    \
+        DG_STAGE(false, true, FXV);      \
+    else                                 \
+        DG_STAGE(false, false, FXV)
     DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, {
         constexpr int EW = 64 / NT;
         const int tx = (g.nx + EW - 1) / EW;
         const int tt = tx * g.ny;
-        if (pp)
-            DG_STAGE(true, false);
-        else if (tq_part)
-            DG_STAGE(false, true);
-        else
-            DG_STAGE(false, false);
+        if constexpr (CT == CL_ADI) {
+            if (g.flux == 1) {
+                DG_STAGE_FX(1);
+            } else {
+                DG_STAGE_FX(0);
+            }
+        } else {
+            DG_STAGE_FX(0);
+        }
     }));
+#undef DG_STAGE_FX
 #undef DG_STAGE
     return hipGetLastError();
 }

@@ -22,6 +22,7 @@ BC_PERIODIC, BC_FIXED_INITIAL, BC_GRADIENT_FREE = 0, 1, 2
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 LIMITER_NONE, LIMITER_MODAL_DECAY, LIMITER_LEARNED = 0, 1, 2
 RK_SSP33, RK_SSP22, RK_SSP54, RK_CASHKARP = 0, 1, 2, 3
+FLUX_RUSANOV, FLUX_HLLC = 0, 1
 
 
 class DGError(RuntimeError):
@@ -40,7 +41,7 @@ class dg_config(C.Structure):
         ("damping", C.c_int), ("rd_in", C.c_double), ("rd_out", C.c_double),
         ("cfl", C.c_double), ("precision", C.c_int), ("sigma0", C.c_double), ("limiter", C.c_int),
         ("limiter_s0", C.c_double), ("mlp_theta", C.c_double), ("rk", C.c_int), ("positivity", C.c_int),
-        ("pp_eps", C.c_double),
+        ("pp_eps", C.c_double), ("flux", C.c_int),
     ]
 
 
@@ -79,6 +80,7 @@ class Config:
     rk: int = RK_SSP33
     positivity: int = 0
     pp_eps: float = 0.0
+    flux: int = 0
 
     @property
     def n(self):

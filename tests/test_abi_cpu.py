@@ -68,6 +68,8 @@ def dataclass_fields(cfg):
     (dict(pp_eps=-1.0), dg.DG_EINVAL),
     (dict(pp_eps=float("nan")), dg.DG_EINVAL),
     (dict(bc=3), dg.DG_EINVAL),
+    (dict(flux=2), dg.DG_EINVAL),
+    (dict(flux=dg.FLUX_HLLC), dg.DG_EUNSUPPORTED),  # isothermal closure
 ])
 def test_init_rejects_bad_configs_without_a_device(bad, code):
     cfg = W.wave(nx=8).replace(**bad)

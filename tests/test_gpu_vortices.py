@@ -165,11 +165,13 @@ def vorticity(cfg, a):
 
 def test_gresho_errors_against_table1():
     """Sec. 4.2, Table 1: relative L1 errors of vorticity and density at
-    T = 3 on 40 x 40, orders 2-4.  Loose checks (the paper's CFL number and
-    time integrator for this table are not stated): vorticity within a factor
-    1.5 of the paper's value (measured 26.8, 12.4, 7.8 % against 20.5, 12.0,
-    6.46 %), density within a factor 10 (0.28, 0.035, 0.0048 % against 0.05,
-    0.01, 0.008 %), and both decrease with the order as in the paper."""
+    T = 3 on 40 x 40, orders 2-4, with the Rusanov flux: vorticity within a
+    factor 1.5 of the paper's value (measured 26.8, 12.4, 7.8 % against 20.5,
+    12.0, 6.46 %), density within a factor 6 (0.28, 0.035, 0.0048 % against
+    0.05, 0.01, 0.008 %), and both decrease with the order as in the paper.
+    The density gap is the flux's: the paper does not name its flux, and with
+    the HLLC flux the same runs meet the density rows within a factor 1.3
+    (tests/test_gpu_hllc.py); halving the step changes nothing."""
     rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
     res = []
     for name, order, vort_pct, dens_pct in rows:
@@ -189,5 +191,5 @@ def test_gresho_errors_against_table1():
               f"L1 density error {de:.4f} % (paper {dens_pct})", flush=True)
         res.append((ve, de, float(vort_pct), float(dens_pct)))
     for ve, de, pv, pd in res:
-        assert pv / 1.5 <= ve <= pv * 1.5 and pd / 10 <= de <= pd * 10, res
+        assert pv / 1.5 <= ve <= pv * 1.5 and pd / 6 <= de <= pd * 6, res
     assert res[0][0] > res[1][0] > res[2][0] and res[0][1] > res[1][1] > res[2][1], res
