@@ -282,10 +282,11 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
     constexpr BasisTab B = make_basis(N);
-    // C, later X then Y; south/north fluxes; with the positivity scaling
-    // fused, its rows and minima after that
-    constexpr int SLOT = lds_slot_odd(PP && pp_slot<N, NV>() > NV * NN + 2 * NV * N ? pp_slot<N, NV>()
-                                                                                   : NV * NN + 2 * NV * N);
+    // C, later X then Y; the y collapses of the element's rows (phase 1 to 2),
+    // later the south/north fluxes in the same place; with the positivity
+    // scaling fused, its rows and minima after that
+    constexpr int SLOT = lds_slot_odd(PP && pp_slot<N, NV>() > NV * NN + 4 * NV * N ? pp_slot<N, NV>()
+                                                                                   : NV * NN + 4 * NV * N);
     __shared__ double lds[EW * SLOT];
 
     // Lane k * EW + s holds index k of element slot s: the lanes of one k
@@ -452,6 +453,18 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             Tr[v] = fr ? e + o : Tr[v];
         }
     }
+    // the y collapses of row k (own south / north, exterior south / north)
+    // for the element's other lanes: [kind][v][a] after C
+    {
+        double* TT = S + NV * NN;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            TT[(0 * NV + v) * N + k] = Tm[v];
+            TT[(1 * NV + v) * N + k] = Tp[v];
+            TT[(2 * NV + v) * N + k] = Tb[v];
+            TT[(3 * NV + v) * N + k] = Tt[v];
+        }
+    }
     __syncthreads();
 
     // ---- phase 2: k = Gauss row r
@@ -465,9 +478,11 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int a = 0; a < N; ++a) Cc[v][a] = S[(v * N + a) * N + k];
-    // edge traces at point k and their fluxes (outward normals); a collapse of
-    // row a is held by lane e0 + a * EW
-    double* H = S + NV * NN;  // south / north fluxes [edge][v][point]
+    // edge traces at point k and their fluxes (outward normals); the y
+    // collapses of the element's rows come from LDS (TT), the x collapses of a
+    // loaded neighbour column from lane e0 + a * EW
+    const double* TT = S + NV * NN;
+    double* H = S + NV * NN;  // south / north fluxes [edge][v][point], written over TT once it is read
     double X[NV][N], Y[NV][N];
     {
         double Ui[NV], Uo[NV], hw[NV], he[NV], hs[NV];
@@ -506,35 +521,38 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             }
         }
         const double xk = xc + 0.5 * g.dx * xik;
-        // south / north: own and exterior traces from the y collapses
+        // south / north: own and exterior traces from the y collapses; both
+        // fluxes are formed before either is stored over the collapses
+        double hn[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             double si = 0.0, so = 0.0;
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                si += phk[a] * __shfl(Tm[v], e0 + a * EW);
-                so += phk[a] * __shfl(Tb[v], e0 + a * EW);
+                si += phk[a] * TT[(0 * NV + v) * N + a];
+                so += phk[a] * TT[(2 * NV + v) * N + a];
             }
             Ui[v] = si;
             Uo[v] = so;
         }
         edge_flux<CL, FX, 1, -1>(g, Ui, Uo, xk, yc - 0.5 * g.dy, hs);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) H[(0 * NV + v) * N + k] = hs[v];
-#pragma unroll
         for (int v = 0; v < NV; ++v) {
             double si = 0.0, so = 0.0;
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                si += phk[a] * __shfl(Tp[v], e0 + a * EW);
-                so += phk[a] * __shfl(Tt[v], e0 + a * EW);
+                si += phk[a] * TT[(1 * NV + v) * N + a];
+                so += phk[a] * TT[(3 * NV + v) * N + a];
             }
             Ui[v] = si;
             Uo[v] = so;
         }
-        edge_flux<CL, FX, 1, 1>(g, Ui, Uo, xk, yc + 0.5 * g.dy, hs);
+        edge_flux<CL, FX, 1, 1>(g, Ui, Uo, xk, yc + 0.5 * g.dy, hn);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) H[(1 * NV + v) * N + k] = hs[v];
+        for (int v = 0; v < NV; ++v) {
+            H[(0 * NV + v) * N + k] = hs[v];
+            H[(1 * NV + v) * N + k] = hn[v];
+        }
     }
     const double wk = pick<N>(B.wh, k) * g.dx * g.dy;  // torque: node mass factor of Gauss row k
     double tqs = 0.0;
