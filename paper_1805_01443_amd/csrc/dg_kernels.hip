@@ -285,8 +285,14 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     // C, later X then Y; the y collapses of the element's rows (phase 1 to 2),
     // later the south/north fluxes in the same place; with the positivity
     // scaling fused, its rows and minima after that
-    constexpr int SLOT = lds_slot_odd(PP && pp_slot<N, NV>() > NV * NN + 4 * NV * N ? pp_slot<N, NV>()
-                                                                                   : NV * NN + 4 * NV * N);
+    // At orders 4 and 5 (two waves per SIMD) the y collapses of an element's
+    // rows reach its other lanes through LDS (YL: two doubles per read, where
+    // 120 lane permutes of 32 bits queued behind the wave's limit of LDS
+    // operations in flight); lower orders run more waves per SIMD and keep
+    // the lane permutes (and their smaller LDS slot).
+    constexpr bool YL = N >= 4;
+    constexpr int NEED = NV * NN + (YL ? 4 : 2) * NV * N;
+    constexpr int SLOT = lds_slot_odd(PP && pp_slot<N, NV>() > NEED ? pp_slot<N, NV>() : NEED);
     __shared__ double lds[EW * SLOT];
 
     // Lane k * EW + s holds index k of element slot s: the lanes of one k
@@ -455,7 +461,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     }
     // the y collapses of row k (own south / north, exterior south / north)
     // for the element's other lanes: [kind][v][a] after C
-    {
+    if constexpr (YL) {
         double* TT = S + NV * NN;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -479,8 +485,9 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
         for (int a = 0; a < N; ++a) Cc[v][a] = S[(v * N + a) * N + k];
     // edge traces at point k and their fluxes (outward normals); the y
-    // collapses of the element's rows come from LDS (TT), the x collapses of a
-    // loaded neighbour column from lane e0 + a * EW
+    // collapses of the element's rows come from LDS (TT, YL) or from lane
+    // e0 + a * EW, the x collapses of a loaded neighbour column from lane
+    // e0 + a * EW
     const double* TT = S + NV * NN;
     double* H = S + NV * NN;  // south / north fluxes [edge][v][point], written over TT once it is read
     double X[NV][N], Y[NV][N];
@@ -529,20 +536,34 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             double si = 0.0, so = 0.0;
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                si += phk[a] * TT[(0 * NV + v) * N + a];
-                so += phk[a] * TT[(2 * NV + v) * N + a];
+                if constexpr (YL) {
+                    si += phk[a] * TT[(0 * NV + v) * N + a];
+                    so += phk[a] * TT[(2 * NV + v) * N + a];
+                } else {
+                    si += phk[a] * __shfl(Tm[v], e0 + a * EW);
+                    so += phk[a] * __shfl(Tb[v], e0 + a * EW);
+                }
             }
             Ui[v] = si;
             Uo[v] = so;
         }
         edge_flux<CL, FX, 1, -1>(g, Ui, Uo, xk, yc - 0.5 * g.dy, hs);
+        if constexpr (!YL) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) H[(0 * NV + v) * N + k] = hs[v];
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             double si = 0.0, so = 0.0;
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                si += phk[a] * TT[(1 * NV + v) * N + a];
-                so += phk[a] * TT[(3 * NV + v) * N + a];
+                if constexpr (YL) {
+                    si += phk[a] * TT[(1 * NV + v) * N + a];
+                    so += phk[a] * TT[(3 * NV + v) * N + a];
+                } else {
+                    si += phk[a] * __shfl(Tp[v], e0 + a * EW);
+                    so += phk[a] * __shfl(Tt[v], e0 + a * EW);
+                }
             }
             Ui[v] = si;
             Uo[v] = so;
@@ -550,7 +571,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         edge_flux<CL, FX, 1, 1>(g, Ui, Uo, xk, yc + 0.5 * g.dy, hn);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            H[(0 * NV + v) * N + k] = hs[v];
+            if constexpr (YL) H[(0 * NV + v) * N + k] = hs[v];
             H[(1 * NV + v) * N + k] = hn[v];
         }
     }
