@@ -221,8 +221,8 @@ def run_limited(a):
     difference after the timed steps, on two states.
       smooth: the ring from t = 0.  At 1024^2 the plain sensor flags no element
               for t < 1 (31 500 steps): this times the indicators' cost alone.
-      jump:   the same ring with density and energy doubled inside r = 1.6, an
-              edge through the middle of elements that both pipelines must
+      jump:   the same ring with density and pressure doubled inside r = 1.6,
+              an edge through the middle of elements that both pipelines must
               limit from the first step.
     Each run first takes NCAP untimed steps that capture the plain indicator's
     flags and labels and the network's flags on the run's own last-stage states
