@@ -1780,13 +1780,21 @@ __global__ void __launch_bounds__(64 * kTorqueWaves) k_torque(const Geo g, doubl
     if (lane == 0 && live) partials[tile] = s;
 }
 
-// one block: thread p adds the partials p, p + 1024, ... in order, then the
-// block sum in a fixed order
+// one block: thread p adds the partials p, p + 1024, ... in order (eight
+// loads issued before their adds), then the block sum in a fixed order
 __global__ void __launch_bounds__(kTorqueFinal) k_torque_final(const double* __restrict__ partials, int nb,
                                                                double* __restrict__ out) {
     __shared__ double red[kTorqueFinal / 64];
     double s = 0.0;
-    for (int k = threadIdx.x; k < nb; k += kTorqueFinal) s += partials[k];
+    int k = threadIdx.x;
+    for (; k + 7 * kTorqueFinal < nb; k += 8 * kTorqueFinal) {
+        double v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = partials[k + m * kTorqueFinal];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) s += v[m];
+    }
+    for (; k < nb; k += kTorqueFinal) s += partials[k];
     const double b = block_sum<kTorqueFinal / 64>(s, red);
     if (threadIdx.x == 0) *out = b;
 }
