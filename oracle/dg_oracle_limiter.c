@@ -115,14 +115,6 @@ static double pressure_of(const or_cfg *c, const double *U)
     return (c->gamma - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0]);
 }
 
-/* rho p = (gamma - 1) (E rho - |m|^2 / 2): the pressure test p >= eps of
- * Sec. 2.4 written for a positive density as rho p >= eps rho, without the
- * division */
-static double rho_pressure_of(const or_cfg *c, const double *U)
-{
-    return (c->gamma - 1.0) * (U[3] * U[0] - 0.5 * (U[1] * U[1] + U[2] * U[2]));
-}
-
 void or_positivity(const or_cfg *c, double *u, unsigned char *changed, double *theta)
 {
     long E = (long)c->nx * c->ny;
@@ -179,17 +171,16 @@ void or_positivity(const or_cfg *c, double *u, unsigned char *changed, double *t
                 for (int v = 0; v < 4; ++v) W[v] = point_value(c, u, e, v, px[k2], py[k2]);
                 if (!(pressure_of(c, W) < eps)) continue;
                 /* p(M + t (W - M)) is concave in t, >= eps at 0 and < eps at 1:
-                 * the admissible t form [0, t*].  Bisection, keeping the
-                 * admissible end (the closed-form root of the equivalent
-                 * quadratic loses digits near a double root, and a point
-                 * left at p < 0 breaks the sound speed).  The density along
-                 * the segment is positive (the mean and the density-limited
-                 * point value are), so each step tests rho p >= eps rho. */
+                 * the admissible t form [0, t*].  Bisection on the condition
+                 * p >= eps itself, keeping the admissible end (the
+                 * closed-form root of the equivalent quadratic loses digits
+                 * near a double root, and a point left at p < 0 breaks the
+                 * sound speed). */
                 double lo = 0.0, hi = 1.0;
                 for (int it = 0; it < 64; ++it) {
                     double mid = 0.5 * (lo + hi), S[4];
                     for (int v = 0; v < 4; ++v) S[v] = M[v] + mid * (W[v] - M[v]);
-                    if (rho_pressure_of(c, S) >= eps * S[0])
+                    if (pressure_of(c, S) >= eps)
                         lo = mid;
                     else
                         hi = mid;
