@@ -31,7 +31,8 @@
  * problems (non-finite or non-positive density means) raise a flag that the
  * next dg_sync() reports as DG_ENONFINITE.  A handle belongs to one stream and
  * is not thread-safe.  Process-wide state: the message of the last failed
- * handle-less call is kept per host thread.
+ * handle-less call, kept per host thread, and the static device array of
+ * dg_torque_noalloc (one per GPU) with its device addresses.
  */
 #ifndef DG_MI355X_H
 #define DG_MI355X_H
