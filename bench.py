@@ -79,7 +79,7 @@ def calibrate_copy():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for fn in ("dg_kernels.hip", "dg_internal.h", "dg_pp.h"):
+    for fn in ("dg_kernels.hip", "dg_internal.h", "dg_pp.h", "dg_mlp.h"):
         with open(os.path.join(ROOT, "paper_1805_01443_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -94,12 +94,23 @@ struct StepBlock {
 // launchers (all asynchronous on `s`)
 hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim_dev, double* u_dev,
                           hipStream_t s);
+// The learned indicator's flags of a stage's new rows (order 4, adiabatic):
+// flags[e] = logit > zthr, features u_vm / (|u_v00| + scale_v), weights from
+// launch_mlp_pack.
+struct MlpFlags {
+    const void* pack;
+    const double* scale;
+    unsigned char* flags;
+    float zthr;
+};
 // pp: the positivity scaling fused into the stage (after the combination);
 // tq_part (optional, not with pp; a stage whose input u is the state at the
 // stage time): also the torque of eq. (5) on u, one partial per tile
-// (torque_partials doubles), for launch_torque_final
+// (torque_partials doubles), for launch_torque_final; mf (optional, order 4
+// adiabatic, not with pp): also the learned indicator's flags of out
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0,
-                        double* out, const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s);
+                        double* out, const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s,
+                        const MlpFlags* mf = nullptr);
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
 // CFL step per element; per-block minimum into dt_part[block] and a per-block
@@ -150,8 +161,10 @@ hipError_t launch_features(int n, int nvar, const Geo& g, const double* u, const
                            hipStream_t s);
 hipError_t launch_mlp_forward(const unsigned short* x, long long n, const float* par, float* z, float* h1, float* h2,
                               unsigned char* flags, float zthr, hipStream_t s);
-hipError_t launch_mlp_flags(const Geo& g, const double* u, const double* scale, const float* par,
-                            unsigned char* flags, float zthr, hipStream_t s);
+// the network's weights in per-lane fragment form (mlp_pack_bytes), for the
+// stage kernel that forms the learned indicator's flags
+hipError_t launch_mlp_pack(const float* par, void* pack, hipStream_t s);
+int mlp_pack_bytes();
 int mlp_delta_blocks(long long n);
 int mlp_nparam();
 hipError_t launch_mlp_backward(const unsigned short* x, const float* y, long long n, float pos_weight,

@@ -15,6 +15,7 @@
 #include <cstdint>
 
 #include "dg_basis.h"
+#include "dg_mlp.h"
 #include "dg_internal.h"
 #include "dg_pp.h"
 
@@ -273,11 +274,18 @@ __device__ __forceinline__ double wave_sum(double s) {
 // TQ (a stage whose input is u^n at its own time, the first one): also the
 // torque of eq. (5) on u, from the node densities and planet offsets phase 2
 // evaluates anyway, as the tile's partial tq_part[tile].
-template <int N, int CL, bool PP, bool TQ, int FX>
+// MF (order 4, adiabatic): also the learned indicator's flag of every new
+// element: at order 4 lane k * 16 + s holds modes (k, 0..3) of element slot
+// s, which is the MFMA B-fragment layout of the network (dg_mlp.h), so the
+// features go from the stored rows straight into the fragments.
+template <int N, int CL, bool PP, bool TQ, int FX, bool MF>
 __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int tiles_total,
                                                 const double* __restrict__ u, const double* un,
                                                 const double* __restrict__ u0, double* out,
-                                                const StageCoeffs* __restrict__ scp, double* tq_part) {
+                                                const StageCoeffs* __restrict__ scp, double* tq_part,
+                                                const void* __restrict__ mlp_pack,
+                                                const double* __restrict__ mlp_scale,
+                                                unsigned char* mlp_flags, float mlp_zthr) {
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
@@ -736,6 +744,21 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int b = 0; b < N; ++b) st64(rout, vrow, (unsigned)(v * N + b) * RS, O[v][b]);
+    }
+    if constexpr (MF) {
+        static_assert(N == 4 && NV == 4, "the network takes 16 modes of 4 variables");
+        MlpLane w;
+        mlp_lane_from_pack(mlp_pack, lane, w);
+        bf16x4 bfr[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            // the element's mean is mode (0, 0), held by its lane k = 0 (lane sl)
+            const double d = fabs(__shfl(O[v][0], sl)) + mlp_scale[v];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bfr[v][b] = active ? (short)f2bf((float)(O[v][b] / d)) : (short)0;
+        }
+        const float z = mlp_logit(w, bfr);
+        if (active && k == 0) mlp_flags[(size_t)j * g.nx + i] = z > mlp_zthr ? 1 : 0;
     }
 }
 
@@ -1828,7 +1851,7 @@ hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim, dou
 }
 
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0, double* out,
-                        const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s) {
+                        const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s, const MlpFlags* mf) {
     // arrays that a launch does not read still get a valid base (buffer
     // resources are never built on a null pointer)
     if (!un) un = u;
@@ -1836,16 +1859,32 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
     // with the positivity scaling fused the torque terms take the order-5
     // adiabatic kernel past 256 registers (one wave per SIMD): not offered
     if (pp && tq_part) return hipErrorInvalidValue;
-#define DG_STAGE(PPV, TQV, FXV)                                                                                  \
-    hipLaunchKernelGGL((k_stage_c<NT, CT, PPV, TQV, FXV>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, out, \
-                       sc, tq_part)
-#define DG_STAGE_FX(FXV)                 \
-    if (pp)                              \
-        DG_STAGE(true, false, FXV);      \
-    else if (tq_part)                    \
-        DG_STAGE(false, true, FXV);      \
-    else                                 \
-        DG_STAGE(false, false, FXV)
+    if (mf && (pp || n != 4 || g.closure != CL_ADI || !mf->pack || !mf->scale || !mf->flags))
+        return hipErrorInvalidValue;
+    const void* mpack = mf ? mf->pack : nullptr;
+    const double* mscale = mf ? mf->scale : nullptr;
+    unsigned char* mflags = mf ? mf->flags : nullptr;
+    const float mzthr = mf ? mf->zthr : 0.f;
+#define DG_STAGE(PPV, TQV, FXV, MFV)                                                                             \
+    hipLaunchKernelGGL((k_stage_c<NT, CT, PPV, TQV, FXV, MFV>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, \
+                       out, sc, tq_part, mpack, mscale, mflags, mzthr)
+#define DG_STAGE_MF(TQV, FXV)                                      \
+    if constexpr (NT == 4 && CT == CL_ADI) {                       \
+        if (mf)                                                    \
+            DG_STAGE(false, TQV, FXV, true);                       \
+        else                                                       \
+            DG_STAGE(false, TQV, FXV, false);                      \
+    } else {                                                       \
+        DG_STAGE(false, TQV, FXV, false);                          \
+    }
+#define DG_STAGE_FX(FXV)                       \
+    if (pp) {                                  \
+        DG_STAGE(true, false, FXV, false);     \
+    } else if (tq_part) {                      \
+        DG_STAGE_MF(true, FXV)                 \
+    } else {                                   \
+        DG_STAGE_MF(false, FXV)                \
+    }
     DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, {
         constexpr int EW = 64 / NT;
         const int tx = (g.nx + EW - 1) / EW;
@@ -1861,6 +1900,7 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
         }
     }));
 #undef DG_STAGE_FX
+#undef DG_STAGE_MF
 #undef DG_STAGE
     return hipGetLastError();
 }

@@ -9,6 +9,7 @@
 
 #include "dg_basis.h"
 #include "dg_internal.h"
+#include "dg_mlp.h"
 #include "dg_pp.h"
 
 namespace dgk {
@@ -156,21 +157,6 @@ __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const 
 }
 
 // ------------------------------------------------------------------ learned indicator
-constexpr int kIn = 64, kH = 32;
-constexpr int kW1 = 0, kB1 = kW1 + kH * kIn, kW2 = kB1 + kH, kB2 = kW2 + kH * kH, kW3 = kB2 + kH, kB3 = kW3 + kH;
-constexpr int kNParam = kB3 + 1;  // 3169
-
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ unsigned short f2bf(float x) {
-    // round to nearest even (finite inputs)
-    unsigned int b = __float_as_uint(x);
-    if ((b & 0x7f800000u) == 0x7f800000u) return (unsigned short)(b >> 16);
-    b += 0x7fffu + ((b >> 16) & 1u);
-    return (unsigned short)(b >> 16);
-}
-__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
 // features of every element: f[e][v*16 + m] = u_vm / (|u_v00| + scale_v), bf16
 template <int N, int NV>
@@ -303,93 +289,29 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const unsigned short* __res
     }
 }
 
-// Learned-indicator flags straight from the state (order 4, four variables:
-// 64 features): the same MLP as k_mlp_forward, but each lane builds its B
-// fragments from the modes it loads (K step s = variable s, rows 4g..4g+3 =
-// modes), so no feature array is written or read.  flag[e] = z > zthr.
-__global__ void __launch_bounds__(256) k_mlp_flags(const Geo g, const double* __restrict__ u,
-                                                   const double* __restrict__ scale, const float* __restrict__ par,
-                                                   unsigned char* __restrict__ flag_out, float zthr) {
-    constexpr int NN = 16;
-    __shared__ unsigned short sW1[kH * kIn], sW2[kH * kH];
-    for (int k = threadIdx.x; k < kH * kIn; k += 256) sW1[k] = f2bf(par[kW1 + k]);
-    for (int k = threadIdx.x; k < kH * kH; k += 256) sW2[k] = f2bf(par[kW2 + k]);
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = lane & 15, gq = lane >> 4;
-    bf16x4 a1[2][4], a2[2][2];
+// The network's weights in the per-lane fragment form of dg_mlp.h, from the
+// FP32 parameters (one wavefront), for the stage kernel that forms the flags
+// of the rows it writes.
+__global__ void __launch_bounds__(64) k_mlp_pack(const float* __restrict__ par, void* __restrict__ pack) {
+    const int lane = threadIdx.x;
+    MlpLane w;
+    mlp_lane_from_params(par, lane, w);
+    unsigned long long* fr = (unsigned long long*)pack;
+    float* fv = (float*)(fr + kPackFrag * 64);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s) fr[(t * 4 + s) * 64 + lane] = __builtin_bit_cast(unsigned long long, w.a1[t][s]);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a1[t][s][k] = (short)sW1[(16 * t + i) * kIn + 16 * s + 4 * gq + k];
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) a2[t][s][k] = (short)sW2[(16 * t + i) * kH + 16 * s + 4 * gq + k];
-    }
-    float b1v[2][4], b2v[2][4], w3v[2][4];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
+        for (int s = 0; s < 2; ++s) fr[(8 + t * 2 + s) * 64 + lane] = __builtin_bit_cast(unsigned long long, w.a2[t][s]);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int row = 16 * t + 4 * gq + k;
-            b1v[t][k] = par[kB1 + row];
-            b2v[t][k] = par[kB2 + row];
-            w3v[t][k] = bf2f(f2bf(par[kW3 + row]));
+            fv[(t * 4 + k) * 64 + lane] = w.b1v[t][k];
+            fv[(8 + t * 4 + k) * 64 + lane] = w.b2v[t][k];
+            fv[(16 + t * 4 + k) * 64 + lane] = w.w3v[t][k];
         }
-    const float b3 = par[kB3];
-    const long long E = g.E;
-    const long long ntile = (E + 15) / 16;
-    for (long long tile = (long long)blockIdx.x * 4 + wave; tile < ntile; tile += (long long)gridDim.x * 4) {
-        const long long e = tile * 16 + i;
-        const bool valid = e < E;
-        const long long el = valid ? e : E - 1;  // in-bounds loads on a ragged last tile
-        const unsigned base = tiled_base<4, 4>(g, (int)(el % g.nx), (int)(el / g.nx));
-        f32x4 c1[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) c1[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const double d = fabs(u[base + mode_off<4>(s, 0, 0)]) + scale[s];
-            bf16x4 b;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                // mode m = 4 gq + k = (a, b) with a = gq, b = k
-                const short fv = (short)f2bf((float)(u[base + mode_off<4>(s, gq, k)] / d));
-                b[k] = valid ? fv : (short)0;
-            }
-#pragma unroll
-            for (int t = 0; t < 2; ++t) c1[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[t][s], b, c1[t], 0, 0, 0);
-        }
-        bf16x4 hb[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float zz = c1[t][k] + b1v[t][k];
-                hb[t][k] = (short)f2bf(zz > 0.f ? zz : 0.f);
-            }
-        f32x4 c2[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) c2[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int t = 0; t < 2; ++t) c2[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[t][s], hb[s], c2[t], 0, 0, 0);
-        float part = 0.f;
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float zz = c2[t][k] + b2v[t][k];
-                part += w3v[t][k] * bf2f(f2bf(zz > 0.f ? zz : 0.f));
-            }
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        if (valid && gq == 0) flag_out[e] = (part + b3) > zthr ? 1 : 0;
     }
+    if (lane == 0) fv[kPackVec * 64] = w.b3;
 }
 
 // Backward pass of the BCE-with-logits loss (mean over n, positives weighted
@@ -535,15 +457,12 @@ hipError_t launch_mlp_forward(const unsigned short* x, long long n, const float*
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_flags(const Geo& g, const double* u, const double* scale, const float* par,
-                            unsigned char* flags, float zthr, hipStream_t s) {
-    const long long ntile = (g.E + 15) / 16;
-    long long blocks = (ntile + 3) / 4;
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_mlp_flags, dim3((unsigned)blocks), dim3(256), 0, s, g, u, scale, par, flags, zthr);
+hipError_t launch_mlp_pack(const float* par, void* pack, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(64), 0, s, par, pack);
     return hipGetLastError();
 }
+
+int mlp_pack_bytes() { return kPackBytes; }
 
 int mlp_delta_blocks(long long n) { return (int)((n + 255) / 256); }
 int mlp_nparam() { return kNParam; }
