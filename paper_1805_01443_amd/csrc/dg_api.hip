@@ -51,6 +51,7 @@ struct dg_handle {
     unsigned short* feat = nullptr;  // E * 64 (learned limiter)
     float* mlp = nullptr;            // parameters, Adam m, Adam v (3 * nparam)
     void* mlp_pack = nullptr;        // the weights in per-lane fragment form (learned limiter)
+    unsigned char* pp_ok = nullptr;  // per tile: no positivity scaling needed (limiter + positivity, order 4 adiabatic)
     long long adam_t = 0;
     long long tr_cap = 0;            // training workspace capacity (samples)
     float* tr_ws = nullptr;          // z, h1, h2, dz, d1, d2, loss partials, grad
@@ -227,7 +228,8 @@ void drop_events(dg_handle* h) {
 // launch one stage kernel, bracketed by events while profiling; pp: with the
 // positivity scaling fused (FP64 path)
 hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, const StageCoeffs* sc,
-                 bool pp = false, double* tq_part = nullptr, const dgk::MlpFlags* mf = nullptr) {
+                 bool pp = false, double* tq_part = nullptr, const dgk::MlpFlags* mf = nullptr,
+                 unsigned char* pp_ok = nullptr) {
     hipEvent_t a = nullptr, b = nullptr;
     if (h->prof) {
         hipError_t e = hipEventCreate(&a);
@@ -239,7 +241,7 @@ hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, c
         if (e != hipSuccess) return e;
     }
     hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, h->eqtr, out, sc, h->s)
-                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, tq_part, h->s, mf);
+                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, tq_part, h->s, mf, pp_ok);
     if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
     return e;
 }
@@ -285,14 +287,14 @@ hipError_t limit(dg_handle* h, double* u, bool last) {
     }
     if (lim == DG_LIMITER_MODAL_DECAY)
         return dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, h->cfg.limiter_s0, 0, 1, nullptr, nullptr, nullptr,
-                                    nullptr, pp, nullptr, h->s);
+                                    nullptr, pp, nullptr, h->s, h->pp_ok);
     // the learned indicator's flags of u were formed by the stage kernel that
     // wrote u
     if (e == hipSuccess && cap && h->cap_mlp)
         e = hipMemcpyAsync(h->cap_mlp, h->flags, (size_t)h->E, hipMemcpyDeviceToDevice, h->s);
     if (e == hipSuccess)
         e = dgk::launch_troubled(h->n, h->nvar, h->g, u, h->u0, 0.0, 1, 1, h->flags, nullptr, nullptr, nullptr, pp,
-                                 nullptr, h->s);
+                                 nullptr, h->s, h->pp_ok);
     return e;
 }
 
@@ -360,6 +362,8 @@ void release(dg_handle* h) {
     (void)hipFree(h->mlp);
     (void)hipFree(h->mlp_pack);
     h->mlp_pack = nullptr;
+    (void)hipFree(h->pp_ok);
+    h->pp_ok = nullptr;
     (void)hipFree(h->tr_ws);
     (void)hipFree(h->kbuf);
     h->kbuf = nullptr;
@@ -472,6 +476,8 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
     DG_ALLOC(h->flags, (size_t)h->E);
     DG_ALLOC(h->mlp, sizeof(float) * 3 * (size_t)dgk::mlp_nparam());
     if (cfg->limiter == DG_LIMITER_LEARNED) DG_ALLOC(h->mlp_pack, (size_t)dgk::mlp_pack_bytes());
+    if (cfg->limiter != DG_LIMITER_NONE && cfg->positivity && h->n == 4 && cfg->closure == DG_CLOSURE_ADIABATIC)
+        DG_ALLOC(h->pp_ok, (size_t)dgk::torque_partials(h->g));  // one byte per tile
     butcher_table(cfg->rk, &h->tab);
     if (h->tab.s > 0) DG_ALLOC(h->kbuf, state_bytes * (size_t)h->tab.s);
     if (h->dev) {
@@ -658,11 +664,15 @@ static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, 
                              std::log(th / (1.0f - th))};  // sigmoid(z) > theta  <=>  z > logit(theta)
         mf = &mlpf;
     }
-    DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0], fuse, tqp, mf), "stage 1");
+    // with a troubled-cell limiter and the positivity limiter (order 4,
+    // adiabatic) each stage kernel marks the tiles that need no positivity
+    // scaling, and the pass after the limiter skips them
+    unsigned char* ppk = fuse ? nullptr : h->pp_ok;
+    DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0], fuse, tqp, mf, ppk), "stage 1");
     if (!fuse) DG_HIP(h, limit(h, h->ws1, false), "limiter");
-    DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1], fuse, nullptr, mf), "stage 2");
+    DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1], fuse, nullptr, mf, ppk), "stage 2");
     if (!fuse) DG_HIP(h, limit(h, h->ws2, false), "limiter");
-    DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2], fuse, nullptr, mf), "stage 3");
+    DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2], fuse, nullptr, mf, ppk), "stage 3");
     if (!fuse) DG_HIP(h, limit(h, u_dev, true), "limiter");
     if (h->cfg.damping) {
         DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),

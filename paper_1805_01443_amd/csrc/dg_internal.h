@@ -107,10 +107,12 @@ struct MlpFlags {
 // tq_part (optional, not with pp; a stage whose input u is the state at the
 // stage time): also the torque of eq. (5) on u, one partial per tile
 // (torque_partials doubles), for launch_torque_final; mf (optional, order 4
-// adiabatic, not with pp): also the learned indicator's flags of out
+// adiabatic, not with pp): also the learned indicator's flags of out; pp_ok
+// (optional, order 4 adiabatic, not with pp): per tile, 1 if no element of
+// out needs the positivity scaling (for launch_troubled)
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0,
                         double* out, const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s,
-                        const MlpFlags* mf = nullptr);
+                        const MlpFlags* mf = nullptr, unsigned char* pp_ok = nullptr);
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
 // CFL step per element; per-block minimum into dt_part[block] and a per-block
@@ -154,9 +156,13 @@ int torque_partials(const Geo& g);
 // troubled cells and the learned indicator
 // means of every variable into out[v * E + e] (contiguous), from a state array
 hipError_t launch_means(int n, int nvar, const Geo& g, const double* u, double* out, hipStream_t s);
+// pp_ok (optional, with pp and no changed_out / theta_out): the stage
+// kernel's per-tile marks; elements that minmod changes clear their tile's
+// mark, and the positivity pass skips the tiles still marked
 hipError_t launch_troubled(int n, int nvar, const Geo& g, double* u, const double* u0, double s0, int mode, int apply,
                            const unsigned char* flag_in, unsigned char* flag_out, unsigned char* changed_out,
-                           float* sensor_out, int pp, double* theta_out, hipStream_t s);
+                           float* sensor_out, int pp, double* theta_out, hipStream_t s,
+                           unsigned char* pp_ok = nullptr);
 hipError_t launch_features(int n, int nvar, const Geo& g, const double* u, const double* scale, unsigned short* f,
                            hipStream_t s);
 hipError_t launch_mlp_forward(const unsigned short* x, long long n, const float* par, float* z, float* h1, float* h2,

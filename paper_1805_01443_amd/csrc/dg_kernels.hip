@@ -278,14 +278,20 @@ __device__ __forceinline__ double wave_sum(double s) {
 // element: at order 4 lane k * 16 + s holds modes (k, 0..3) of element slot
 // s, which is the MFMA B-fragment layout of the network (dg_mlp.h), so the
 // features go from the stored rows straight into the fragments.
-template <int N, int CL, bool PP, bool TQ, int FX, bool MF>
+// PP: 0 none; 1 the positivity scaling of Sec. 2.4 on the new rows before
+// the store (fused positivity limiter); 2 only its factors, to mark in
+// pp_ok[tile] a tile whose every element needs no scaling (the positivity
+// pass after a troubled-cell limiter then skips it unless the limiter
+// changed one of its elements).
+template <int N, int CL, int PP, bool TQ, int FX, bool MF>
 __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int tiles_total,
                                                 const double* __restrict__ u, const double* un,
                                                 const double* __restrict__ u0, double* out,
                                                 const StageCoeffs* __restrict__ scp, double* tq_part,
                                                 const void* __restrict__ mlp_pack,
                                                 const double* __restrict__ mlp_scale,
-                                                unsigned char* mlp_flags, float mlp_zthr) {
+                                                unsigned char* mlp_flags, float mlp_zthr,
+                                                unsigned char* pp_ok) {
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
@@ -300,7 +306,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     // the lane permutes (and their smaller LDS slot).
     constexpr bool YL = N >= 4;
     constexpr int NEED = NV * NN + (YL ? 4 : 2) * NV * N;
-    constexpr int SLOT = lds_slot_odd(PP && pp_slot<N, NV>() > NEED ? pp_slot<N, NV>() : NEED);
+    constexpr int SLOT = lds_slot_odd(PP != 0 && pp_slot<N, NV>() > NEED ? pp_slot<N, NV>() : NEED);
     __shared__ double lds[EW * SLOT];
 
     // Lane k * EW + s holds index k of element slot s: the lanes of one k
@@ -733,11 +739,16 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
             for (int b = 0; b < N; ++b) O[v][b] = a1 * U1[v][b] + a2 * R[v][b];
     }
-    if constexpr (PP) {
+    if constexpr (PP != 0) {
         __syncthreads();  // every lane has read Y
         double th1, th2;
         pp_factors<N, NV>(g, S, k, O, g.pp_eps, th1, th2);
-        pp_scale_row<N, NV>(k, th1, th2, O);
+        if constexpr (PP == 1) {
+            pp_scale_row<N, NV>(k, th1, th2, O);
+        } else {
+            const bool ok = __all(!active || (th1 >= 1.0 && th2 >= 1.0));
+            if (lane == 0) pp_ok[tile] = ok ? 1 : 0;
+        }
     }
     if (active) {
 #pragma unroll
@@ -1851,7 +1862,8 @@ hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim, dou
 }
 
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0, double* out,
-                        const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s, const MlpFlags* mf) {
+                        const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s, const MlpFlags* mf,
+                        unsigned char* pp_ok) {
     // arrays that a launch does not read still get a valid base (buffer
     // resources are never built on a null pointer)
     if (!un) un = u;
@@ -1861,25 +1873,32 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
     if (pp && tq_part) return hipErrorInvalidValue;
     if (mf && (pp || n != 4 || g.closure != CL_ADI || !mf->pack || !mf->scale || !mf->flags))
         return hipErrorInvalidValue;
+    if (pp_ok && (pp || n != 4 || g.closure != CL_ADI)) return hipErrorInvalidValue;
     const void* mpack = mf ? mf->pack : nullptr;
     const double* mscale = mf ? mf->scale : nullptr;
     unsigned char* mflags = mf ? mf->flags : nullptr;
     const float mzthr = mf ? mf->zthr : 0.f;
 #define DG_STAGE(PPV, TQV, FXV, MFV)                                                                             \
     hipLaunchKernelGGL((k_stage_c<NT, CT, PPV, TQV, FXV, MFV>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, \
-                       out, sc, tq_part, mpack, mscale, mflags, mzthr)
+                       out, sc, tq_part, mpack, mscale, mflags, mzthr, pp_ok)
 #define DG_STAGE_MF(TQV, FXV)                                      \
     if constexpr (NT == 4 && CT == CL_ADI) {                       \
-        if (mf)                                                    \
-            DG_STAGE(false, TQV, FXV, true);                       \
-        else                                                       \
-            DG_STAGE(false, TQV, FXV, false);                      \
+        if (pp_ok) {                                               \
+            if (mf)                                                \
+                DG_STAGE(2, TQV, FXV, true);                       \
+            else                                                   \
+                DG_STAGE(2, TQV, FXV, false);                      \
+        } else if (mf) {                                           \
+            DG_STAGE(0, TQV, FXV, true);                           \
+        } else {                                                   \
+            DG_STAGE(0, TQV, FXV, false);                          \
+        }                                                          \
     } else {                                                       \
-        DG_STAGE(false, TQV, FXV, false);                          \
+        DG_STAGE(0, TQV, FXV, false);                              \
     }
 #define DG_STAGE_FX(FXV)                       \
     if (pp) {                                  \
-        DG_STAGE(true, false, FXV, false);     \
+        DG_STAGE(1, false, FXV, false);        \
     } else if (tq_part) {                      \
         DG_STAGE_MF(true, FXV)                 \
     } else {                                   \

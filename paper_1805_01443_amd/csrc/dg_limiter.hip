@@ -43,7 +43,7 @@ __device__ __forceinline__ double nb_mean(const Geo& g, const double* __restrict
 // lane of a changed element scales and stores its row.
 template <int N, int NV>
 __global__ void __launch_bounds__(64) k_pp_c(const Geo g, double* u, double e0, unsigned char* changed_out,
-                                             double* theta_out) {
+                                             double* theta_out, const unsigned char* __restrict__ pp_ok) {
     constexpr int EW = 64 / N;
     constexpr int SLOT = pp_slot<N, NV>() | 1;  // odd: the slots of one k on distinct banks
     __shared__ double lds[EW * SLOT];
@@ -54,6 +54,9 @@ __global__ void __launch_bounds__(64) k_pp_c(const Geo g, double* u, double e0, 
     const int k = own ? lane / EW : lane - N * EW;
     const int sl = own ? lane - k * EW : EW;
     const int tile = blockIdx.x;
+    // a tile that the stage kernel found admissible and the troubled-cell
+    // limiter left alone needs no scaling: the whole block leaves at once
+    if (pp_ok && pp_ok[tile]) return;
     const int j = tile / g.tiles_x;
     const int i0 = (tile - j * g.tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
@@ -101,7 +104,7 @@ template <int N, int NV>
 __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const double* __restrict__ u0, double s0,
                                                   int mode, int apply, const unsigned char* __restrict__ flag_in,
                                                   unsigned char* flag_out, unsigned char* changed_out,
-                                                  float* sensor_out, double* theta_out) {
+                                                  float* sensor_out, double* theta_out, unsigned char* pp_ok) {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= g.E) return;
     const int i = (int)(e % g.nx), j = (int)(e / g.nx);
@@ -154,6 +157,8 @@ __global__ void __launch_bounds__(256) k_troubled(const Geo g, double* u, const 
         }
     }
     if (changed_out) changed_out[e] = changed ? 1 : 0;
+    // an element changed here needs the positivity check again
+    if (pp_ok && changed && apply) pp_ok[j * g.tiles_x + i / (64 / N)] = 0;
 }
 
 // ------------------------------------------------------------------ learned indicator
@@ -423,19 +428,21 @@ __global__ void __launch_bounds__(256) k_mlp_adam(const float* __restrict__ grad
 
 hipError_t launch_troubled(int n, int nvar, const Geo& g, double* u, const double* u0, double s0, int mode, int apply,
                            const unsigned char* flag_in, unsigned char* flag_out, unsigned char* changed_out,
-                           float* sensor_out, int pp, double* theta_out, hipStream_t s) {
+                           float* sensor_out, int pp, double* theta_out, hipStream_t s, unsigned char* pp_ok) {
+    // the tile marks are only used where no per-element output is asked for
+    if (changed_out || theta_out || !pp) pp_ok = nullptr;
     const int blocks = (int)((g.E + 255) / 256);
     // flags and minmod (skipped when there are no flags), then the positivity
     // scaling with N lanes per element
     if (mode != 2 || !pp) {
         DGL_DISPATCH(n, nvar, hipLaunchKernelGGL((k_troubled<NT, VT>), dim3(blocks), dim3(256), 0, s, g, u, u0,
                                                  s0, mode, apply, flag_in, flag_out, pp ? nullptr : changed_out,
-                                                 sensor_out, nullptr));
+                                                 sensor_out, nullptr, pp_ok));
     }
     if (pp && apply) {
         const int tiles = g.tiles_x * g.ny;
         DGL_DISPATCH(n, nvar, hipLaunchKernelGGL((k_pp_c<NT, VT>), dim3(tiles), dim3(64), 0, s, g, u, g.pp_eps,
-                                                 changed_out, theta_out));
+                                                 changed_out, theta_out, pp_ok));
     }
     return hipGetLastError();
 }
