@@ -52,6 +52,7 @@ struct dg_handle {
     float* mlp = nullptr;            // parameters, Adam m, Adam v (3 * nparam)
     void* mlp_pack = nullptr;        // the weights in per-lane fragment form (learned limiter)
     unsigned char* pp_ok = nullptr;  // per tile: no positivity scaling needed (limiter + positivity, order 4 adiabatic)
+    unsigned char* undamped = nullptr;  // per tile: not touched by the damping (positivity + damping)
     long long adam_t = 0;
     long long tr_cap = 0;            // training workspace capacity (samples)
     float* tr_ws = nullptr;          // z, h1, h2, dz, d1, d2, loss partials, grad
@@ -364,6 +365,8 @@ void release(dg_handle* h) {
     h->mlp_pack = nullptr;
     (void)hipFree(h->pp_ok);
     h->pp_ok = nullptr;
+    (void)hipFree(h->undamped);
+    h->undamped = nullptr;
     (void)hipFree(h->tr_ws);
     (void)hipFree(h->kbuf);
     h->kbuf = nullptr;
@@ -508,6 +511,19 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
                 if (any) list.push_back(j * h->g.tiles_x + t);
             }
         h->ndamp = (int)list.size();
+        if (cfg->positivity) {
+            // the positivity pass after the damping looks at the damped tiles
+            // only: every other tile left the last stage admissible and the
+            // damping did not touch it
+            std::vector<unsigned char> und((size_t)dgk::torque_partials(h->g), 1);
+            for (int tl : list) und[tl] = 0;
+            DG_ALLOC(h->undamped, und.size());
+            e = hipMemcpy(h->undamped, und.data(), und.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(prim_dev);
+                return bail(hip_fail(h, e, "undamped tile marks upload"));
+            }
+        }
         if (h->ndamp) {
             DG_ALLOC(h->damp_list, sizeof(int) * list.size());
             DG_ALLOC(h->damp_q0, sizeof(double) * list.size() * (size_t)h->nvar * h->n * h->n * h->g.ew);
@@ -677,10 +693,11 @@ static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, 
     if (h->cfg.damping) {
         DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
                "damping");
-        // the damped state gets the positivity scaling too
+        // the damped state gets the positivity scaling too (damped tiles
+        // only: the pass read-only skips the tiles marked undamped)
         if (h->cfg.positivity)
             DG_HIP(h, dgk::launch_troubled(h->n, h->nvar, h->g, u_dev, nullptr, 0.0, 2, 1, nullptr, nullptr, nullptr,
-                                           nullptr, 1, nullptr, h->s),
+                                           nullptr, 1, nullptr, h->s, h->undamped),
                    "positivity after damping");
     }
     return DG_OK;
