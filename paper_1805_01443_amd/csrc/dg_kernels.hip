@@ -246,6 +246,64 @@ __device__ __forceinline__ double wave_sum(double s) {
     return s;
 }
 
+// LDS layout of an element slot of the stage kernel.  A 64-lane access of
+// single doubles is served 32 lanes at a time over 64 banks of 4 bytes, so a
+// half-wave meets no bank twice when its 32 doubles fall on 32 different
+// residues mod 32.  Lane k * EW + s (element slot s, index k) addresses
+// s * SLOT + k * c + const, with c the access's k-stride; at order 5 with three
+// variables (EW = 12) every stride used below is 4 mod 32 and SLOT is 3 mod 8,
+// which makes the residue SLOT * (s + EW * k) mod 32: 32 different ones for
+// 32 consecutive lanes.  The plain layout (C as [v][a][r], the collapses as
+// [kind][v][a]) meets its banks twice per half-wave at order 5; at order 4
+// the counters show no conflicts in it (and more with the order-5 scheme
+// carried over), lower orders gather their y collapses by lane permute, and
+// order 5 with four variables would lose a wave per SIMD to registers in the
+// new layout: all of these keep the plain one.
+//   C (later X, then Y): entry (v, a, r) at v * CV + a * CA + r * CR, written
+//   by lane a and read by lane r (X and Y: written by lane r, read by lane a);
+//   the y collapses [kind][v] of row a (later the south/north fluxes
+//   [edge][v] at point a): entry (t, a) at TOFF + t * TT + a * TA.
+template <int N, int NV>
+struct StageLds {
+    static constexpr bool C5 = N == 5 && NV == 3;
+    static constexpr int CV = C5 ? 1 : N * N;
+    static constexpr int CR = C5 ? 4 : 1;
+    static constexpr int CA = C5 ? 36 : N;
+    static constexpr int TOFF = C5 ? 20 : NV * N * N;
+    static constexpr int TT = C5 ? 1 : N;
+    static constexpr int TA = C5 ? CA : 1;
+    static constexpr int NEED = C5 ? CA * N : NV * N * N + (N >= 4 ? 4 : 2) * NV * N;
+    static constexpr int slot(int need) {
+        int s = need;
+        if (C5)
+            while (s % 8 != 3) ++s;
+        else
+            s |= 1;
+        return s;
+    }
+    static constexpr int ci(int v, int a, int r) { return v * CV + a * CA + r * CR; }
+    static constexpr int ti(int t, int a) { return TOFF + t * TT + a * TA; }
+    // every entry of C and of the collapses inside the slot, no two alike
+    static constexpr bool fits() {
+        bool used[NEED] = {};
+        for (int v = 0; v < NV; ++v)
+            for (int a = 0; a < N; ++a)
+                for (int r = 0; r < N; ++r) {
+                    const int x = ci(v, a, r);
+                    if (x < 0 || x >= NEED || used[x]) return false;
+                    used[x] = true;
+                }
+        for (int t = 0; t < (N >= 4 ? 4 : 2) * NV; ++t)
+            for (int a = 0; a < N; ++a) {
+                const int x = ti(t, a);
+                if (x < 0 || x >= NEED || used[x]) return false;
+                used[x] = true;
+            }
+        return true;
+    }
+    static_assert(fits(), "stage kernel LDS slot layout");
+};
+
 // out = a0 u^n + a1 u + a2 L(u, t), with the N lanes of an element sharing
 // its tensor-product contractions.  Lane (s, k) = lane k * EW + s: element
 // slot s of the wave (EW = 64 / N consecutive elements of one row), index k.
@@ -305,27 +363,34 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     // operations in flight); lower orders run more waves per SIMD and keep
     // the lane permutes (and their smaller LDS slot).
     constexpr bool YL = N >= 4;
-    constexpr int NEED = NV * NN + (YL ? 4 : 2) * NV * N;
-    constexpr int SLOT = lds_slot_odd(PP != 0 && pp_slot<N, NV>() > NEED ? pp_slot<N, NV>() : NEED);
-    __shared__ double lds[EW * SLOT];
+    using LY = StageLds<N, NV>;
+    constexpr int SLOT = LY::slot(PP != 0 && pp_slot<N, NV>() > LY::NEED ? pp_slot<N, NV>() : LY::NEED);
+    // after the slots (orders 4 and 5): the x collapses of the two loaded
+    // neighbour columns (west of the first slot, east of the last element),
+    // [side][v][a]; lower orders gather them by lane permute
+    __shared__ double lds[EW * SLOT + (YL ? 2 * NV * N : 0)];
 
     // Lane k * EW + s holds index k of element slot s: the lanes of one k
     // address consecutive doubles of the tile (a row of the EW elements is one
     // contiguous run), so every row load and store is contiguous in lane
-    // order.  Lanes beyond N * EW shadow slot 0's element (same i, j and k):
-    // they compute and store exactly the values of lane (0, k) and share slot 0.
+    // order.  Lanes beyond N * EW mirror another lane (same slot, element and
+    // k): lane - 32 where the slot layout keeps a half-wave on 32 different
+    // banks (order 5, three variables), else lane (0, k).  They compute that
+    // lane's values, write the same values to its slot and store nothing.
+    // Slots past the row end work on the row's first element and store
+    // nothing either.
     const int lane = threadIdx.x;
     const bool own = lane < N * EW;
-    const int k = own ? lane / EW : lane - N * EW;
-    const int sl = own ? lane - k * EW : EW;
+    const int k = own ? lane / EW : LY::C5 ? (lane - 32) / EW : lane - N * EW;
+    const int sl = own ? lane - k * EW : EW;  // EW: a mirror lane
+    const int e0 = own ? sl : LY::C5 ? lane - 32 - k * EW : 0;  // the element's lanes are e0 + a * EW
     const int tile = remap_tile(blockIdx.x, tiles_total);
     const int j = tile / tiles_x;
     const int i0 = (tile - j * tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
-    const int i = active ? i0 + sl : i0;  // idle lanes shadow a valid element and store nothing
-    const int e0 = own ? sl : 0;          // the element's lanes are e0 + a * EW
+    const int i = LY::C5 ? (i0 + e0 < g.nx ? i0 + e0 : i0) : active ? i0 + sl : i0;
     double* S = lds + e0 * SLOT;
-    const int me = e0 + k * EW;           // this lane, or the slot-0 lane an idle lane shadows
+    const int me = e0 + k * EW;  // this lane, or the lane a mirror lane follows
     // The x neighbours inside the wave hand over their x collapses by lane
     // permute; only the first slot (west) and the last slot or the end of the
     // row (east) read the neighbour's column from memory.
@@ -399,7 +464,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             double c = 0.0;
 #pragma unroll
             for (int b = 0; b < N; ++b) c += Ua[v][b] * B.phi[b][r];
-            S[(v * N + k) * N + r] = c;
+            S[LY::ci(v, k, r)] = c;
         }
         // the exterior collapses take the neighbour's far side.  phi_m(-1) =
         // (-1)^m phi_m(1): even and odd partial sums give either side.
@@ -473,16 +538,28 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             Tr[v] = fr ? e + o : Tr[v];
         }
     }
+    // the loaded neighbour columns' collapses for the other lanes of the
+    // first and the last element (one of each per tile: slot 0, and the
+    // element at the last slot or at the row end; a slot past the row end
+    // writes nothing)
+    if constexpr (YL) {
+        double* XE = lds + EW * SLOT;
+        const bool wlast = ge && active;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (gw) XE[v * N + k] = Tl[v];
+            if (wlast) XE[(NV + v) * N + k] = Tr[v];
+        }
+    }
     // the y collapses of row k (own south / north, exterior south / north)
     // for the element's other lanes: [kind][v][a] after C
     if constexpr (YL) {
-        double* TT = S + NV * NN;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            TT[(0 * NV + v) * N + k] = Tm[v];
-            TT[(1 * NV + v) * N + k] = Tp[v];
-            TT[(2 * NV + v) * N + k] = Tb[v];
-            TT[(3 * NV + v) * N + k] = Tt[v];
+            S[LY::ti(0 * NV + v, k)] = Tm[v];
+            S[LY::ti(1 * NV + v, k)] = Tp[v];
+            S[LY::ti(2 * NV + v, k)] = Tb[v];
+            S[LY::ti(3 * NV + v, k)] = Tt[v];
         }
     }
     __syncthreads();
@@ -497,13 +574,13 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int a = 0; a < N; ++a) Cc[v][a] = S[(v * N + a) * N + k];
+        for (int a = 0; a < N; ++a) Cc[v][a] = S[LY::ci(v, a, k)];
     // edge traces at point k and their fluxes (outward normals); the y
     // collapses of the element's rows come from LDS (TT, YL) or from lane
-    // e0 + a * EW, the x collapses of a loaded neighbour column from lane
-    // e0 + a * EW
-    const double* TT = S + NV * NN;
-    double* H = S + NV * NN;  // south / north fluxes [edge][v][point], written over TT once it is read
+    // e0 + a * EW, the x collapses of a loaded neighbour column from LDS (YL)
+    // or from lane e0 + a * EW
+    // the south / north fluxes [edge][v][point] go over the y collapses once
+    // both fluxes of the lane are formed
     double X[NV][N], Y[NV][N];
     {
         double Ui[NV], Uo[NV], hw[NV], he[NV], hs[NV];
@@ -511,6 +588,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         // trace at eta_k (lane permute) inside the wave, and the contraction of
         // the loaded column's collapses at the first and last slot
         double Ei[NV], Wx[NV], Ex[NV];
+        const double* XE = lds + EW * SLOT;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             double w = 0.0, e = 0.0, tl = 0.0, tr = 0.0;
@@ -518,8 +596,13 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             for (int a = 0; a < N; ++a) {
                 w += B.pm[a] * Cc[v][a];
                 e += B.pp[a] * Cc[v][a];
-                tl += phk[a] * __shfl(Tl[v], e0 + a * EW);
-                tr += phk[a] * __shfl(Tr[v], e0 + a * EW);
+                if constexpr (YL) {
+                    tl += phk[a] * XE[v * N + a];
+                    tr += phk[a] * XE[(NV + v) * N + a];
+                } else {
+                    tl += phk[a] * __shfl(Tl[v], e0 + a * EW);
+                    tr += phk[a] * __shfl(Tr[v], e0 + a * EW);
+                }
             }
             const double from_w = __shfl(e, me >= 1 ? me - 1 : me);
             const double from_e = __shfl(w, me + 1 < 64 ? me + 1 : me);
@@ -551,8 +634,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 if constexpr (YL) {
-                    si += phk[a] * TT[(0 * NV + v) * N + a];
-                    so += phk[a] * TT[(2 * NV + v) * N + a];
+                    si += phk[a] * S[LY::ti(0 * NV + v, a)];
+                    so += phk[a] * S[LY::ti(2 * NV + v, a)];
                 } else {
                     si += phk[a] * __shfl(Tm[v], e0 + a * EW);
                     so += phk[a] * __shfl(Tb[v], e0 + a * EW);
@@ -564,7 +647,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         edge_flux<CL, FX, 1, -1>(g, Ui, Uo, xk, yc - 0.5 * g.dy, hs);
         if constexpr (!YL) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) H[(0 * NV + v) * N + k] = hs[v];
+            for (int v = 0; v < NV; ++v) S[LY::ti(0 * NV + v, k)] = hs[v];
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -572,8 +655,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 if constexpr (YL) {
-                    si += phk[a] * TT[(1 * NV + v) * N + a];
-                    so += phk[a] * TT[(3 * NV + v) * N + a];
+                    si += phk[a] * S[LY::ti(1 * NV + v, a)];
+                    so += phk[a] * S[LY::ti(3 * NV + v, a)];
                 } else {
                     si += phk[a] * __shfl(Tp[v], e0 + a * EW);
                     so += phk[a] * __shfl(Tt[v], e0 + a * EW);
@@ -585,8 +668,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         edge_flux<CL, FX, 1, 1>(g, Ui, Uo, xk, yc + 0.5 * g.dy, hn);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            if constexpr (YL) H[(0 * NV + v) * N + k] = hs[v];
-            H[(1 * NV + v) * N + k] = hn[v];
+            if constexpr (YL) S[LY::ti(0 * NV + v, k)] = hs[v];
+            S[LY::ti(1 * NV + v, k)] = hn[v];
         }
     }
     const double wk = pick<N>(B.wh, k) * g.dx * g.dy;  // torque: node mass factor of Gauss row k
@@ -663,7 +746,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int a = 0; a < N; ++a) S[((v * N + k) * N + a)] = X[v][a];
+        for (int a = 0; a < N; ++a) S[LY::ci(v, k, a)] = X[v][a];
     __syncthreads();
 
     // ---- phase 3: k = mode row a
@@ -681,14 +764,14 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         double glb = 0.0, glt = 0.0;
 #pragma unroll
         for (int q = 0; q < N; ++q) {
-            glb += wrow[q] * H[(0 * NV + v) * N + q];
-            glt += wrow[q] * H[(1 * NV + v) * N + q];
+            glb += wrow[q] * S[LY::ti(0 * NV + v, q)];
+            glt += wrow[q] * S[LY::ti(1 * NV + v, q)];
         }
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             double acc = 0.0;
 #pragma unroll
-            for (int r = 0; r < N; ++r) acc += B.wphi[b][r] * S[((v * N + r) * N + k)];
+            for (int r = 0; r < N; ++r) acc += B.wphi[b][r] * S[LY::ci(v, r, k)];
             R[v][b] = acc - g.idy * (B.pm[b] * glb + B.pp[b] * glt);
         }
     }
@@ -696,7 +779,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int a = 0; a < N; ++a) S[((v * N + k) * N + a)] = Y[v][a];
+        for (int a = 0; a < N; ++a) S[LY::ci(v, k, a)] = Y[v][a];
     __syncthreads();
     // the row's u^n, loaded before any store (out may alias u^n, so a load
     // after a store could not be moved ahead of it).  With three variables
@@ -721,7 +804,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         for (int b = 0; b < N; ++b) {
             double acc = 0.0;
 #pragma unroll
-            for (int r = 0; r < N; ++r) acc += B.wdphi[b][r] * S[((v * N + r) * N + k)];
+            for (int r = 0; r < N; ++r) acc += B.wdphi[b][r] * S[LY::ci(v, r, k)];
             R[v][b] += acc;
         }
     // the new row; with PP the positivity scaling of Sec. 2.4 on it before
@@ -763,8 +846,8 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         bf16x4 bfr[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            // the element's mean is mode (0, 0), held by its lane k = 0 (lane sl)
-            const double d = fabs(__shfl(O[v][0], sl)) + mlp_scale[v];
+            // the element's mean is mode (0, 0), held by its lane k = 0 (lane e0)
+            const double d = fabs(__shfl(O[v][0], e0)) + mlp_scale[v];
 #pragma unroll
             for (int b = 0; b < 4; ++b) bfr[v][b] = active ? (short)f2bf((float)(O[v][b] / d)) : (short)0;
         }
