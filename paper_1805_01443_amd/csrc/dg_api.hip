@@ -44,6 +44,7 @@ struct dg_handle {
     int ndamp = 0;
     double* damp_q0 = nullptr;  // damping targets at the Gauss nodes of the listed tiles
     double* tq_part = nullptr;  // torque partials, one per tile
+    bool rev = false;           // tile direction of the next stage launch (alternates)
     // troubled cells / learned indicator
     double* scale_dev = nullptr;     // feature scales (nvar)
     double scale_host[4] = {0, 0, 0, 0};
@@ -241,8 +242,11 @@ hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, c
         e = hipEventRecord(a, h->s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, h->eqtr, out, sc, h->s)
-                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, tq_part, h->s, mf, pp_ok);
+    // each launch walks the tiles in the direction opposite to the last one
+    const bool rev = h->rev;
+    h->rev = !h->rev;
+    hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, h->eqtr, out, sc, h->s, rev)
+                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, tq_part, h->s, mf, pp_ok, rev);
     if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
     return e;
 }

