@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -514,6 +515,15 @@ int dg_init(const dg_config* cfg, const double* prim_nodes_host, double* u0_dev,
                 }
                 if (any) list.push_back(j * h->g.tiles_x + t);
             }
+        // ordered by the tile's place in its XCD band (the stage kernels give
+        // XCD x the x-th eighth of the tiles): the damping then follows the
+        // last stage's order, or runs against it (it starts where that stage
+        // ended, on the tiles it wrote last)
+        {
+            const long long tot = (long long)h->g.tiles_x * cfg->ny;
+            const long long per = tot % 8 == 0 ? tot / 8 : tot;
+            std::stable_sort(list.begin(), list.end(), [per](int a, int b) { return a % per < b % per; });
+        }
         h->ndamp = (int)list.size();
         if (cfg->positivity) {
             // the positivity pass after the damping looks at the damped tiles
@@ -654,7 +664,8 @@ static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, 
         }
         DG_HIP(h, dgk::launch_rk_combine(u_dev, k, S, &sb->comb[0][0], u_dev, N, h->s), "update");
         if (h->cfg.damping)
-            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
+            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s,
+                                       h->rev),
                    "damping");
         return DG_OK;
     }
@@ -664,7 +675,8 @@ static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, 
         DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0], false, tqp), "stage 1");
         DG_HIP(h, stage(h, h->ws1, u_dev, u_dev, &sb->st[1]), "stage 2");
         if (h->cfg.damping)
-            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
+            DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s,
+                                       h->rev),
                    "damping");
         return DG_OK;
     }
@@ -695,7 +707,8 @@ static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, 
     DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2], fuse, nullptr, mf, ppk), "stage 3");
     if (!fuse) DG_HIP(h, limit(h, u_dev, true), "limiter");
     if (h->cfg.damping) {
-        DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s),
+        DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s,
+                                       h->rev),
                "damping");
         // the damped state gets the positivity scaling too (damped tiles
         // only: the pass read-only skips the tiles marked undamped)

@@ -136,8 +136,9 @@ hipError_t launch_step_begin(const Geo& g, StepBlock* sb, const double* dt_part,
 // damping targets of the listed tiles from u0 (once), q0: nlist NV n n EW doubles
 hipError_t launch_damp_prep(int n, const Geo& g, const double* u0, const int* list, int nlist, double* q0,
                             hipStream_t s);
+// rev: the list from its end
 hipError_t launch_damp(int n, const Geo& g, double* u, const double* q0, const double* eq, const int* list,
-                       int nlist, const StageCoeffs* sc, hipStream_t s);
+                       int nlist, const StageCoeffs* sc, hipStream_t s, bool rev = false);
 // torque of eq. (5): one partial per tile into partials (torque_partials
 // doubles), then their sum in a fixed order into *out
 hipError_t launch_torque(int n, const Geo& g, double t, const double* t_dev, const double* u, const double* eq,

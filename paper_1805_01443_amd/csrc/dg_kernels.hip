@@ -1678,7 +1678,7 @@ __global__ void __launch_bounds__(64) k_damp_prep(const Geo g, const double* __r
 template <int N, int CL>
 __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const double* __restrict__ q0,
                                                const double* __restrict__ eq, const int* __restrict__ list, int nlist,
-                                               const StageCoeffs* __restrict__ scp) {
+                                               const StageCoeffs* __restrict__ scp, int rev) {
     constexpr BasisTab B = make_basis(N);
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
@@ -1692,7 +1692,10 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
     const bool own = lane < N * EW;
     const int k = own ? lane / EW : lane - N * EW;
     const int sl = own ? lane - k * EW : EW;
-    const int tile = list[blockIdx.x];
+    // rev: the list from its end (the list is ordered by the tile's place in
+    // its XCD band; the damping starts where the last stage ended)
+    const int li = rev ? nlist - 1 - (int)blockIdx.x : (int)blockIdx.x;
+    const int tile = list[li];
     const int j = tile / g.tiles_x;
     const int i0 = (tile - j * g.tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
@@ -1705,7 +1708,7 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
 
     // the targets of Gauss row k (loaded first, used in the second phase)
     const unsigned qs = (unsigned)(N * EW);
-    const double* qb = q0 + (size_t)blockIdx.x * NV * N * qs + k * EW + (own ? sl : 0);
+    const double* qb = q0 + (size_t)li * NV * N * qs + k * EW + (own ? sl : 0);
     double Tg[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -2080,10 +2083,10 @@ hipError_t launch_damp_prep(int n, const Geo& g, const double* u0, const int* li
 }
 
 hipError_t launch_damp(int n, const Geo& g, double* u, const double* q0, const double* eq, const int* list,
-                       int nlist, const StageCoeffs* sc, hipStream_t s) {
+                       int nlist, const StageCoeffs* sc, hipStream_t s, bool rev) {
     if (nlist <= 0) return hipSuccess;
     DG_DISPATCH_CL(g.closure, DG_DISPATCH_N(n, hipLaunchKernelGGL((k_damp_c<NT, CT>), dim3(nlist), dim3(64), 0, s, g,
-                                                                  u, q0, eq, list, nlist, sc)));
+                                                                  u, q0, eq, list, nlist, sc, rev ? 1 : 0)));
     return hipGetLastError();
 }
 
