@@ -165,8 +165,9 @@ int dg_torque(dg_handle *h, double t, const double *t_dev, const double *u_dev, 
  * step of dg_rk_step (Algorithm 1): the same torque bits and the same state.
  * Sec. 5.2 records the torque every step; here the first stage kernel forms it
  * from the node densities and planet offsets it evaluates anyway (one partial
- * per tile, summed in the same fixed order as dg_torque), which saves the
- * torque kernel's read of the density.  The deviation form, and the positivity
+ * per tile), and one more block of the last stage launch adds the partials up
+ * in the same fixed order as dg_torque; this saves the torque kernel's read
+ * of the density and the launch of the final sum.  The deviation form, and the positivity
  * limiter without a troubled-cell limiter (its scaling fused into the stage
  * kernels), run the two calls one after the other.  After the last step, dg_torque gives the torque of the
  * final state.  torque_dev: device double.  Errors as for dg_rk_step. */

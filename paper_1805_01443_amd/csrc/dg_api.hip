@@ -232,7 +232,7 @@ void drop_events(dg_handle* h) {
 // positivity scaling fused (FP64 path)
 hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, const StageCoeffs* sc,
                  bool pp = false, double* tq_part = nullptr, const dgk::MlpFlags* mf = nullptr,
-                 unsigned char* pp_ok = nullptr) {
+                 unsigned char* pp_ok = nullptr, double* tq_out = nullptr) {
     hipEvent_t a = nullptr, b = nullptr;
     if (h->prof) {
         hipError_t e = hipEventCreate(&a);
@@ -247,7 +247,8 @@ hipError_t stage(dg_handle* h, const double* u, const double* un, double* out, c
     const bool rev = h->rev;
     h->rev = !h->rev;
     hipError_t e = h->dev ? dgk::launch_stage_dev(h->n, h->g, u, un, h->du0, h->leq, h->eqtr, out, sc, h->s, rev)
-                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, tq_part, h->s, mf, pp_ok, rev);
+                          : dgk::launch_stage(h->n, h->g, u, un, h->u0, out, sc, pp, tq_part, h->s, mf, pp_ok, rev,
+                                              tq_out ? h->tq_part : nullptr, tq_out);
     if (e == hipSuccess && h->prof) e = hipEventRecord(b, h->s);
     return e;
 }
@@ -636,9 +637,12 @@ int dg_rhs(dg_handle* h, double t, const double* u_dev, double* rhs_dev) {
     return DG_OK;
 }
 
-// One step (Algorithm 1); with tq (FP64 form) the first stage, whose input is
-// u^n at t^n, also forms the torque partials of u^n (h->tq_part).
-static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, double* dt_used_dev, bool tq) {
+// One step (Algorithm 1); with tq_out (FP64 form) the first stage, whose
+// input is u^n at t^n, also forms the torque partials of u^n (h->tq_part),
+// and the last stage adds them up into *tq_out.
+static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, double* dt_used_dev,
+                   double* tq_out) {
+    const bool tq = tq_out != nullptr;
     if (!h) return fail(nullptr, DG_EINVAL, "NULL handle");
     if (!u_dev || !t_dev) return fail(h, DG_EINVAL, "u_dev and t_dev are required");
     if (!(dt_fixed == dt_fixed)) return fail(h, DG_EINVAL, "dt_fixed is NaN");
@@ -656,7 +660,9 @@ static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, 
                                                          dt_fixed, dt_used_dev, h->s), "step begin");
         for (int i = 0; i < S; ++i) {
             const double* y = i == 0 ? u_dev : h->ws1;
-            DG_HIP(h, stage(h, y, nullptr, h->kbuf + (size_t)i * (size_t)N, &sb->st[i], false, i == 0 ? tqp : nullptr),
+            const bool last = i + 1 == S;
+            DG_HIP(h, stage(h, y, nullptr, h->kbuf + (size_t)i * (size_t)N, &sb->st[i], false, i == 0 ? tqp : nullptr,
+                            nullptr, nullptr, last && i > 0 ? tq_out : nullptr),
                    "stage");
             if (i + 1 < S) {
                 DG_HIP(h, dgk::launch_rk_combine(u_dev, k, i + 1, &sb->comb[i + 1][0], h->ws1, N, h->s), "stage state");
@@ -673,7 +679,7 @@ static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, 
         DG_HIP(h, dgk::launch_step_begin(h->g, sb, h->dt_part, h->bad_part, h->dt_blocks, t_dev, dt_fixed,
                                                    dt_used_dev, 2, h->s), "step begin");
         DG_HIP(h, stage(h, u_dev, nullptr, h->ws1, &sb->st[0], false, tqp), "stage 1");
-        DG_HIP(h, stage(h, h->ws1, u_dev, u_dev, &sb->st[1]), "stage 2");
+        DG_HIP(h, stage(h, h->ws1, u_dev, u_dev, &sb->st[1], false, nullptr, nullptr, nullptr, tq_out), "stage 2");
         if (h->cfg.damping)
             DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s,
                                        h->rev),
@@ -704,7 +710,7 @@ static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, 
     if (!fuse) DG_HIP(h, limit(h, h->ws1, false), "limiter");
     DG_HIP(h, stage(h, h->ws1, u_dev, h->ws2, &sb->st[1], fuse, nullptr, mf, ppk), "stage 2");
     if (!fuse) DG_HIP(h, limit(h, h->ws2, false), "limiter");
-    DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2], fuse, nullptr, mf, ppk), "stage 3");
+    DG_HIP(h, stage(h, h->ws2, u_dev, u_dev, &sb->st[2], fuse, nullptr, mf, ppk, tq_out), "stage 3");
     if (!fuse) DG_HIP(h, limit(h, u_dev, true), "limiter");
     if (h->cfg.damping) {
         DG_HIP(h, dgk::launch_damp(h->n, h->g, u_dev, h->damp_q0, h->eq, h->damp_list, h->ndamp, &sb->st[0], h->s,
@@ -721,7 +727,7 @@ static int rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, 
 }
 
 int dg_rk_step(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, double* dt_used_dev) {
-    return rk_step(h, u_dev, t_dev, dt_fixed, dt_used_dev, false);
+    return rk_step(h, u_dev, t_dev, dt_fixed, dt_used_dev, nullptr);
 }
 
 int dg_rk_step_torque(dg_handle* h, double* u_dev, double* t_dev, double dt_fixed, double* dt_used_dev,
@@ -733,11 +739,12 @@ int dg_rk_step_torque(dg_handle* h, double* u_dev, double* t_dev, double dt_fixe
     // there the two calls run one after the other
     if (h->dev || (h->cfg.positivity && h->cfg.limiter == DG_LIMITER_NONE)) {
         const int rc = dg_torque(h, 0.0, t_dev, u_dev, torque_dev);
-        return rc != DG_OK ? rc : rk_step(h, u_dev, t_dev, dt_fixed, dt_used_dev, false);
+        return rc != DG_OK ? rc : rk_step(h, u_dev, t_dev, dt_fixed, dt_used_dev, nullptr);
     }
-    const int rc = rk_step(h, u_dev, t_dev, dt_fixed, dt_used_dev, true);
+    const int rc = rk_step(h, u_dev, t_dev, dt_fixed, dt_used_dev, torque_dev);
     if (rc != DG_OK) return rc;
-    DG_HIP(h, dgk::launch_torque_final(h->g, h->tq_part, torque_dev, h->s), "torque sum");
+    // a one-stage Butcher table has no later stage to add the partials up
+    if (h->tab.s == 1) DG_HIP(h, dgk::launch_torque_final(h->g, h->tq_part, torque_dev, h->s), "torque sum");
     return DG_OK;
 }
 

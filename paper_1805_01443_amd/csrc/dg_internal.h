@@ -111,10 +111,13 @@ struct MlpFlags {
 // (optional, order 4 adiabatic, not with pp): per tile, 1 if no element of
 // out needs the positivity scaling (for launch_troubled)
 // rev: the tiles of each XCD's band in reverse order (stage launches
-// alternate it; the results do not depend on it)
+// alternate it; the results do not depend on it).  tq_sum, tq_out: the
+// torque partials of an earlier first stage (tq_part there) added up into
+// *tq_out by one more block, with the bits of launch_torque_final.
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0,
                         double* out, const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s,
-                        const MlpFlags* mf = nullptr, unsigned char* pp_ok = nullptr, bool rev = false);
+                        const MlpFlags* mf = nullptr, unsigned char* pp_ok = nullptr, bool rev = false,
+                        const double* tq_sum = nullptr, double* tq_out = nullptr);
 hipError_t launch_set_coeffs(StageCoeffs* sc, const Geo& g, double t, double a0, double a1,
                              double a2, hipStream_t s);
 // CFL step per element; per-block minimum into dt_part[block] and a per-block

@@ -250,6 +250,64 @@ __device__ __forceinline__ double wave_sum(double s) {
     return s;
 }
 
+constexpr int kTorqueWaves = 4;      // tiles per block of the torque kernel
+constexpr int kTorqueFinal = 1024;   // threads of the final sum (k_torque_final)
+
+// The sum of k_torque_final computed by one wavefront (in the last stage
+// kernel of dg_rk_step_torque, beside its tiles): lane l plays the
+// threads w * 64 + l of that kernel (w = 0 .. 15), four of them at a time,
+// each with its own order of additions (its main loop of eight loads then
+// eight adds, then its remaining partials one by one), the same butterfly per
+// wavefront of 64 threads, and the wavefront sums added in index order: the
+// bits of k_torque_final.  Every lane returns the sum.
+__device__ double torque_final_in_wave(const double* __restrict__ partials, int nb) {
+    constexpr int TW = kTorqueFinal / 64, G = 2;
+    double r = 0.0;
+    for (int w0 = 0; w0 < TW; w0 += G) {
+        double s[G];
+        int k[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            s[q] = 0.0;
+            k[q] = (w0 + q) * 64 + (int)threadIdx.x;
+        }
+        // main loops of the G threads, trip by trip
+        while (k[0] + 7 * kTorqueFinal < nb || k[G - 1] + 7 * kTorqueFinal < nb) {
+            double v[G][8];
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const bool go = k[q] + 7 * kTorqueFinal < nb;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) v[q][m] = go ? partials[k[q] + m * kTorqueFinal] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                if (k[q] + 7 * kTorqueFinal < nb) {
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) s[q] += v[q][m];
+                    k[q] += 8 * kTorqueFinal;
+                }
+            }
+        }
+        // the remaining partials (at most seven per thread), one by one
+        double t[G][7];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int m = 0; m < 7; ++m) t[q][m] = k[q] + m * kTorqueFinal < nb ? partials[k[q] + m * kTorqueFinal] : 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m)
+                if (k[q] + m * kTorqueFinal < nb) s[q] += t[q][m];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_xor(s[q], off);
+            r += s[q];
+        }
+    }
+    return r;
+}
+
 // LDS layout of an element slot of the stage kernel.  A 64-lane access of
 // single doubles is served 32 lanes at a time over 64 banks of 4 bytes, so a
 // half-wave meets no bank twice when its 32 doubles fall on 32 different
@@ -353,7 +411,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
                                                 const void* __restrict__ mlp_pack,
                                                 const double* __restrict__ mlp_scale,
                                                 unsigned char* mlp_flags, float mlp_zthr,
-                                                unsigned char* pp_ok, int rev) {
+                                                unsigned char* pp_ok, int rev, double* tq_out) {
     constexpr int NV = NVar<CL>::value;
     constexpr int NN = N * N;
     constexpr int EW = 64 / N;
@@ -374,6 +432,19 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     // [side][v][a]; lower orders gather them by lane permute
     __shared__ double lds[EW * SLOT + (YL ? 2 * NV * N : 0)];
 
+    // With tq_out (the last stage of dg_rk_step_torque) the launch has eight
+    // more blocks in front, one per XCD, so that the tile blocks keep their
+    // XCD; the first adds up the torque partials tq_part of the step's first
+    // stage into *tq_out, the others end at once.
+    if (tq_out && blockIdx.x < 8) {
+        if (blockIdx.x == 0) {
+            const double r = torque_final_in_wave(tq_part, tiles_total);
+            if (threadIdx.x == 0) *tq_out = r;
+        }
+        return;
+    }
+    const int bid = (int)blockIdx.x - (tq_out ? 8 : 0);
+
     // Lane k * EW + s holds index k of element slot s: the lanes of one k
     // address consecutive doubles of the tile (a row of the EW elements is one
     // contiguous run), so every row load and store is contiguous in lane
@@ -388,7 +459,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
     const int k = own ? lane / EW : LY::C5 ? (lane - 32) / EW : lane - N * EW;
     const int sl = own ? lane - k * EW : EW;  // EW: a mirror lane
     const int e0 = own ? sl : LY::C5 ? lane - 32 - k * EW : 0;  // the element's lanes are e0 + a * EW
-    const int tile = remap_tile(blockIdx.x, tiles_total, rev);
+    const int tile = remap_tile(bid, tiles_total, rev);
     const int j = tile / tiles_x;
     const int i0 = (tile - j * tiles_x) * EW;
     const bool active = sl < EW && i0 + sl < g.nx;
@@ -1813,8 +1884,6 @@ __global__ void __launch_bounds__(64) k_damp_c(const Geo g, double* u, const dou
 }
 
 // ------------------------------------------------------------------ torque
-constexpr int kTorqueWaves = 4;      // tiles per block of the torque kernel
-constexpr int kTorqueFinal = 1024;   // threads of the final sum
 
 // deterministic block sum: fixed xor-butterfly inside each wavefront, then the
 // wavefront sums in index order by thread 0 (its return value; other threads
@@ -1953,7 +2022,7 @@ hipError_t launch_project(int n, int nvar, const Geo& g, const double* prim, dou
 
 hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, const double* u0, double* out,
                         const StageCoeffs* sc, bool pp, double* tq_part, hipStream_t s, const MlpFlags* mf,
-                        unsigned char* pp_ok, bool rev) {
+                        unsigned char* pp_ok, bool rev, const double* tq_sum, double* tq_out) {
     // arrays that a launch does not read still get a valid base (buffer
     // resources are never built on a null pointer)
     if (!un) un = u;
@@ -1961,6 +2030,10 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
     // with the positivity scaling fused the torque terms take the order-5
     // adiabatic kernel past 256 registers (one wave per SIMD): not offered
     if (pp && tq_part) return hipErrorInvalidValue;
+    // the torque partials of the first stage added up in a later one
+    if ((tq_out != nullptr) != (tq_sum != nullptr) || (tq_out && tq_part)) return hipErrorInvalidValue;
+    double* tq_arg = tq_part ? tq_part : const_cast<double*>(tq_sum);
+    const int lead = tq_out ? 8 : 0;
     if (mf && (pp || n != 4 || g.closure != CL_ADI || !mf->pack || !mf->scale || !mf->flags))
         return hipErrorInvalidValue;
     if (pp_ok && (pp || n != 4 || g.closure != CL_ADI)) return hipErrorInvalidValue;
@@ -1969,8 +2042,8 @@ hipError_t launch_stage(int n, const Geo& g, const double* u, const double* un, 
     unsigned char* mflags = mf ? mf->flags : nullptr;
     const float mzthr = mf ? mf->zthr : 0.f;
 #define DG_STAGE(PPV, TQV, FXV, MFV)                                                                             \
-    hipLaunchKernelGGL((k_stage_c<NT, CT, PPV, TQV, FXV, MFV>), dim3(tt), dim3(64), 0, s, g, tx, tt, u, un, u0, \
-                       out, sc, tq_part, mpack, mscale, mflags, mzthr, pp_ok, rev ? 1 : 0)
+    hipLaunchKernelGGL((k_stage_c<NT, CT, PPV, TQV, FXV, MFV>), dim3(tt + lead), dim3(64), 0, s, g, tx, tt, u, un, \
+                       u0, out, sc, tq_arg, mpack, mscale, mflags, mzthr, pp_ok, rev ? 1 : 0, tq_out)
 #define DG_STAGE_MF(TQV, FXV)                                      \
     if constexpr (NT == 4 && CT == CL_ADI) {                       \
         if (pp_ok) {                                               \
