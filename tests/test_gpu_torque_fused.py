@@ -1,9 +1,12 @@
 """The torque of eq. (5) formed inside a step (dg_rk_step_torque): the first
-stage kernel forms the torque of the state entering the step, u^n at t^n, from
-the node densities and planet offsets it evaluates.  Against dg_torque before
-dg_rk_step on a second handle from the same initial state: the same torque
-bits and the same states at every step; and the torque of the initial state
-against the oracle's (Sec. 5.2) to 1e-12 of the sum of |terms|.
+stage kernel forms the per-tile partials of the torque of the state entering
+the step, u^n at t^n, from the node densities and planet offsets it
+evaluates, and one more block of the last stage kernel adds them up in the
+order of the final-sum kernel.  Against dg_torque before dg_rk_step on a
+second handle from the same initial state: the same torque bits and the same
+states at every step (SSP(3,3), SSP(2,2) and a Butcher table, where the sum
+runs in stage 3, stage 2 and the last of six stages); and the torque of the
+initial state against the oracle's (Sec. 5.2) to 1e-12 of the sum of |terms|.
 """
 import dataclasses
 
