@@ -85,3 +85,34 @@ def test_torque_in_the_step_equals_torque_then_step(name, cfg, kind, seed):
     assert abs(qa[0].item() - g) <= TOL * sabs
     for h in (ha, hb):
         h.close()
+
+
+def test_torque_sum_bits_with_many_tiles():
+    """The benchmark's 512 x 512 order-5 disc: 22016 tile partials, so the
+    in-stage sum runs the eight-load trips of the final-sum kernel's threads
+    as well as their remainders; two steps, the torque bits and the states
+    against dg_torque then dg_rk_step on a second handle."""
+    T = torch()
+    cfg = W.disc(nx=512, order=5)
+    oc = O.cfg(dataclasses.asdict(cfg))
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, "disc", seed=0, x=x, y=y)
+    print("[torque in step] disc 512x512 order 5, 22016 partials", flush=True)
+    ha, ua = dg.dg_init(cfg, prim)
+    hb, ub = dg.dg_init(cfg, prim)
+    ta = T.zeros(1, dtype=T.float64, device="cuda")
+    tb = T.zeros(1, dtype=T.float64, device="cuda")
+    qa = T.zeros(2, dtype=T.float64, device="cuda")
+    qb = T.zeros(2, dtype=T.float64, device="cuda")
+    for k in range(2):
+        dg.dg_rk_step_torque(ha, ua, ta, qa[k:k + 1])
+        dg.dg_torque(hb, ub, qb[k:k + 1], t_dev=tb)
+        dg.dg_rk_step(hb, ub, tb, 0.0, None)
+    dg.dg_sync(ha)
+    dg.dg_sync(hb)
+    print(f"  torques {qa.cpu().numpy()} / {qb.cpu().numpy()}", flush=True)
+    assert T.equal(qa, qb)
+    assert T.equal(ua, ub)
+    assert ta.item() == tb.item()
+    for h in (ha, hb):
+        h.close()
