@@ -179,6 +179,9 @@ void make_geo(const dg_config* c, Geo* g) {
     g->rc3inv = c->r_core > 0 ? c->gm / (c->r_core * c->r_core * c->r_core) : 0.0;
     g->q = c->q;
     g->eps2 = c->eps * c->eps;
+    g->gm_h = g->gm * (0.5 * g->dx);
+    g->rc3inv_h = g->rc3inv * (0.5 * g->dx);
+    g->q_h = g->q * (0.5 * g->dx);
     g->rp = c->rp;
     g->phi0 = c->phi0;
     g->omp = c->rp > 0 ? std::sqrt(c->gm / (c->rp * c->rp * c->rp)) : 0.0;

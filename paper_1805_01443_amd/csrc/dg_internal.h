@@ -36,6 +36,7 @@ struct Geo {
     double gamma;
     double gm, r_core, rc3inv;  // GM / r_core^3
     double q, eps2;
+    double gm_h, rc3inv_h, q_h; // gm, rc3inv, q times dx / 2 (the stage kernel's x projection)
     double rp, phi0, omp;       // planet orbit, Omega_p
     // damping
     int damping;

@@ -692,10 +692,10 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         // w_r phi_b(eta_r) as X[r][a]: X[r][a] = -(1/dx)(phi_a(-1) h_W + phi_a(1) h_E)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double hp = g.idx * (he[v] + hw[v]), hm = g.idx * (he[v] - hw[v]);
+            const double hp = he[v] + hw[v], hm = he[v] - hw[v];
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                X[v][a] = -(B.pp[a] * ((a & 1) ? hm : hp));
+                X[v][a] = -((0.5 * B.pp[a]) * ((a & 1) ? hm : hp));
                 Y[v][a] = 0.0;
             }
         }
@@ -774,7 +774,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         const double vx = W[1] * inv, vy = W[2] * inv;
         double gx = 0.0, gy = 0.0;
         if (g.star) {
-            const double kk = r2 < g.rc2 ? g.rc3inv : g.gm * ir * ir * ir;
+            const double kk = r2 < g.rc2 ? g.rc3inv_h : g.gm_h * ir * ir * ir;
             gx = kk * x;
             gy = kk * y;
         }
@@ -782,7 +782,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             const double dx = x - xp, dy = y - yp;
             const double id = rsq64(dx * dx + dy * dy + g.eps2);
             const double id3 = id * id * id;
-            const double kk = g.q * id3;
+            const double kk = g.q_h * id3;
             gx += kk * dx;
             gy += kk * dy;
             if constexpr (TQ) tqs += torque_term(W[0], wk * B.wh[q], xp, yp, dx, dy, id3);
@@ -804,7 +804,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double fxx = g.rdx2 * fx[v], fyy = g.rdy2 * fy[v];
+            const double fxx = fx[v], fyy = fy[v];
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 // the density equation has no source term
@@ -833,6 +833,10 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
         for (int m = 1; m < N; ++m) r = k == m ? B.wphi[m][q] : r;
         wrow[q] = r;
     }
+    // R = a2 L(u) row by row: X and Y hold the x and y projections without
+    // their 2/dx and 2/dy (the sources and the west/east lifts scaled by dx/2
+    // instead), which go in with a2 here
+    const double a2x = a2 * g.rdx2, a2y = a2 * g.rdy2, a2i = a2 * g.idy;
     double R[NV][N];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -847,7 +851,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             double acc = 0.0;
 #pragma unroll
             for (int r = 0; r < N; ++r) acc += B.wphi[b][r] * S[LY::ci(v, r, k)];
-            R[v][b] = acc - g.idy * (B.pm[b] * glb + B.pp[b] * glt);
+            R[v][b] = a2x * acc - a2i * (B.pm[b] * glb + B.pp[b] * glt);
         }
     }
     __syncthreads();  // every lane has read X
@@ -880,7 +884,7 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
             double acc = 0.0;
 #pragma unroll
             for (int r = 0; r < N; ++r) acc += B.wdphi[b][r] * S[LY::ci(v, r, k)];
-            R[v][b] += acc;
+            R[v][b] += a2y * acc;
         }
     // the new row; with PP the positivity scaling of Sec. 2.4 on it before
     // the store (the same factors as the separate positivity pass on the
@@ -890,12 +894,12 @@ __global__ void __launch_bounds__(64) k_stage_c(const Geo g, int tiles_x, int ti
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int b = 0; b < N; ++b) O[v][b] = a0 * Un[v][b] + (a1 * U1[v][b] + a2 * R[v][b]);
+            for (int b = 0; b < N; ++b) O[v][b] = a0 * Un[v][b] + (a1 * U1[v][b] + R[v][b]);
     } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int b = 0; b < N; ++b) O[v][b] = a1 * U1[v][b] + a2 * R[v][b];
+            for (int b = 0; b < N; ++b) O[v][b] = a1 * U1[v][b] + R[v][b];
     }
     if constexpr (PP != 0) {
         __syncthreads();  // every lane has read Y
