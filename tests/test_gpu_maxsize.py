@@ -1,0 +1,129 @@
+"""Parity at the largest state the library accepts: the seeded planet disc
+at order 5 on 1895 x 1887 elements (158 tiles per row, the last holding 11
+of 12 elements; 2 146 651 200 bytes per state array, just below the 2^31 - 1
+bytes a buffer resource covers, so the last rows sit at the highest offsets
+the kernels form).  One dg_rk_step_torque call, the benchmark's:
+
+* the projection of the whole state against the oracle's, 1e-12 of max|u_v|;
+* dt against the oracle's CFL step of the whole state, to 1e-14;
+* the torque of the initial state against the oracle's, 1e-12 of the sum of
+  |terms|;
+* the new state on sampled windows of 7 x 7 elements (box corners, the
+  ragged last tile, the planet, the inner damping edge, tile and row
+  boundaries): the oracle steps each window alone with the same dt, and the
+  elements at least three elements from every window edge that is not a box
+  edge are exact (each of the three stages reaches one element further),
+  1e-12 of the window's max|rho| for the density and of its largest
+  momentum component for the momenta.  (Checked on the CPU with the oracle's
+  own full-size step in place of the GPU's: those elements agree to 1e-17,
+  the others differ by about 2e-6.)
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1805_01443_amd import configs as W
+from paper_1805_01443_amd import dg
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+TOL = 1e-12
+NX, NY, WIN = 1895, 1887, 7
+
+
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU test needs a ROCm device"
+    return T
+
+
+def window_cfg(cfg, i0, j0):
+    dx = (cfg.x1 - cfg.x0) / cfg.nx
+    dy = (cfg.y1 - cfg.y0) / cfg.ny
+    return cfg.replace(nx=WIN, ny=WIN, x0=cfg.x0 + i0 * dx, x1=cfg.x0 + (i0 + WIN) * dx,
+                       y0=cfg.y0 + j0 * dy, y1=cfg.y0 + (j0 + WIN) * dy)
+
+
+def exact_cells(i0, j0):
+    """(i, j) of the window's elements that the window's own edges cannot
+    reach within one three-stage step."""
+    out = []
+    for j in range(j0, j0 + WIN):
+        for i in range(i0, i0 + WIN):
+            if i0 > 0 and i - i0 < 3 or i0 + WIN < NX and i0 + WIN - 1 - i < 3:
+                continue
+            if j0 > 0 and j - j0 < 3 or j0 + WIN < NY and j0 + WIN - 1 - j < 3:
+                continue
+            out.append((i, j))
+    return out
+
+
+def test_largest_state_step_parity():
+    T = torch()
+    cfg = W.disc(nx=NX, order=5).replace(ny=NY)
+    assert dg.dg_state_size(cfg) * 8 == 600 * 1896 * NY <= 2 ** 31 - 1
+    oc = O.cfg(dataclasses.asdict(cfg))
+    print(f"[max size] disc {NX}x{NY} order 5, seed 0: nodes and primitive values", flush=True)
+    x, y = O.nodes(oc)
+    prim = W.prim_for(cfg, "disc", seed=0, x=x, y=y)
+    del x, y
+    print("[max size] dg_init and one dg_rk_step_torque", flush=True)
+    h, u = dg.dg_init(cfg, prim)
+    ug0 = dg.to_planes(cfg, u.detach().cpu().numpy())
+    t_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
+    tq = T.zeros(1, dtype=T.float64, device="cuda")
+    dg.dg_rk_step_torque(h, u, t_dev, tq, 0.0, dt_dev)
+    dg.dg_sync(h)
+    ug = dg.to_planes(cfg, u.detach().cpu().numpy())
+    h.close()
+    del u
+    T.cuda.empty_cache()
+
+    print("[max size] oracle projection, dt and torque", flush=True)
+    uo = O.project(oc, prim)
+    err = [float(np.max(np.abs(ug0[v] - uo[v])) / np.max(np.abs(uo[v]))) for v in range(3)]
+    del ug0
+    dto = O.dt(oc, uo)
+    g, sabs = O.torque(oc, 0.0, uo)
+    del uo
+    print(f"[max size] projection rel err {err}; dt {dt_dev.item():.17e} vs {dto:.17e}; "
+          f"torque {tq.item():.17e} vs {g:.17e} (sum|terms| {sabs:.3e})", flush=True)
+    assert max(err) <= TOL
+    assert abs(dt_dev.item() - dto) <= 1e-14 * dto
+    assert abs(tq.item() - g) <= TOL * sabs
+
+    dx = (cfg.x1 - cfg.x0) / NX
+    dy = (cfg.y1 - cfg.y0) / NY
+    ip, jp = int((1.0 - cfg.x0) / dx), int((0.0 - cfg.y0) / dy)  # the planet at t = 0
+    ir = int((0.4 - cfg.x0) / dx)  # the inner damping edge on the x axis
+    windows = [
+        (0, 0),  # south-west corner
+        (NX - WIN, NY - WIN),  # north-east corner: the ragged last tile, the highest offsets
+        (NX - WIN, 0),
+        (0, NY - WIN),
+        (ip - 3, jp - 3),
+        (ir - 3, jp - 3),
+        (12 * 79 - 4, 1000),  # across a tile boundary
+        (500, NY // 2 - 3),
+    ]
+    rng = np.random.default_rng(5)
+    windows += [(int(rng.integers(0, NX - WIN)), int(rng.integers(0, NY - WIN))) for _ in range(4)]
+    for i0, j0 in windows:
+        wc = window_cfg(cfg, i0, j0)
+        woc = O.cfg(dataclasses.asdict(wc))
+        ids = np.array([j * NX + i for j in range(j0, j0 + WIN) for i in range(i0, i0 + WIN)])
+        uw = O.project(woc, prim[:, ids, :])
+        un, _ = O.step(woc, uw, 0.0, dto, u0=uw)
+        cells = exact_cells(i0, j0)
+        we = np.array([(j - j0) * WIN + (i - i0) for i, j in cells])
+        ge = np.array([j * NX + i for i, j in cells])
+        want = un[:, :, we]
+        got = ug[:, :, ge]
+        # momentum: relative to the larger of its two components (one of them
+        # is near zero on a window that the x or the y axis crosses)
+        sc = [np.max(np.abs(want[0])), np.max(np.abs(want[1:]))]
+        e = [float(np.max(np.abs(got[v] - want[v])) / sc[min(v, 1)]) for v in range(3)]
+        print(f"[max size] window ({i0}, {j0}): {len(cells)} elements, rel err {e}", flush=True)
+        assert max(e) <= TOL
