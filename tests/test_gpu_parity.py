@@ -103,6 +103,14 @@ def test_projection_and_rhs_parity(name, cfg, kind):
     ("disc_p4_damped", W.disc(nx=26, order=5, q=1e-3), "disc", 3),
     ("ring_p3", W.disc_ring(nx=40, order=4), "disc_ring", 3),
     ("paper_disc_p4_damped", W.paper_disc(nx=36, order=5, q=1e-3, positivity=0), "paper_disc", 3),
+    # degenerate grids: one column (both x neighbours are fixed box edges,
+    # read by the same lane), one element (four fixed edges), one periodic
+    # row (each element its own y neighbour; 13 = 12 + 1 elements, a second
+    # tile holding one), and no planet (q = 0)
+    ("disc_p4_one_column", W.disc(nx=1, order=5, q=1e-3).replace(ny=9), "disc", 2),
+    ("disc_p2_one_element", W.disc(nx=1, order=3, q=1e-3).replace(ny=1), "disc", 2),
+    ("wave_p4_one_row", W.wave(nx=13, order=5).replace(ny=1), "wave", 2),
+    ("disc_p4_no_planet", W.disc(nx=24, order=5, q=0.0).replace(ny=22), "disc", 2),
 ])
 def test_rk_steps_parity(name, cfg, kind, nsteps):
     T = torch()
