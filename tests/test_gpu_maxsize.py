@@ -1,8 +1,10 @@
-"""Parity at the largest state the library accepts: the seeded planet disc
-at order 5 on 1895 x 1887 elements (158 tiles per row, the last holding 11
-of 12 elements; 2 146 651 200 bytes per state array, just below the 2^31 - 1
-bytes a buffer resource covers, so the last rows sit at the highest offsets
-the kernels form).  One dg_rk_step_torque call, the benchmark's:
+"""Parity at the largest states the library accepts: the seeded planet disc
+at each order on the largest near-square grid whose state array stays below
+the 2^31 - 1 bytes a buffer resource covers, with a ragged last tile in
+every row (order 5: 1895 x 1887 elements, 158 tiles per row, the last
+holding 11 of 12; 2 146 651 200 bytes per state array), so the last rows sit
+at the highest offsets the kernels form; one more row is refused.  One
+dg_rk_step_torque call, the benchmark's:
 
 * the projection of the whole state against the oracle's, 1e-12 of max|u_v|;
 * dt against the oracle's CFL step of the whole state, to 1e-14;
@@ -29,7 +31,9 @@ from paper_1805_01443_amd import dg
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 TOL = 1e-12
-NX, NY, WIN = 1895, 1887, 7
+WIN = 7
+# (order, nx, ny): nx one or more elements short of a whole number of tiles
+SIZES = [(2, 4729, 4723), (3, 3149, 3156), (4, 2363, 2361), (5, 1895, 1887)]
 
 
 def torch():
@@ -45,7 +49,7 @@ def window_cfg(cfg, i0, j0):
                        y0=cfg.y0 + j0 * dy, y1=cfg.y0 + (j0 + WIN) * dy)
 
 
-def exact_cells(i0, j0):
+def exact_cells(i0, j0, NX, NY):
     """(i, j) of the window's elements that the window's own edges cannot
     reach within one three-stage step."""
     out = []
@@ -59,12 +63,17 @@ def exact_cells(i0, j0):
     return out
 
 
-def test_largest_state_step_parity():
+@pytest.mark.parametrize("order,NX,NY", SIZES, ids=[f"p{s[0] - 1}" for s in SIZES])
+def test_largest_state_step_parity(order, NX, NY):
     T = torch()
-    cfg = W.disc(nx=NX, order=5).replace(ny=NY)
-    assert dg.dg_state_size(cfg) * 8 == 600 * 1896 * NY <= 2 ** 31 - 1
+    cfg = W.disc(nx=NX, order=order).replace(ny=NY)
+    EW = 64 // order
+    assert NX % EW != 0
+    assert dg.dg_state_size(cfg) * 8 == 24 * order * order * (-(-NX // EW) * EW) * NY <= 2 ** 31 - 1
+    with pytest.raises(dg.DGError):
+        dg.dg_state_size(cfg.replace(ny=NY + 1))
     oc = O.cfg(dataclasses.asdict(cfg))
-    print(f"[max size] disc {NX}x{NY} order 5, seed 0: nodes and primitive values", flush=True)
+    print(f"[max size] disc {NX}x{NY} order {order}, seed 0: nodes and primitive values", flush=True)
     x, y = O.nodes(oc)
     prim = W.prim_for(cfg, "disc", seed=0, x=x, y=y)
     del x, y
@@ -105,7 +114,7 @@ def test_largest_state_step_parity():
         (0, NY - WIN),
         (ip - 3, jp - 3),
         (ir - 3, jp - 3),
-        (12 * 79 - 4, 1000),  # across a tile boundary
+        (EW * (NX // EW // 2) - 4, NY // 2 + 60),  # across a tile boundary
         (500, NY // 2 - 3),
     ]
     rng = np.random.default_rng(5)
@@ -116,7 +125,7 @@ def test_largest_state_step_parity():
         ids = np.array([j * NX + i for j in range(j0, j0 + WIN) for i in range(i0, i0 + WIN)])
         uw = O.project(woc, prim[:, ids, :])
         un, _ = O.step(woc, uw, 0.0, dto, u0=uw)
-        cells = exact_cells(i0, j0)
+        cells = exact_cells(i0, j0, NX, NY)
         we = np.array([(j - j0) * WIN + (i - i0) for i, j in cells])
         ge = np.array([j * NX + i for i, j in cells])
         want = un[:, :, we]
