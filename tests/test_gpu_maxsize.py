@@ -1,5 +1,6 @@
 """Parity at the largest states the library accepts: the seeded planet disc
-at each order on the largest near-square grid whose state array stays below
+at each order, and the adiabatic ring (four variables) at order 4, on the
+largest near-square grid whose state array stays below
 the 2^31 - 1 bytes a buffer resource covers, with a ragged last tile in
 every row (order 5: 1895 x 1887 elements, 158 tiles per row, the last
 holding 11 of 12; 2 146 651 200 bytes per state array), so the last rows sit
@@ -15,8 +16,8 @@ dg_rk_step_torque call, the benchmark's:
   boundaries): the oracle steps each window alone with the same dt, and the
   elements at least three elements from every window edge that is not a box
   edge are exact (each of the three stages reaches one element further),
-  1e-12 of the window's max|rho| for the density and of its largest
-  momentum component for the momenta.  (Checked on the CPU with the oracle's
+  1e-12 of the window's max|rho| for the density, of its largest momentum
+  component for the momenta and of its max|E| for the energy.  (Checked on the CPU with the oracle's
   own full-size step in place of the GPU's: those elements agree to 1e-17,
   the others differ by about 2e-6.)
 """
@@ -32,8 +33,11 @@ from paper_1805_01443_amd import dg
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 TOL = 1e-12
 WIN = 7
-# (order, nx, ny): nx one or more elements short of a whole number of tiles
-SIZES = [(2, 4729, 4723), (3, 3149, 3156), (4, 2363, 2361), (5, 1895, 1887)]
+# (order, nx, ny, initial data): nx one or more elements short of a whole
+# number of tiles; the adiabatic ring has four variables (32 n^2 bytes per
+# element slot)
+SIZES = [(2, 4729, 4723, "disc"), (3, 3149, 3156, "disc"), (4, 2363, 2361, "disc"), (5, 1895, 1887, "disc"),
+         (4, 2045, 2047, "disc_ring")]
 
 
 def torch():
@@ -63,19 +67,20 @@ def exact_cells(i0, j0, NX, NY):
     return out
 
 
-@pytest.mark.parametrize("order,NX,NY", SIZES, ids=[f"p{s[0] - 1}" for s in SIZES])
-def test_largest_state_step_parity(order, NX, NY):
+@pytest.mark.parametrize("order,NX,NY,kind", SIZES, ids=[f"{s[3]}_p{s[0] - 1}" for s in SIZES])
+def test_largest_state_step_parity(order, NX, NY, kind):
     T = torch()
-    cfg = W.disc(nx=NX, order=order).replace(ny=NY)
+    cfg = (W.disc if kind == "disc" else W.disc_ring)(nx=NX, order=order).replace(ny=NY)
+    nv = cfg.nvar
     EW = 64 // order
     assert NX % EW != 0
-    assert dg.dg_state_size(cfg) * 8 == 24 * order * order * (-(-NX // EW) * EW) * NY <= 2 ** 31 - 1
+    assert dg.dg_state_size(cfg) * 8 == 8 * nv * order * order * (-(-NX // EW) * EW) * NY <= 2 ** 31 - 1
     with pytest.raises(dg.DGError):
         dg.dg_state_size(cfg.replace(ny=NY + 1))
     oc = O.cfg(dataclasses.asdict(cfg))
-    print(f"[max size] disc {NX}x{NY} order {order}, seed 0: nodes and primitive values", flush=True)
+    print(f"[max size] {kind} {NX}x{NY} order {order}, seed 0: nodes and primitive values", flush=True)
     x, y = O.nodes(oc)
-    prim = W.prim_for(cfg, "disc", seed=0, x=x, y=y)
+    prim = W.prim_for(cfg, kind, seed=0, x=x, y=y)
     del x, y
     print("[max size] dg_init and one dg_rk_step_torque", flush=True)
     h, u = dg.dg_init(cfg, prim)
@@ -92,7 +97,7 @@ def test_largest_state_step_parity(order, NX, NY):
 
     print("[max size] oracle projection, dt and torque", flush=True)
     uo = O.project(oc, prim)
-    err = [float(np.max(np.abs(ug0[v] - uo[v])) / np.max(np.abs(uo[v]))) for v in range(3)]
+    err = [float(np.max(np.abs(ug0[v] - uo[v])) / np.max(np.abs(uo[v]))) for v in range(nv)]
     del ug0
     dto = O.dt(oc, uo)
     g, sabs = O.torque(oc, 0.0, uo)
@@ -132,7 +137,8 @@ def test_largest_state_step_parity(order, NX, NY):
         got = ug[:, :, ge]
         # momentum: relative to the larger of its two components (one of them
         # is near zero on a window that the x or the y axis crosses)
-        sc = [np.max(np.abs(want[0])), np.max(np.abs(want[1:]))]
-        e = [float(np.max(np.abs(got[v] - want[v])) / sc[min(v, 1)]) for v in range(3)]
+        sc = [np.max(np.abs(want[0])), np.max(np.abs(want[1:3])), np.max(np.abs(want[1:3]))]
+        sc += [np.max(np.abs(want[3]))] if nv == 4 else []
+        e = [float(np.max(np.abs(got[v] - want[v])) / sc[v]) for v in range(nv)]
         print(f"[max size] window ({i0}, {j0}): {len(cells)} elements, rel err {e}", flush=True)
         assert max(e) <= TOL
