@@ -1,5 +1,6 @@
 """Parity at the largest states the library accepts: the seeded planet disc
-at each order, and the adiabatic ring (four variables) at order 4, on the
+at each order, the adiabatic ring (four variables) at order 4 and the
+deviation form of the disc at order 5, on the
 largest near-square grid whose state array stays below
 the 2^31 - 1 bytes a buffer resource covers, with a ragged last tile in
 every row (order 5: 1895 x 1887 elements, 158 tiles per row, the last
@@ -17,7 +18,8 @@ dg_rk_step_torque call, the benchmark's:
   elements at least three elements from every window edge that is not a box
   edge are exact (each of the three stages reaches one element further),
   1e-12 of the window's max|rho| for the density, of its largest momentum
-  component for the momenta and of its max|E| for the energy.  (Checked on the CPU with the oracle's
+  component for the momenta and of its max|E| for the energy (the deviation
+  form: 1e-5, its bar against the FP64 oracle, dt to 1e-13).  (Checked on the CPU with the oracle's
   own full-size step in place of the GPU's: those elements agree to 1e-17,
   the others differ by about 2e-6.)
 """
@@ -37,7 +39,8 @@ WIN = 7
 # number of tiles; the adiabatic ring has four variables (32 n^2 bytes per
 # element slot)
 SIZES = [(2, 4729, 4723, "disc"), (3, 3149, 3156, "disc"), (4, 2363, 2361, "disc"), (5, 1895, 1887, "disc"),
-         (4, 2045, 2047, "disc_ring")]
+         (4, 2045, 2047, "disc_ring"), (5, 1895, 1887, "disc_mixed")]
+MAKE = {"disc": W.disc, "disc_ring": W.disc_ring, "disc_mixed": W.disc_mixed}
 
 
 def torch():
@@ -70,8 +73,12 @@ def exact_cells(i0, j0, NX, NY):
 @pytest.mark.parametrize("order,NX,NY,kind", SIZES, ids=[f"{s[3]}_p{s[0] - 1}" for s in SIZES])
 def test_largest_state_step_parity(order, NX, NY, kind):
     T = torch()
-    cfg = (W.disc if kind == "disc" else W.disc_ring)(nx=NX, order=order).replace(ny=NY)
+    cfg = MAKE[kind](nx=NX, order=order).replace(ny=NY)
     nv = cfg.nvar
+    mixed = kind == "disc_mixed"
+    # the deviation form: FP32 deviation terms, the FP64 oracle's bar for its
+    # state; its CFL step from FP64 means of u_eq + du
+    tol_step, tol_dt = (1e-5, 1e-13) if mixed else (TOL, 1e-14)
     EW = 64 // order
     assert NX % EW != 0
     assert dg.dg_state_size(cfg) * 8 == 8 * nv * order * order * (-(-NX // EW) * EW) * NY <= 2 ** 31 - 1
@@ -80,17 +87,26 @@ def test_largest_state_step_parity(order, NX, NY, kind):
     oc = O.cfg(dataclasses.asdict(cfg))
     print(f"[max size] {kind} {NX}x{NY} order {order}, seed 0: nodes and primitive values", flush=True)
     x, y = O.nodes(oc)
-    prim = W.prim_for(cfg, kind, seed=0, x=x, y=y)
+    prim = W.prim_for(cfg, "disc" if mixed else kind, seed=0, x=x, y=y)
     del x, y
     print("[max size] dg_init and one dg_rk_step_torque", flush=True)
     h, u = dg.dg_init(cfg, prim)
-    ug0 = dg.to_planes(cfg, u.detach().cpu().numpy())
+
+    def full_planes():
+        if not mixed:
+            return dg.to_planes(cfg, u.detach().cpu().numpy())
+        full = T.empty_like(u)
+        dg.dg_full_state(h, u, full)
+        dg.dg_sync(h)
+        return dg.to_planes(cfg, full.detach().cpu().numpy())
+
+    ug0 = full_planes()
     t_dev = T.zeros(1, dtype=T.float64, device="cuda")
     dt_dev = T.zeros(1, dtype=T.float64, device="cuda")
     tq = T.zeros(1, dtype=T.float64, device="cuda")
     dg.dg_rk_step_torque(h, u, t_dev, tq, 0.0, dt_dev)
     dg.dg_sync(h)
-    ug = dg.to_planes(cfg, u.detach().cpu().numpy())
+    ug = full_planes()
     h.close()
     del u
     T.cuda.empty_cache()
@@ -105,7 +121,7 @@ def test_largest_state_step_parity(order, NX, NY, kind):
     print(f"[max size] projection rel err {err}; dt {dt_dev.item():.17e} vs {dto:.17e}; "
           f"torque {tq.item():.17e} vs {g:.17e} (sum|terms| {sabs:.3e})", flush=True)
     assert max(err) <= TOL
-    assert abs(dt_dev.item() - dto) <= 1e-14 * dto
+    assert abs(dt_dev.item() - dto) <= tol_dt * dto
     assert abs(tq.item() - g) <= TOL * sabs
 
     dx = (cfg.x1 - cfg.x0) / NX
@@ -141,4 +157,4 @@ def test_largest_state_step_parity(order, NX, NY, kind):
         sc += [np.max(np.abs(want[3]))] if nv == 4 else []
         e = [float(np.max(np.abs(got[v] - want[v])) / sc[v]) for v in range(nv)]
         print(f"[max size] window ({i0}, {j0}): {len(cells)} elements, rel err {e}", flush=True)
-        assert max(e) <= TOL
+        assert max(e) <= tol_step
