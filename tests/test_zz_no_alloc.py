@@ -45,3 +45,23 @@ def test_noalloc_torque_matches_dg_torque_bitwise_on_two_calls():
         assert np.isfinite(ref) and ref != 0.0
         assert got == ref
         assert got_t == ref_t
+
+
+def test_noalloc_torque_fills_the_scratch_exactly():
+    """The largest grid the static scratch holds: order 2 on 4096 x 4096
+    elements, 128 tiles of 32 elements per row, 524288 partial sums, every
+    slot of the scratch; one more row is refused before any device work.
+    Then a smaller call, which must not see the partials left behind."""
+    import torch as T
+    assert T.cuda.is_available()
+    full = W.disc(nx=4096, order=2).replace(ny=4096)
+    with pytest.raises(dg.DGError) as ex:
+        dg.dg_torque_noalloc(full.replace(ny=4097), None, None, stream=0)
+    assert ex.value.code == dg.DG_EUNSUPPORTED
+    for cfg in (full, W.disc(nx=36, order=3, q=1e-3)):
+        print(f"[noalloc torque] {cfg.nx}x{cfg.ny} order {cfg.order}", flush=True)
+        ref, got, ref_t, got_t = _torque_pair(T, cfg, 0.0)
+        print(f"  dg_torque {ref!r}, dg_torque_noalloc {got!r}", flush=True)
+        assert np.isfinite(ref) and ref != 0.0
+        assert got == ref
+        assert got_t == ref_t
