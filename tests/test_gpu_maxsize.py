@@ -21,7 +21,11 @@ dg_rk_step_torque call, the benchmark's:
   edge are exact (each of the three stages reaches one element further),
   1e-12 of the window's max|rho| for the density, of its largest momentum
   component for the momenta and of its max|E| for the energy (the deviation
-  form: 1e-5, its bar against the FP64 oracle, dt to 1e-13).  (Checked on the CPU with the oracle's
+  form: 1e-5, its bar against the FP64 oracle, dt to 1e-13).  With the
+  modal-decay limiter after every stage (the ring, order 4, positivity
+  limiter too) a step reaches six elements, the windows are 13 x 13, four
+  of them sit on elements the oracle's indicator flags, and the limiter
+  must have changed some of the compared elements.  (Checked on the CPU with the oracle's
   own full-size step in place of the GPU's: those elements agree to 1e-17,
   the others differ by about 2e-6.)
 """
@@ -37,17 +41,20 @@ from paper_1805_01443_amd import dg
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 TOL = 1e-12
-WIN = 7
+REACH = 3  # elements a three-stage step reaches (one per stage)
+LIM_S0 = -9.0  # flags about 800 elements at the core's edge in the largest grid at t = 0
 # (order, nx, ny, initial data): nx one or more elements short of a whole
 # number of tiles; the adiabatic ring has four variables (32 n^2 bytes per
 # element slot)
 SIZES = [(2, 4729, 4723, "disc"), (3, 3149, 3156, "disc"), (4, 2363, 2361, "disc"), (5, 1895, 1887, "disc"),
          (4, 2045, 2047, "disc_ring"), (4, 2045, 2047, "disc_ring_hllc"), (5, 1637, 1632, "paper_disc"),
-         (5, 1895, 1887, "disc_mixed")]
+         (4, 2045, 2047, "disc_ring_limited"), (5, 1895, 1887, "disc_mixed")]
 MAKE = {"disc": W.disc, "disc_ring": W.disc_ring, "disc_mixed": W.disc_mixed,
         "disc_ring_hllc": lambda nx, order: W.disc_ring(nx=nx, order=order).replace(flux=dg.FLUX_HLLC),
-        "paper_disc": lambda nx, order: W.paper_disc(nx=nx, order=order, q=1e-3)}
-PRIM = {"disc_mixed": "disc", "disc_ring_hllc": "disc_ring"}
+        "paper_disc": lambda nx, order: W.paper_disc(nx=nx, order=order, q=1e-3),
+        "disc_ring_limited": lambda nx, order: W.disc_ring(nx=nx, order=order).replace(
+            limiter=dg.LIMITER_MODAL_DECAY, limiter_s0=LIM_S0, positivity=1)}
+PRIM = {"disc_mixed": "disc", "disc_ring_hllc": "disc_ring", "disc_ring_limited": "disc_ring"}
 
 
 def torch():
@@ -56,22 +63,23 @@ def torch():
     return T
 
 
-def window_cfg(cfg, i0, j0):
+def window_cfg(cfg, i0, j0, WIN=2 * REACH + 1):
     dx = (cfg.x1 - cfg.x0) / cfg.nx
     dy = (cfg.y1 - cfg.y0) / cfg.ny
     return cfg.replace(nx=WIN, ny=WIN, x0=cfg.x0 + i0 * dx, x1=cfg.x0 + (i0 + WIN) * dx,
                        y0=cfg.y0 + j0 * dy, y1=cfg.y0 + (j0 + WIN) * dy)
 
 
-def exact_cells(i0, j0, NX, NY):
+def exact_cells(i0, j0, NX, NY, R=REACH):
     """(i, j) of the window's elements that the window's own edges cannot
     reach within one three-stage step."""
+    WIN = 2 * R + 1
     out = []
     for j in range(j0, j0 + WIN):
         for i in range(i0, i0 + WIN):
-            if i0 > 0 and i - i0 < 3 or i0 + WIN < NX and i0 + WIN - 1 - i < 3:
+            if i0 > 0 and i - i0 < R or i0 + WIN < NX and i0 + WIN - 1 - i < R:
                 continue
-            if j0 > 0 and j - j0 < 3 or j0 + WIN < NY and j0 + WIN - 1 - j < 3:
+            if j0 > 0 and j - j0 < R or j0 + WIN < NY and j0 + WIN - 1 - j < R:
                 continue
             out.append((i, j))
     return out
@@ -128,6 +136,10 @@ def test_largest_state_step_parity(order, NX, NY, kind):
     del ug0
     dto = O.dt(oc, uo)
     g, sabs = O.torque(oc, 0.0, uo)
+    # with the limiter: windows on elements the oracle's indicator flags in
+    # the state entering the step
+    flagged = np.nonzero(O.indicator(oc, uo) > cfg.limiter_s0)[0] if cfg.limiter else np.zeros(0, int)
+    assert flagged.size > 0 or not cfg.limiter
     del uo
     print(f"[max size] projection rel err {err}; dt {dt_dev.item():.17e} vs {dto:.17e}; "
           f"torque {tq.item():.17e} vs {g:.17e} (sum|terms| {sabs:.3e})", flush=True)
@@ -135,6 +147,10 @@ def test_largest_state_step_parity(order, NX, NY, kind):
     assert abs(dt_dev.item() - dto) <= tol_dt * dto
     assert abs(tq.item() - g) <= TOL * sabs
 
+    # the modal-decay limiter after every stage reads the neighbours' new
+    # means: two elements per stage
+    R = 2 * REACH if cfg.limiter else REACH
+    WIN = 2 * R + 1
     dx = (cfg.x1 - cfg.x0) / NX
     dy = (cfg.y1 - cfg.y0) / NY
     ip, jp = int((1.0 - cfg.x0) / dx), int((0.0 - cfg.y0) / dy)  # the planet at t = 0
@@ -144,24 +160,33 @@ def test_largest_state_step_parity(order, NX, NY, kind):
         (NX - WIN, NY - WIN),  # north-east corner: the ragged last tile, the highest offsets
         (NX - WIN, 0),
         (0, NY - WIN),
-        (ip - 3, jp - 3),
-        (ir - 3, jp - 3),
-        (EW * (NX // EW // 2) - 4, NY // 2 + 60),  # across a tile boundary
-        (500, NY // 2 - 3),
+        (ip - R, jp - R),
+        (ir - R, jp - R),
+        (EW * (NX // EW // 2) - R - 1, NY // 2 + 60),  # across a tile boundary
+        (500, NY // 2 - R),
     ]
     rng = np.random.default_rng(5)
     windows += [(int(rng.integers(0, NX - WIN)), int(rng.integers(0, NY - WIN))) for _ in range(4)]
+    windows += [(min(max(int(e % NX) - R, 0), NX - WIN), min(max(int(e // NX) - R, 0), NY - WIN))
+                for e in flagged[::max(1, flagged.size // 4)][:4]]
+    acted = 0
     for i0, j0 in windows:
-        wc = window_cfg(cfg, i0, j0)
+        wc = window_cfg(cfg, i0, j0, WIN)
         woc = O.cfg(dataclasses.asdict(wc))
         ids = np.array([j * NX + i for j in range(j0, j0 + WIN) for i in range(i0, i0 + WIN)])
         uw = O.project(woc, prim[:, ids, :])
         if cfg.positivity:
             uw, _, _ = O.positivity(woc, uw)
+        if cfg.limiter:
+            un, _ = O.step_limited(woc, uw, 0.0, dto, uw, cfg.limiter_s0)
+            plain, _ = O.step_limited(woc, uw, 0.0, dto, uw, math.inf)
+            inner = np.array([(j - j0) * WIN + (i - i0) for i, j in exact_cells(i0, j0, NX, NY, R)])
+            acted += int((np.abs(un - plain).max(axis=(0, 1))[inner] > 0).sum())
+        elif cfg.positivity:
             un, _ = O.step_limited(woc, uw, 0.0, dto, uw, math.inf)
         else:
             un, _ = O.step(woc, uw, 0.0, dto, u0=uw)
-        cells = exact_cells(i0, j0, NX, NY)
+        cells = exact_cells(i0, j0, NX, NY, R)
         we = np.array([(j - j0) * WIN + (i - i0) for i, j in cells])
         ge = np.array([j * NX + i for i, j in cells])
         want = un[:, :, we]
@@ -176,3 +201,6 @@ def test_largest_state_step_parity(order, NX, NY, kind):
         e = [float(np.max(np.abs(got[v] - want[v])) / sc[v]) for v in range(nv)]
         print(f"[max size] window ({i0}, {j0}): {len(cells)} elements, rel err {e}", flush=True)
         assert max(e) <= tol_step
+    if cfg.limiter:
+        print(f"[max size] the limiter changed {acted} of the compared elements", flush=True)
+        assert acted > 0
